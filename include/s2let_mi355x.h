@@ -1,0 +1,133 @@
+/*
+ * s2let_mi355x -- exact spherical harmonic transform on McEwen-Wiaux (MW) sampling and the
+ * axisymmetric scale-discretised wavelet transform on the sphere, on one AMD Instinct MI355X
+ * (gfx950).  Method: Leistedt, McEwen, Vandergheynst & Wiaux, "S2LET: A code to perform fast
+ * wavelet analysis on the sphere" (A&A 2013), Sects. 2-3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Status: 0 = S2LET_OK, negative = error.  Arguments are validated before anything is
+ *    launched; an invalid call returns S2LET_EINVAL and has no side effect.  No exception and
+ *    no abort crosses this interface.
+ *  - Sampling (Sect. 2.1): band-limit k gives k rings theta_t = pi(2t+1)/(2k-1), t < k (ring
+ *    k-1 is the south pole, stored 2k-1 times) and 2k-1 samples phi_p = 2 pi p/(2k-1) per ring.
+ *    A map is [k][2k-1] row-major, ring by ring: doubles for real signals, interleaved
+ *    (re, im) double pairs for complex ones.
+ *  - Harmonic coefficients f_lm (l < L, |m| <= l) are [L*L] complex (interleaved doubles) with
+ *    f_lm at index l*l + l + m, orthonormal Y_lm with the Condon-Shortley phase.  Real signals
+ *    exchange the full Hermitian array (f_{l,-m} = (-1)^m conj f_lm).
+ *  - Batches: nmaps >= 1 maps are processed by one call; map i starts at i * (size of one map).
+ *  - Pointers named "device" are device (HBM) addresses owned by the caller and must be
+ *    16-byte aligned; the library never frees or keeps caller memory.  The library owns only
+ *    its plan cache (host-computed tables copied to device memory once per device and size),
+ *    released by s2let_finalize().
+ *  - ws / ws_bytes: caller-owned device scratch of at least s2let_workspace_size(...) bytes.
+ *  - stream: a hipStream_t passed as void*; NULL means the default stream.  Every device call
+ *    is asynchronous on that stream; concurrent calls on different streams need separate
+ *    workspaces.
+ *  - Asynchronous device faults surface as S2LET_EHIP from a later call or s2let_sync().
+ *  - Limits: 1 <= L <= S2LET_MAX_L for the harmonic transforms, 3 <= L <= S2LET_MAX_L for the
+ *    wavelet transforms; larger L returns S2LET_EUNSUPPORTED.
+ */
+#ifndef S2LET_MI355X_H
+#define S2LET_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  S2LET_OK = 0,
+  S2LET_EINVAL = -1,        /* invalid argument (nothing launched) */
+  S2LET_ENOMEM = -2,        /* workspace too small, or the plan cache could not allocate */
+  S2LET_EHIP = -3,          /* a HIP runtime call failed */
+  S2LET_EUNSUPPORTED = -4   /* valid by the paper, outside this library's limits */
+};
+
+enum { S2LET_REAL = 0, S2LET_COMPLEX = 1 };                       /* reality */
+enum { S2LET_FP64 = 0, S2LET_MIXED_FP32 = 1, S2LET_MIXED_BF16X3 = 2 };  /* precision of the
+                                                                     Legendre contraction */
+#define S2LET_MAX_L 2048
+
+/* Scale range (Sect. 2.2, after Eq. (16)): J = ceil(log_B(L-1)), computed exactly in integers
+ * as the smallest J with B^J >= L-1.  Returns J, or S2LET_EINVAL unless L >= 3 and B >= 2. */
+int s2let_j_max(int L, int B);
+
+/* Band-limit of wavelet scale j (Sect. 3.1): min(B^(j+1), L) with multiresolution, else L.
+ * Returns S2LET_EINVAL for j < 0, L < 1 or B < 2. */
+int s2let_bandlimit_wav(int j, int L, int B, int multires);
+
+/* Band-limit of the scaling map: min(B^J_min, L) with multiresolution (the support of the
+ * scaling kernel of Eq. (16) is l < B^J_min), else L.  S2LET_EINVAL on bad arguments. */
+int s2let_bandlimit_scal(int J_min, int L, int B, int multires);
+
+/* Number of samples stored for one map at band-limit k: k*(2k-1) (the (k-1)(2k-1)+1 distinct
+ * points of Sect. 2.1 plus the 2k-2 repeats of the south pole).  -1 if k < 1. */
+int64_t s2let_mw_size(int k);
+
+/* Samples per map of the concatenated wavelet maps, scales J_min..J in order:
+ * sum_j s2let_mw_size(k_j).  -1 on bad arguments. */
+int64_t s2let_wav_size(int L, int B, int J_min, int multires);
+
+/* Harmonic kernels of Eqs. (15)-(16) without the sqrt((2l+1)/4pi) factor, which cancels in
+ * Eqs. (4), (6) and (8):  kappa[(j-J_min)*L + l] = kappa_B(l/B^j) (Eq. (13)) for j = J_min..J,
+ * eta[l] = eta_B(l/B^J_min) (Eq. (14)), l < L.  Host memory, owned by the caller:
+ * kappa has (J-J_min+1)*L doubles, eta has L.  k_B of Eq. (12) is evaluated by composite
+ * Gauss-Legendre quadrature.  Host-only (no device needed).  S2LET_EINVAL unless
+ * L >= 3, B >= 2, 0 <= J_min < J. */
+int s2let_tiling_axisym(double* kappa, double* eta, int L, int B, int J_min);
+
+/* Bytes of device workspace needed by mw_forward / mw_inverse (wavelet = 0) or by the
+ * wavelet calls (wavelet = 1) for these arguments; 0 on invalid arguments. */
+size_t s2let_workspace_size(int L, int B, int J_min, int multires, int reality, int precision,
+                            int nmaps, int wavelet);
+
+/* Forward MW spherical harmonic transform, Eq. (2) evaluated exactly by the MW quadrature:
+ *   flm (device, out) [nmaps][L*L] complex;  f (device, in) [nmaps][L][2L-1] real or complex.
+ * Only band-limited maps are transformed exactly (their south-pole ring is constant). */
+int mw_forward(void* flm, const void* f, int L, int reality, int precision, int nmaps,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Inverse MW spherical harmonic transform, Eq. (1) truncated at l < L:
+ *   f (device, out) [nmaps][L][2L-1];  flm (device, in) [nmaps][L*L] complex.
+ * For reality = S2LET_REAL only f_lm with m >= 0 are read (the rest follow by symmetry). */
+int mw_inverse(void* f, const void* flm, int L, int reality, int precision, int nmaps,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Axisymmetric wavelet analysis (Eqs. (4) and (6), computed in harmonic space, then one
+ * inverse SHT per scale at its band-limit, Sects. 2.2 and 3.1-3.2):
+ *   f_wav  (device, out) [nmaps][s2let_wav_size(L,B,J_min,multires)]: wavelet maps of scales
+ *          J_min..J concatenated, scale j an MW map at band-limit k_j;
+ *   f_scal (device, out) [nmaps][s2let_mw_size(k_Phi)]: scaling map at k_Phi;
+ *   f      (device, in)  [nmaps][L][2L-1].
+ * Real input gives real output maps; complex gives complex (interleaved). */
+int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                          int multires, int reality, int precision, int nmaps, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Axisymmetric wavelet synthesis, Eq. (8): a forward SHT of every scale at its band-limit,
+ * the harmonic tiling sum, and one inverse SHT at L.  Same layouts as the analysis, with
+ * f the output. */
+int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L, int B,
+                           int J_min, int multires, int reality, int precision, int nmaps,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Waits for the stream and reports a pending asynchronous device error as S2LET_EHIP. */
+int s2let_sync(void* stream);
+
+/* Releases the plan cache of every device (host and device tables). */
+void s2let_finalize(void);
+
+/* Static description of a status code. */
+const char* s2let_strerror(int status);
+
+/* Library version string. */
+const char* s2let_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* S2LET_MI355X_H */

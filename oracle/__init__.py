@@ -292,8 +292,26 @@ def k_lambda(t: float, lam: float) -> float:
 
 
 def kappa_lambda(t: float, lam: float) -> float:
-    """kappa_lambda(t) = sqrt(k_lambda(t/lambda) - k_lambda(t))  (Eq. (13))."""
-    return math.sqrt(max(0.0, k_lambda(t / lam, lam) - k_lambda(t, lam)))
+    """kappa_lambda(t) = sqrt(k_lambda(t/lambda) - k_lambda(t))  (Eq. (13)).
+
+    Both terms of the difference are integrals of the same integrand s_lambda^2(u)/u over
+    [t/lambda, 1] and [t, 1] (each clamped to the support [1/lambda, 1]), so the difference is
+    that integrand integrated over [max(t/lambda, 1/lambda), min(t, 1)], divided by the
+    normalisation of Eq. (12); evaluating it as one integral avoids the cancellation of two
+    values close to 1."""
+    import warnings
+    from scipy.integrate import quad
+    lo, hi = max(t / lam, 1.0 / lam), min(t, 1.0)
+    if hi <= lo:
+        return 0.0
+    g = lambda u: s_lambda(u, lam) ** 2 / u
+    den_key = ("den", float(lam))
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        if den_key not in _k_cache:
+            _k_cache[den_key] = quad(g, 1.0 / lam, 1.0, epsabs=0.0, epsrel=1.2e-14, limit=400)[0]
+        num = quad(g, lo, hi, epsabs=0.0, epsrel=1.2e-14, limit=400)[0]
+    return math.sqrt(max(0.0, num / _k_cache[den_key]))
 
 
 def eta_lambda(t: float, lam: float) -> float:

@@ -1,0 +1,257 @@
+"""Python binding of libs2let_mi355x: the exact MW spherical harmonic transform and the
+axisymmetric scale-discretised wavelet transform on one MI355X (gfx950).
+
+Argument marshalling only: every step of the transforms runs in the HIP kernels behind the
+C ABI declared in include/s2let_mi355x.h.  torch supplies device memory (inputs, outputs and
+the workspace, all caller-owned) and the current stream.  There is no CPU fallback: if the
+library or a GPU is missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "REAL", "COMPLEX", "FP64", "MIXED_FP32", "MIXED_BF16X3", "MAX_L", "S2letError", "lib",
+    "j_max", "bandlimit_wav", "bandlimit_scal", "mw_size", "wav_size", "tiling_axisym",
+    "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
+]
+
+REAL, COMPLEX = 0, 1
+FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
+MAX_L = 2048
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libs2let_mi355x.so")
+
+
+class S2letError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.s2let_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__("%s failed: %s (status %d)" % (where, msg, status))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libs2let_mi355x.so is not built (run __graft_entry__.build() or "
+                          "python paper_1211_1680_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i, i64, sz, vp, dp = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, \
+        ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "s2let_j_max": (i, [i, i]),
+        "s2let_bandlimit_wav": (i, [i, i, i, i]),
+        "s2let_bandlimit_scal": (i, [i, i, i, i]),
+        "s2let_mw_size": (i64, [i]),
+        "s2let_wav_size": (i64, [i, i, i, i]),
+        "s2let_tiling_axisym": (i, [dp, dp, i, i, i]),
+        "s2let_workspace_size": (sz, [i, i, i, i, i, i, i, i]),
+        "mw_forward": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
+        "mw_inverse": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
+        "s2let_axisym_analysis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
+        "s2let_axisym_synthesis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
+        "s2let_sync": (i, [vp]),
+        "s2let_finalize": (None, []),
+        "s2let_strerror": (ctypes.c_char_p, [i]),
+        "s2let_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+lib = _lib
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise S2letError(status, where)
+
+
+# ---------------------------------------------------------------- host helpers
+def j_max(L: int, B: int) -> int:
+    r = _lib.s2let_j_max(L, B)
+    _check(min(r, 0), "s2let_j_max")
+    return r
+
+
+def bandlimit_wav(j: int, L: int, B: int, multires: bool) -> int:
+    r = _lib.s2let_bandlimit_wav(j, L, B, int(multires))
+    _check(min(r, 0), "s2let_bandlimit_wav")
+    return r
+
+
+def bandlimit_scal(J_min: int, L: int, B: int, multires: bool) -> int:
+    r = _lib.s2let_bandlimit_scal(J_min, L, B, int(multires))
+    _check(min(r, 0), "s2let_bandlimit_scal")
+    return r
+
+
+def mw_size(k: int) -> int:
+    r = _lib.s2let_mw_size(k)
+    if r < 0:
+        raise S2letError(EINVAL, "s2let_mw_size")
+    return r
+
+
+def wav_size(L: int, B: int, J_min: int, multires: bool) -> int:
+    r = _lib.s2let_wav_size(L, B, J_min, int(multires))
+    if r < 0:
+        raise S2letError(EINVAL, "s2let_wav_size")
+    return r
+
+
+def tiling_axisym(L: int, B: int, J_min: int):
+    """(kappa [J-J_min+1, L], eta [L]) as numpy arrays (host computation in the library)."""
+    J = j_max(L, B)
+    kappa = np.zeros((J - J_min + 1, L))
+    eta = np.zeros(L)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(_lib.s2let_tiling_axisym(kappa.ctypes.data_as(dp), eta.ctypes.data_as(dp), L, B, J_min),
+           "s2let_tiling_axisym")
+    return kappa, eta
+
+
+def workspace_size(L, B=2, J_min=0, multires=False, reality=REAL, precision=FP64, nmaps=1,
+                   wavelet=False) -> int:
+    return int(_lib.s2let_workspace_size(L, B, J_min, int(multires), reality, precision, nmaps,
+                                         int(wavelet)))
+
+
+# ---------------------------------------------------------------- device calls
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes: int, device, workspace=None):
+    torch = _torch()
+    if nbytes == 0:
+        raise S2letError(EINVAL, "s2let_workspace_size")
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise S2letError(ENOMEM, "workspace")
+        return workspace
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _need_cuda(t, name, dtype):
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must have dtype %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _map_dtype(reality):
+    torch = _torch()
+    return torch.float64 if reality == REAL else torch.complex128
+
+
+def mw_forward(f, L: int, reality: int = REAL, precision: int = FP64, workspace=None):
+    """f: [nmaps, L, 2L-1] (float64 for REAL, complex128 for COMPLEX) -> flm [nmaps, L*L]."""
+    torch = _torch()
+    _need_cuda(f, "f", _map_dtype(reality))
+    nmaps = f.shape[0] if f.dim() == 3 else 1
+    if f.numel() != nmaps * mw_size(L):
+        raise ValueError("f must hold nmaps * L * (2L-1) samples")
+    flm = torch.empty((nmaps, L * L), dtype=torch.complex128, device=f.device)
+    ws = _workspace(workspace_size(L, reality=reality, precision=precision, nmaps=nmaps), f.device,
+                    workspace)
+    _check(_lib.mw_forward(flm.data_ptr(), f.data_ptr(), L, reality, precision, nmaps,
+                           ws.data_ptr(), ws.numel() * ws.element_size(), _stream(f.device)),
+           "mw_forward")
+    return flm
+
+
+def mw_inverse(flm, L: int, reality: int = REAL, precision: int = FP64, workspace=None):
+    """flm: [nmaps, L*L] complex128 -> f [nmaps, L, 2L-1]."""
+    torch = _torch()
+    _need_cuda(flm, "flm", torch.complex128)
+    nmaps = flm.shape[0] if flm.dim() == 2 else 1
+    if flm.numel() != nmaps * L * L:
+        raise ValueError("flm must hold nmaps * L * L coefficients")
+    f = torch.empty((nmaps, L, 2 * L - 1), dtype=_map_dtype(reality), device=flm.device)
+    ws = _workspace(workspace_size(L, reality=reality, precision=precision, nmaps=nmaps),
+                    flm.device, workspace)
+    _check(_lib.mw_inverse(f.data_ptr(), flm.data_ptr(), L, reality, precision, nmaps,
+                           ws.data_ptr(), ws.numel() * ws.element_size(), _stream(flm.device)),
+           "mw_inverse")
+    return f
+
+
+def analysis(f, L: int, B: int, J_min: int, multires: bool = True, reality: int = REAL,
+             precision: int = FP64, workspace=None, out=None):
+    """Wavelet analysis.  Returns (f_wav [nmaps, wav_size], f_scal [nmaps, mw_size(k_Phi)])."""
+    torch = _torch()
+    dt = _map_dtype(reality)
+    _need_cuda(f, "f", dt)
+    nmaps = f.shape[0] if f.dim() == 3 else 1
+    if f.numel() != nmaps * mw_size(L):
+        raise ValueError("f must hold nmaps * L * (2L-1) samples")
+    kP = bandlimit_scal(J_min, L, B, multires)
+    if out is None:
+        f_wav = torch.empty((nmaps, wav_size(L, B, J_min, multires)), dtype=dt, device=f.device)
+        f_scal = torch.empty((nmaps, mw_size(kP)), dtype=dt, device=f.device)
+    else:
+        f_wav, f_scal = out
+    ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
+                    f.device, workspace)
+    _check(_lib.s2let_axisym_analysis(f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), L, B, J_min,
+                                      int(multires), reality, precision, nmaps, ws.data_ptr(),
+                                      ws.numel() * ws.element_size(), _stream(f.device)),
+           "s2let_axisym_analysis")
+    return f_wav, f_scal
+
+
+def synthesis(f_wav, f_scal, L: int, B: int, J_min: int, multires: bool = True,
+              reality: int = REAL, precision: int = FP64, workspace=None, out=None):
+    """Wavelet synthesis (Eq. (8)).  Returns f [nmaps, L, 2L-1]."""
+    torch = _torch()
+    dt = _map_dtype(reality)
+    _need_cuda(f_wav, "f_wav", dt)
+    _need_cuda(f_scal, "f_scal", dt)
+    nmaps = f_wav.shape[0] if f_wav.dim() == 2 else 1
+    if f_wav.numel() != nmaps * wav_size(L, B, J_min, multires):
+        raise ValueError("f_wav has the wrong size")
+    if f_scal.numel() != nmaps * mw_size(bandlimit_scal(J_min, L, B, multires)):
+        raise ValueError("f_scal has the wrong size")
+    f = out if out is not None else torch.empty((nmaps, L, 2 * L - 1), dtype=dt, device=f_wav.device)
+    ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
+                    f_wav.device, workspace)
+    _check(_lib.s2let_axisym_synthesis(f.data_ptr(), f_wav.data_ptr(), f_scal.data_ptr(), L, B, J_min,
+                                       int(multires), reality, precision, nmaps, ws.data_ptr(),
+                                       ws.numel() * ws.element_size(), _stream(f_wav.device)),
+           "s2let_axisym_synthesis")
+    return f
+
+
+def split_wav(f_wav, L: int, B: int, J_min: int, multires: bool = True):
+    """Views of the concatenated wavelet maps: list over j = J_min..J of [nmaps, k_j, 2k_j-1]."""
+    out, off = [], 0
+    nmaps = f_wav.shape[0]
+    for j in range(J_min, j_max(L, B) + 1):
+        k = bandlimit_wav(j, L, B, multires)
+        n = mw_size(k)
+        out.append(f_wav[:, off:off + n].reshape(nmaps, k, 2 * k - 1))
+        off += n
+    return out
+
+
+def sync(device=None):
+    _check(_lib.s2let_sync(_stream(device)), "s2let_sync")

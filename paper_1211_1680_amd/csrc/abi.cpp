@@ -1,0 +1,461 @@
+// C ABI of the library: argument validation, the per-device plan cache, workspace layout and
+// the per-scale driver of the wavelet transforms (Sects. 2.2, 3.1, 3.2).
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/s2let_mi355x.h"
+#include "common.h"
+#include "plan.h"
+
+#define S2LET_API extern "C" __attribute__((visibility("default")))
+
+namespace s2let {
+namespace {
+
+struct WavTables {
+  int J = 0;
+  double* kappa = nullptr;  // [(J-J_min+1) * L]
+  double* eta = nullptr;    // [L]
+};
+
+struct DevCache {
+  std::map<int, ShtTables> sht;
+  LegTables leg;
+  std::map<std::tuple<int, int, int>, WavTables> wav;
+};
+
+std::mutex g_mu;
+std::map<int, DevCache> g_cache;
+
+constexpr int kMaxRealPerBatch = 16;     // 2 columns per real map -> 32 columns
+constexpr int kMaxComplexPerBatch = 8;   // 4 columns per complex map -> 32 columns
+
+int col_template(int used) {
+  int c = 2;
+  while (c < used) c <<= 1;
+  return c;
+}
+
+Batch make_batch(int reality, int nb) {
+  Batch b;
+  b.nb = nb;
+  b.reality = reality;
+  b.used = (reality == S2LET_REAL ? 2 : 4) * nb;
+  b.C = col_template(b.used);
+  return b;
+}
+
+int batch_cap(int reality) { return reality == S2LET_REAL ? kMaxRealPerBatch : kMaxComplexPerBatch; }
+
+int jmax_int(int L, int B) {
+  int J = 0;
+  long long p = 1;
+  while (p < L - 1) {
+    p *= B;
+    ++J;
+  }
+  return J;
+}
+
+long long ipow_cap(int B, int e, long long cap) {
+  long long p = 1;
+  for (int i = 0; i < e; ++i) {
+    p *= B;
+    if (p >= cap) return cap;
+  }
+  return p;
+}
+
+int bl_wav(int j, int L, int B, int multires) { return multires ? (int)ipow_cap(B, j + 1, L) : L; }
+int bl_scal(int J_min, int L, int B, int multires) { return multires ? (int)ipow_cap(B, J_min, L) : L; }
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Workspace {
+  double* GT;
+  double* HM;
+  double* R;
+  double* S;
+};
+
+// Workspace for transforms up to band-limit L with C columns.
+size_t ws_bytes_for(int L, int C, bool wavelet) {
+  const size_t sq = align_up(sizeof(double) * (size_t)L * L * C);
+  const size_t tri = align_up(sizeof(double) * (size_t)tri_rows(L) * C);
+  return wavelet ? 2 * sq + 2 * tri : 2 * sq + tri;
+}
+
+Workspace carve(void* ws, int L, int C, bool wavelet) {
+  Workspace w;
+  char* p = (char*)ws;
+  const size_t sq = align_up(sizeof(double) * (size_t)L * L * C);
+  const size_t tri = align_up(sizeof(double) * (size_t)tri_rows(L) * C);
+  w.GT = (double*)p;
+  w.HM = (double*)(p + sq);
+  w.R = (double*)(p + 2 * sq);
+  w.S = wavelet ? (double*)(p + 2 * sq + tri) : w.R;
+  return w;
+}
+
+int to_status(hipError_t e) { return e == hipSuccess ? S2LET_OK : S2LET_EHIP; }
+
+// ---- plan cache (lock held by caller) ----
+int get_device(int* dev) { return hipGetDevice(dev) == hipSuccess ? S2LET_OK : S2LET_EHIP; }
+
+int ensure_leg(DevCache& dc) {
+  if (dc.leg.Lt == 0) {
+    hipError_t e = build_leg_tables(S2LET_MAX_L, &dc.leg);
+    if (e != hipSuccess) {
+      free_leg_tables(&dc.leg);
+      return e == hipErrorOutOfMemory ? S2LET_ENOMEM : S2LET_EHIP;
+    }
+  }
+  return S2LET_OK;
+}
+
+int ensure_sht(DevCache& dc, int k, ShtTables** out) {
+  auto it = dc.sht.find(k);
+  if (it == dc.sht.end()) {
+    ShtTables T;
+    hipError_t e = build_sht_tables(k, &T);
+    if (e != hipSuccess) {
+      free_sht_tables(&T);
+      return e == hipErrorOutOfMemory ? S2LET_ENOMEM : S2LET_EHIP;
+    }
+    it = dc.sht.emplace(k, T).first;
+  }
+  *out = &it->second;
+  return S2LET_OK;
+}
+
+int ensure_wav(DevCache& dc, int L, int B, int J_min, WavTables** out) {
+  auto key = std::make_tuple(L, B, J_min);
+  auto it = dc.wav.find(key);
+  if (it == dc.wav.end()) {
+    WavTables W;
+    W.J = jmax_int(L, B);
+    const int ns = W.J - J_min + 1;
+    std::vector<double> kappa((size_t)ns * L), eta(L);
+    tiling_host(L, B, J_min, W.J, kappa.data(), eta.data());
+    if (hipMalloc((void**)&W.kappa, sizeof(double) * kappa.size()) != hipSuccess) return S2LET_ENOMEM;
+    if (hipMalloc((void**)&W.eta, sizeof(double) * eta.size()) != hipSuccess) {
+      hipFree(W.kappa);
+      return S2LET_ENOMEM;
+    }
+    if (hipMemcpy(W.kappa, kappa.data(), sizeof(double) * kappa.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(W.eta, eta.data(), sizeof(double) * eta.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(W.kappa);
+      hipFree(W.eta);
+      return S2LET_EHIP;
+    }
+    it = dc.wav.emplace(key, W).first;
+  }
+  *out = &it->second;
+  return S2LET_OK;
+}
+
+// ---- the harmonic transforms on one batch ----
+int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const void* f,
+                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_phi_forward(T, b, f, map_stride, w.GT, s)) != hipSuccess) return to_status(e);
+  if ((e = launch_theta(T, b, w.GT, w.HM, s)) != hipSuccess) return to_status(e);
+  if ((e = launch_legendre_forward(T, G, b, w.HM, w.R, precision, s)) != hipSuccess) return to_status(e);
+  return S2LET_OK;
+}
+
+int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const double* S, void* f,
+                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_legendre_inverse(T, G, b, S, w.GT, precision, s)) != hipSuccess) return to_status(e);
+  if ((e = launch_phi_inverse(T, b, w.GT, f, map_stride, s)) != hipSuccess) return to_status(e);
+  return S2LET_OK;
+}
+
+int check_common(int reality, int precision, int nmaps) {
+  if (reality != S2LET_REAL && reality != S2LET_COMPLEX) return S2LET_EINVAL;
+  if (precision != S2LET_FP64 && precision != S2LET_MIXED_FP32 && precision != S2LET_MIXED_BF16X3)
+    return S2LET_EINVAL;
+  if (nmaps < 1) return S2LET_EINVAL;
+  return S2LET_OK;
+}
+
+int check_wavelet(int L, int B, int J_min, int multires) {
+  if (L < 3 || B < 2) return S2LET_EINVAL;
+  if (multires != 0 && multires != 1) return S2LET_EINVAL;
+  const int J = jmax_int(L, B);
+  if (J_min < 0 || J_min >= J) return S2LET_EINVAL;
+  return S2LET_OK;
+}
+
+int64_t wav_size_int(int L, int B, int J_min, int multires) {
+  const int J = jmax_int(L, B);
+  int64_t tot = 0;
+  for (int j = J_min; j <= J; ++j) {
+    const int64_t k = bl_wav(j, L, B, multires);
+    tot += k * (2 * k - 1);
+  }
+  return tot;
+}
+
+}  // namespace
+}  // namespace s2let
+
+using namespace s2let;
+
+S2LET_API int s2let_j_max(int L, int B) {
+  if (L < 3 || B < 2) return S2LET_EINVAL;
+  return jmax_int(L, B);
+}
+
+S2LET_API int s2let_bandlimit_wav(int j, int L, int B, int multires) {
+  if (j < 0 || L < 1 || B < 2) return S2LET_EINVAL;
+  return bl_wav(j, L, B, multires);
+}
+
+S2LET_API int s2let_bandlimit_scal(int J_min, int L, int B, int multires) {
+  if (J_min < 0 || L < 1 || B < 2) return S2LET_EINVAL;
+  return bl_scal(J_min, L, B, multires);
+}
+
+S2LET_API int64_t s2let_mw_size(int k) { return k < 1 ? -1 : (int64_t)k * (2 * k - 1); }
+
+S2LET_API int64_t s2let_wav_size(int L, int B, int J_min, int multires) {
+  if (check_wavelet(L, B, J_min, multires) != S2LET_OK) return -1;
+  return wav_size_int(L, B, J_min, multires);
+}
+
+S2LET_API int s2let_tiling_axisym(double* kappa, double* eta, int L, int B, int J_min) {
+  if (!kappa || !eta) return S2LET_EINVAL;
+  if (check_wavelet(L, B, J_min, 0) != S2LET_OK) return S2LET_EINVAL;
+  tiling_host(L, B, J_min, jmax_int(L, B), kappa, eta);
+  return S2LET_OK;
+}
+
+S2LET_API size_t s2let_workspace_size(int L, int B, int J_min, int multires, int reality,
+                                      int precision, int nmaps, int wavelet) {
+  if (check_common(reality, precision, nmaps) != S2LET_OK) return 0;
+  if (L < 1 || L > S2LET_MAX_L) return 0;
+  if (wavelet && check_wavelet(L, B, J_min, multires) != S2LET_OK) return 0;
+  const int nb = std::min(nmaps, batch_cap(reality));
+  const Batch b = make_batch(reality, nb);
+  return ws_bytes_for(L, b.C, wavelet != 0);
+}
+
+static int prologue(int L, int reality, int precision, int nmaps, void* ws, size_t ws_bytes,
+                    bool wavelet, int* dev) {
+  int st = check_common(reality, precision, nmaps);
+  if (st != S2LET_OK) return st;
+  if (L < 1) return S2LET_EINVAL;
+  if (L > S2LET_MAX_L) return S2LET_EUNSUPPORTED;
+  if (precision != S2LET_FP64) return S2LET_EUNSUPPORTED;
+  if (!ws || !aligned16(ws)) return S2LET_EINVAL;
+  const Batch b = make_batch(reality, std::min(nmaps, batch_cap(reality)));
+  if (ws_bytes < ws_bytes_for(L, b.C, wavelet)) return S2LET_ENOMEM;
+  return get_device(dev);
+}
+
+S2LET_API int mw_forward(void* flm, const void* f, int L, int reality, int precision, int nmaps,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!flm || !f || !aligned16(flm) || !aligned16(f)) return S2LET_EINVAL;
+  int dev;
+  int st = prologue(L, reality, precision, nmaps, ws, ws_bytes, false, &dev);
+  if (st != S2LET_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevCache& dc = g_cache[dev];
+  if ((st = ensure_leg(dc)) != S2LET_OK) return st;
+  ShtTables* T;
+  if ((st = ensure_sht(dc, L, &T)) != S2LET_OK) return st;
+  const int cap = batch_cap(reality);
+  const int64_t msz = s2let_mw_size(L);
+  const int cmul = reality == S2LET_REAL ? 1 : 2;
+  for (int start = 0; start < nmaps; start += cap) {
+    const Batch b = make_batch(reality, std::min(cap, nmaps - start));
+    const Workspace w = carve(ws, L, b.C, false);
+    const double* fin = (const double*)f + (size_t)start * msz * cmul;
+    if ((st = forward_batch(*T, dc.leg, b, fin, msz, w, precision, s)) != S2LET_OK) return st;
+    double2* out = (double2*)flm + (size_t)start * L * L;
+    hipError_t e = launch_pack_flm(dc.leg, b, L, w.R, out, s);
+    if (e != hipSuccess) return S2LET_EHIP;
+  }
+  return S2LET_OK;
+}
+
+S2LET_API int mw_inverse(void* f, const void* flm, int L, int reality, int precision, int nmaps,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!flm || !f || !aligned16(flm) || !aligned16(f)) return S2LET_EINVAL;
+  int dev;
+  int st = prologue(L, reality, precision, nmaps, ws, ws_bytes, false, &dev);
+  if (st != S2LET_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevCache& dc = g_cache[dev];
+  if ((st = ensure_leg(dc)) != S2LET_OK) return st;
+  ShtTables* T;
+  if ((st = ensure_sht(dc, L, &T)) != S2LET_OK) return st;
+  const int cap = batch_cap(reality);
+  const int64_t msz = s2let_mw_size(L);
+  const int cmul = reality == S2LET_REAL ? 1 : 2;
+  for (int start = 0; start < nmaps; start += cap) {
+    const Batch b = make_batch(reality, std::min(cap, nmaps - start));
+    const Workspace w = carve(ws, L, b.C, false);
+    const double2* in = (const double2*)flm + (size_t)start * L * L;
+    hipError_t e = launch_unpack_flm(dc.leg, b, L, in, w.S, s);
+    if (e != hipSuccess) return S2LET_EHIP;
+    double* fout = (double*)f + (size_t)start * msz * cmul;
+    if ((st = inverse_batch(*T, dc.leg, b, w.S, fout, msz, w, precision, s)) != S2LET_OK) return st;
+  }
+  return S2LET_OK;
+}
+
+S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                                    int multires, int reality, int precision, int nmaps, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
+    return S2LET_EINVAL;
+  int st = check_wavelet(L, B, J_min, multires);
+  if (st != S2LET_OK) return st;
+  int dev;
+  if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev)) != S2LET_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevCache& dc = g_cache[dev];
+  if ((st = ensure_leg(dc)) != S2LET_OK) return st;
+  WavTables* W;
+  if ((st = ensure_wav(dc, L, B, J_min, &W)) != S2LET_OK) return st;
+  const int J = W->J;
+  const int kP = bl_scal(J_min, L, B, multires);
+  ShtTables *TL, *TP;
+  if ((st = ensure_sht(dc, L, &TL)) != S2LET_OK) return st;
+  if ((st = ensure_sht(dc, kP, &TP)) != S2LET_OK) return st;
+  std::vector<ShtTables*> TJ;
+  for (int j = J_min; j <= J; ++j) {
+    ShtTables* t;
+    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires), &t)) != S2LET_OK) return st;
+    TJ.push_back(t);
+  }
+  const int cap = batch_cap(reality);
+  const int cmul = reality == S2LET_REAL ? 1 : 2;
+  const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires),
+                psz = s2let_mw_size(kP);
+  for (int start = 0; start < nmaps; start += cap) {
+    const Batch b = make_batch(reality, std::min(cap, nmaps - start));
+    const Workspace w = carve(ws, L, b.C, true);
+    const double* fin = (const double*)f + (size_t)start * msz * cmul;
+    if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s)) != S2LET_OK) return st;
+    // scaling part, Eq. (6)
+    hipError_t e = launch_tile(dc.leg, b, w.R, L, w.S, kP, W->eta, 0, s);
+    if (e != hipSuccess) return S2LET_EHIP;
+    double* pout = (double*)f_scal + (size_t)start * psz * cmul;
+    if ((st = inverse_batch(*TP, dc.leg, b, w.S, pout, psz, w, precision, s)) != S2LET_OK) return st;
+    // wavelet scales, Eq. (4)
+    int64_t off = 0;
+    for (int j = J_min; j <= J; ++j) {
+      const int kj = bl_wav(j, L, B, multires);
+      e = launch_tile(dc.leg, b, w.R, L, w.S, kj, W->kappa + (size_t)(j - J_min) * L, 0, s);
+      if (e != hipSuccess) return S2LET_EHIP;
+      double* wout = (double*)f_wav + ((size_t)start * wsz + off) * cmul;
+      if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s)) != S2LET_OK)
+        return st;
+      off += (int64_t)kj * (2 * kj - 1);
+    }
+  }
+  return S2LET_OK;
+}
+
+S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L, int B,
+                                     int J_min, int multires, int reality, int precision, int nmaps,
+                                     void* ws, size_t ws_bytes, void* stream) {
+  if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
+    return S2LET_EINVAL;
+  int st = check_wavelet(L, B, J_min, multires);
+  if (st != S2LET_OK) return st;
+  int dev;
+  if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev)) != S2LET_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevCache& dc = g_cache[dev];
+  if ((st = ensure_leg(dc)) != S2LET_OK) return st;
+  WavTables* W;
+  if ((st = ensure_wav(dc, L, B, J_min, &W)) != S2LET_OK) return st;
+  const int J = W->J;
+  const int kP = bl_scal(J_min, L, B, multires);
+  ShtTables *TL, *TP;
+  if ((st = ensure_sht(dc, L, &TL)) != S2LET_OK) return st;
+  if ((st = ensure_sht(dc, kP, &TP)) != S2LET_OK) return st;
+  std::vector<ShtTables*> TJ;
+  for (int j = J_min; j <= J; ++j) {
+    ShtTables* t;
+    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires), &t)) != S2LET_OK) return st;
+    TJ.push_back(t);
+  }
+  const int cap = batch_cap(reality);
+  const int cmul = reality == S2LET_REAL ? 1 : 2;
+  const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires),
+                psz = s2let_mw_size(kP);
+  for (int start = 0; start < nmaps; start += cap) {
+    const Batch b = make_batch(reality, std::min(cap, nmaps - start));
+    const Workspace w = carve(ws, L, b.C, true);
+    // scaling part
+    const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
+    if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s)) != S2LET_OK) return st;
+    hipError_t e = launch_tile(dc.leg, b, w.R, kP, w.S, L, W->eta, 0, s);
+    if (e != hipSuccess) return S2LET_EHIP;
+    // wavelet scales, accumulated per Eq. (8)
+    int64_t off = 0;
+    for (int j = J_min; j <= J; ++j) {
+      const int kj = bl_wav(j, L, B, multires);
+      const double* win = (const double*)f_wav + ((size_t)start * wsz + off) * cmul;
+      if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s)) != S2LET_OK) return st;
+      e = launch_tile(dc.leg, b, w.R, kj, w.S, L, W->kappa + (size_t)(j - J_min) * L, 1, s);
+      if (e != hipSuccess) return S2LET_EHIP;
+      off += (int64_t)kj * (2 * kj - 1);
+    }
+    double* fout = (double*)f + (size_t)start * msz * cmul;
+    if ((st = inverse_batch(*TL, dc.leg, b, w.S, fout, msz, w, precision, s)) != S2LET_OK) return st;
+  }
+  return S2LET_OK;
+}
+
+S2LET_API int s2let_sync(void* stream) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return S2LET_EHIP;
+  e = hipGetLastError();
+  return e == hipSuccess ? S2LET_OK : S2LET_EHIP;
+}
+
+S2LET_API void s2let_finalize(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int cur = 0;
+  hipGetDevice(&cur);
+  for (auto& kv : g_cache) {
+    hipSetDevice(kv.first);
+    for (auto& t : kv.second.sht) free_sht_tables(&t.second);
+    free_leg_tables(&kv.second.leg);
+    for (auto& w : kv.second.wav) {
+      hipFree(w.second.kappa);
+      hipFree(w.second.eta);
+    }
+  }
+  g_cache.clear();
+  hipSetDevice(cur);
+}
+
+S2LET_API const char* s2let_strerror(int status) {
+  switch (status) {
+    case S2LET_OK: return "ok";
+    case S2LET_EINVAL: return "invalid argument";
+    case S2LET_ENOMEM: return "workspace too small or out of device memory";
+    case S2LET_EHIP: return "HIP runtime error";
+    case S2LET_EUNSUPPORTED: return "unsupported by this library (size or precision)";
+  }
+  return "unknown status";
+}
+
+S2LET_API const char* s2let_version(void) { return "s2let_mi355x 0.1 (gfx950)"; }

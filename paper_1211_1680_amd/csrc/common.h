@@ -1,0 +1,88 @@
+// Internal declarations shared by the host driver and the HIP kernels (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace s2let {
+
+// Packed (m, l) row index of a triangle of band-limit k: column m holds l = m..k-1 and starts
+// at m*k - m*(m-1)/2.  rows(k) = k(k+1)/2.
+__host__ __device__ inline int64_t tri_off(int k, int m) {
+  return (int64_t)m * k - (int64_t)m * (m - 1) / 2;
+}
+__host__ __device__ inline int64_t tri_rows(int k) { return (int64_t)k * (k + 1) / 2; }
+
+inline int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+inline int ilog2(int v) {
+  int e = 0;
+  while ((1 << e) < v) ++e;
+  return e;
+}
+
+// Per-band-limit tables (device memory), built once per device by the plan cache.
+struct ShtTables {
+  int k = 0;        // band-limit
+  int n = 0;        // 2k-1 samples per ring / extended theta period
+  int M = 0;        // power-of-two FFT length >= 4k-3 (Bluestein and theta convolution)
+  int logM = 0;
+  int loglo = 0;    // two-level twiddle split: W_M^p = lo[p & (2^loglo - 1)] * hi[p >> loglo]
+  double2* chirp = nullptr;    // c_q = exp(-i pi q^2 / n), q < n
+  double2* bhat = nullptr;     // FFT_M of conj(c_q) for |q| <= n-1 (wrapped), divided by M
+  double2* what = nullptr;     // FFT_M of the even theta weight w_e(p) (wrapped), / (M n^2)
+  double2* tw_lo = nullptr;    // exp(-2 pi i p / M), p < 2^loglo
+  double2* tw_hi = nullptr;    // exp(-2 pi i p 2^loglo / M), p < M / 2^loglo
+  double* xt = nullptr;        // cos(theta_t), t < k
+  double* st = nullptr;        // sin(theta_t), t < k
+  double2* hphase = nullptr;   // exp(-i pi j / n) for j in [-(k-1), k-1], index j+k-1
+};
+
+// Tables indexed by (l, m) up to a maximum band-limit Lt (shared by every k <= Lt).
+struct LegTables {
+  int Lt = 0;
+  double* alpha = nullptr;  // tri_off(Lt,m) + (l-m): alpha_lm of z_l = alpha_l x z_{l-1} - z_{l-2}
+  double* dfac = nullptr;   // d_lm with lambda_lm = d_lm z_lm
+  double* cm = nullptr;     // lambda_mm(theta) = cm[m] sin^m(theta)
+};
+
+// Column layout of a batch: C columns of doubles per (row) entry.  Real maps: 2 columns per
+// map (re, im of m >= 0).  Complex maps: 4 per map (re, im of +m, then re, im of -m).
+struct Batch {
+  int nb = 0;        // maps in this batch
+  int reality = 0;   // S2LET_REAL / S2LET_COMPLEX
+  int C = 0;         // columns (template size, >= used columns)
+  int used = 0;      // 2*nb or 4*nb
+};
+
+// ---- kernel launchers (kernels_*.hip) ----
+// phi stage, forward: maps -> GT[t][m][c]  (m < k, C columns), weight 2 pi / n included.
+hipError_t launch_phi_forward(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                              double* GT, hipStream_t s);
+// theta stage: GT[t][m][c] -> HM[m][t][c]  (the quadrature-weighted values H'_m(theta_t)).
+hipError_t launch_theta(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
+// phi stage, inverse: FT[t][m][c] -> maps (ring stride n, map stride map_stride samples).
+hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
+                              int64_t map_stride, hipStream_t s);
+// Legendre contraction, forward: HM[m][t][c] -> R[tri_off(k,m)+l-m][c] = sum_t z_lm(theta_t) H'
+hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const Batch& b,
+                                   const double* HM, double* R, int precision, hipStream_t s);
+// Legendre synthesis: S[tri_off(k,m)+l-m][c] (pre-scaled by d_lm) -> FT[t][m][c]
+hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const Batch& b,
+                                   const double* S, double* FT, int precision, hipStream_t s);
+// flm (user layout) -> S (k-packed rows, scaled by d_lm, -m columns by (-1)^m).
+hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm,
+                             double* S, hipStream_t s);
+// R (k-packed raw forward sums) -> flm (user layout): f_lm = d_lm R (and symmetry for real).
+hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, double2* flm,
+                           hipStream_t s);
+// Tiling: dst[tri_off(kd,m)+l-m][c] (=|+=) kern[l] * d_lm^2 * src[tri_off(ks,m)+l-m][c] for
+// l < min(ks, kd); rows with l >= ks of dst are zeroed when accumulate == 0.
+hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, double* dst,
+                       int kd, const double* kern, int accumulate, hipStream_t s);
+
+}  // namespace s2let

@@ -1,0 +1,115 @@
+// Harmonic-space kernels: the wavelet tiling of Eqs. (4), (6) and (8) (a diagonal multiply by
+// the real kernels kappa_j(l), eta(l), with truncation / zero-extension between band-limits
+// in the multiresolution algorithm of Sect. 3.1), and the conversion between the user's
+// f_lm layout (index l*l + l + m) and the packed (m, l) column layout of the Legendre kernels.
+// Every row of band-limit k: (m, l), 0 <= m <= l < k, at tri_off(k, m) + l - m, C columns.
+#include "common.h"
+#include "../../include/s2let_mi355x.h"
+
+namespace s2let {
+
+// blockIdx.y = m; threads over (l - m) * C + c.
+__global__ void k_unpack(const double2* __restrict__ flm, double* __restrict__ S,
+                         const double* __restrict__ dfac, int k, int Lt, int C, int nb, int real,
+                         long long map_stride) {
+  const int m = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int len = k - m;
+  if (idx >= len * C) return;
+  const int r = idx / C, c = idx % C;
+  const int l = m + r;
+  const double d = dfac[tri_off(Lt, m) + r];
+  double v = 0.0;
+  if (real) {
+    const int a = c >> 1;
+    if (a < nb) {
+      const double2 f = flm[(size_t)a * map_stride + (size_t)l * l + l + m];
+      v = (c & 1) ? f.y : f.x;
+    }
+  } else {
+    const int a = c >> 2, part = c & 3;
+    if (a < nb) {
+      if (part < 2) {
+        const double2 f = flm[(size_t)a * map_stride + (size_t)l * l + l + m];
+        v = (part & 1) ? f.y : f.x;
+      } else if (m > 0) {
+        const double2 f = flm[(size_t)a * map_stride + (size_t)l * l + l - m];
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        v = sg * ((part & 1) ? f.y : f.x);
+      }
+    }
+  }
+  S[(tri_off(k, m) + r) * C + c] = d * v;
+}
+
+// One thread per (m, l, map).
+__global__ void k_pack(const double* __restrict__ R, double2* __restrict__ flm,
+                       const double* __restrict__ dfac, int k, int Lt, int C, int nb, int real,
+                       long long map_stride) {
+  const int m = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int len = k - m;
+  if (idx >= len * nb) return;
+  const int r = idx / nb, a = idx % nb;
+  const int l = m + r;
+  const double d = dfac[tri_off(Lt, m) + r];
+  const double* row = R + (tri_off(k, m) + r) * C;
+  double2* out = flm + (size_t)a * map_stride;
+  const double sg = (m & 1) ? -1.0 : 1.0;
+  if (real) {
+    const double2 f = make_double2(d * row[2 * a], d * row[2 * a + 1]);
+    out[(size_t)l * l + l + m] = f;
+    if (m > 0) out[(size_t)l * l + l - m] = make_double2(sg * f.x, -sg * f.y);
+  } else {
+    out[(size_t)l * l + l + m] = make_double2(d * row[4 * a], d * row[4 * a + 1]);
+    if (m > 0) out[(size_t)l * l + l - m] = make_double2(sg * d * row[4 * a + 2], sg * d * row[4 * a + 3]);
+  }
+}
+
+// dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks); rows l >= ks of dst are
+// zero-filled (when not accumulating).
+__global__ void k_tile(const double* __restrict__ src, int ks, double* __restrict__ dst, int kd,
+                       const double* __restrict__ kern, const double* __restrict__ dfac, int Lt,
+                       int C, int accumulate) {
+  const int m = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int len = kd - m;
+  if (len <= 0 || idx >= len * C) return;
+  const int r = idx / C, c = idx % C;
+  const int l = m + r;
+  double v = 0.0;
+  if (l < ks) {
+    const double d = dfac[tri_off(Lt, m) + r];
+    v = kern[l] * d * d * src[(tri_off(ks, m) + r) * C + c];
+  }
+  double* o = dst + (tri_off(kd, m) + r) * C + c;
+  if (accumulate)
+    *o += v;
+  else
+    *o = v;
+}
+
+hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm, double* S,
+                             hipStream_t s) {
+  dim3 grid((k * b.C + 255) / 256, k);
+  k_unpack<<<grid, 256, 0, s>>>(flm, S, G.dfac, k, G.Lt, b.C, b.nb, b.reality == S2LET_REAL,
+                                (long long)k * k);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, double2* flm,
+                           hipStream_t s) {
+  dim3 grid((k * b.nb + 255) / 256, k);
+  k_pack<<<grid, 256, 0, s>>>(R, flm, G.dfac, k, G.Lt, b.C, b.nb, b.reality == S2LET_REAL,
+                              (long long)k * k);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, double* dst,
+                       int kd, const double* kern, int accumulate, hipStream_t s) {
+  dim3 grid((kd * b.C + 255) / 256, kd);
+  k_tile<<<grid, 256, 0, s>>>(src, ks, dst, kd, kern, G.dfac, G.Lt, b.C, accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace s2let

@@ -1,0 +1,305 @@
+// Host-side tables of the transform, computed in long double and copied to device memory once
+// per (device, size): odd-length DFT chirps and their Bluestein kernels, the theta-quadrature
+// weight kernel, FFT twiddles, MW node cosines/sines, and the Legendre recursion factors.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "common.h"
+#include "plan.h"
+
+namespace s2let {
+
+typedef long double LD;
+typedef std::complex<LD> cLD;
+static const LD PI_L = 3.141592653589793238462643383279502884L;
+
+// exp(-i pi q^2 / n) with the angle reduced exactly: q^2 mod 2n in integers.
+static cLD chirp_value(long long q, long long n) {
+  const long long r = ((q % (2 * n)) * (q % (2 * n))) % (2 * n);
+  const LD ang = -PI_L * (LD)r / (LD)n;
+  return cLD(cosl(ang), sinl(ang));
+}
+
+// In-place radix-2 FFT (sign -1), long double, size a power of two.
+static void host_fft(std::vector<cLD>& a) {
+  const size_t N = a.size();
+  for (size_t i = 1, j = 0; i < N; ++i) {
+    size_t bit = N >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= N; len <<= 1) {
+    for (size_t i = 0; i < N; i += len) {
+      for (size_t q = 0; q < len / 2; ++q) {
+        const LD ang = -2.0L * PI_L * (LD)q / (LD)len;
+        const cLD w(cosl(ang), sinl(ang));
+        const cLD u = a[i + q], v = a[i + q + len / 2] * w;
+        a[i + q] = u + v;
+        a[i + q + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& src) {
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * (src.empty() ? 1 : src.size()));
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+static std::vector<double2> to_d2(const std::vector<cLD>& v) {
+  std::vector<double2> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = make_double2((double)v[i].real(), (double)v[i].imag());
+  return o;
+}
+
+hipError_t build_sht_tables(int k, ShtTables* T) {
+  const int n = 2 * k - 1;
+  const int M = next_pow2(4 * k - 3);
+  T->k = k;
+  T->n = n;
+  T->M = M;
+  T->logM = ilog2(M);
+  T->loglo = (T->logM + 1) / 2;
+
+  std::vector<cLD> chirp(n);
+  for (int q = 0; q < n; ++q) chirp[q] = chirp_value(q, n);
+
+  // Bluestein kernel b[q] = conj(c_q), |q| <= n-1, wrapped modulo M; stored as FFT_M(b) / M.
+  std::vector<cLD> b(M, cLD(0, 0));
+  for (int q = -(n - 1); q <= n - 1; ++q) b[((q % M) + M) % M] = std::conj(chirp[q < 0 ? -q : q]);
+  host_fft(b);
+  for (auto& v : b) v /= (LD)M;
+
+  // Even part of the theta weight, w_e(p) = int_0^pi cos(p t) sin(t) dt = 2/(1-p^2) for even p,
+  // |p| <= 2k-2, wrapped modulo M; stored as FFT_M(w_e) / (M n^2).
+  std::vector<cLD> w(M, cLD(0, 0));
+  for (int p = -(2 * k - 2); p <= 2 * k - 2; p += 2) {
+    const LD pp = (LD)p;
+    w[((p % M) + M) % M] = cLD(2.0L / (1.0L - pp * pp), 0);
+  }
+  host_fft(w);
+  for (auto& v : w) v /= (LD)M * (LD)n * (LD)n;
+
+  const int nlo = 1 << T->loglo, nhi = M / nlo;
+  std::vector<cLD> tlo(nlo), thi(nhi > 0 ? nhi : 1);
+  for (int p = 0; p < nlo; ++p) {
+    const LD ang = -2.0L * PI_L * (LD)p / (LD)M;
+    tlo[p] = cLD(cosl(ang), sinl(ang));
+  }
+  for (int p = 0; p < nhi; ++p) {
+    const LD ang = -2.0L * PI_L * (LD)((long long)p * nlo) / (LD)M;
+    thi[p] = cLD(cosl(ang), sinl(ang));
+  }
+
+  std::vector<double> xt(k), st(k);
+  for (int t = 0; t < k; ++t) {
+    const LD th = PI_L * (LD)(2 * t + 1) / (LD)n;
+    xt[t] = (double)cosl(th);
+    st[t] = (double)sinl(th);
+  }
+  st[k - 1] = 0.0;   // theta_{k-1} = pi exactly
+  xt[k - 1] = -1.0;
+
+  std::vector<cLD> hph(2 * k - 1);
+  for (int j = -(k - 1); j <= k - 1; ++j) {
+    const LD ang = -PI_L * (LD)j / (LD)n;
+    hph[j + k - 1] = cLD(cosl(ang), sinl(ang));
+  }
+
+  hipError_t e;
+  if ((e = upload(&T->chirp, to_d2(chirp))) != hipSuccess) return e;
+  if ((e = upload(&T->bhat, to_d2(b))) != hipSuccess) return e;
+  if ((e = upload(&T->what, to_d2(w))) != hipSuccess) return e;
+  if ((e = upload(&T->tw_lo, to_d2(tlo))) != hipSuccess) return e;
+  if ((e = upload(&T->tw_hi, to_d2(thi))) != hipSuccess) return e;
+  if ((e = upload(&T->xt, xt)) != hipSuccess) return e;
+  if ((e = upload(&T->st, st)) != hipSuccess) return e;
+  if ((e = upload(&T->hphase, to_d2(hph))) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+void free_sht_tables(ShtTables* T) {
+  hipFree(T->chirp);
+  hipFree(T->bhat);
+  hipFree(T->what);
+  hipFree(T->tw_lo);
+  hipFree(T->tw_hi);
+  hipFree(T->xt);
+  hipFree(T->st);
+  hipFree(T->hphase);
+  *T = ShtTables();
+}
+
+// Recursion factors.  The normalised recursion (Condon-Shortley, orthonormal)
+//   lambda_l = a_l (x lambda_{l-1} - b_l lambda_{l-2}),
+//   a_l = sqrt((4l^2-1)/(l^2-m^2)),  b_l = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)),
+//   lambda_{m+1} = sqrt(2m+3) x lambda_m,
+// is rewritten as z_l = alpha_l x z_{l-1} - z_{l-2} with lambda_l = d_l z_l:
+//   d_m = d_{m+1} = 1,  d_l = a_l b_l d_{l-2},  alpha_l = a_l d_{l-1} / d_l,
+//   alpha_{m+1} = sqrt(2m+3)  (z_{m-1} = 0).
+void leg_factors_host(int Lt, std::vector<double>* alpha, std::vector<double>* dfac,
+                      std::vector<double>* cm) {
+  const size_t rows = (size_t)tri_rows(Lt);
+  alpha->assign(rows, 0.0);
+  dfac->assign(rows, 0.0);
+  cm->assign(Lt, 0.0);
+  for (int m = 0; m < Lt; ++m) {
+    const size_t off = (size_t)tri_off(Lt, m);
+    std::vector<LD> d(Lt - m + 1, 0.0L);
+    d[0] = 1.0L;
+    (*alpha)[off] = 0.0;
+    (*dfac)[off] = 1.0;
+    if (m + 1 < Lt) {
+      d[1] = 1.0L;
+      (*alpha)[off + 1] = (double)sqrtl((LD)(2 * m + 3));
+      (*dfac)[off + 1] = 1.0;
+    }
+    for (int l = m + 2; l < Lt; ++l) {
+      const LD ll = l, mm = m;
+      const LD a = sqrtl((4.0L * ll * ll - 1.0L) / (ll * ll - mm * mm));
+      const LD bb = sqrtl(((ll - 1.0L) * (ll - 1.0L) - mm * mm) / (4.0L * (ll - 1.0L) * (ll - 1.0L) - 1.0L));
+      d[l - m] = a * bb * d[l - m - 2];
+      (*alpha)[off + l - m] = (double)(a * d[l - m - 1] / d[l - m]);
+      (*dfac)[off + l - m] = (double)d[l - m];
+    }
+  }
+  // lambda_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{i=1}^m (2i-1)/(2i)) sin^m(theta)
+  LD prod = 1.0L;
+  for (int m = 0; m < Lt; ++m) {
+    if (m > 0) prod *= (LD)(2 * m - 1) / (LD)(2 * m);
+    const LD v = sqrtl((LD)(2 * m + 1) / (4.0L * PI_L) * prod);
+    (*cm)[m] = (double)((m & 1) ? -v : v);
+  }
+}
+
+hipError_t build_leg_tables(int Lt, LegTables* G) {
+  std::vector<double> alpha, dfac, cm;
+  leg_factors_host(Lt, &alpha, &dfac, &cm);
+  G->Lt = Lt;
+  hipError_t e;
+  if ((e = upload(&G->alpha, alpha)) != hipSuccess) return e;
+  if ((e = upload(&G->dfac, dfac)) != hipSuccess) return e;
+  if ((e = upload(&G->cm, cm)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+void free_leg_tables(LegTables* G) {
+  hipFree(G->alpha);
+  hipFree(G->dfac);
+  hipFree(G->cm);
+  *G = LegTables();
+}
+
+// ------------------------------------------------------------------------------------------
+// Scale-discretised generating functions, Eqs. (10)-(14), by composite Gauss-Legendre
+// quadrature (nodes from Newton iteration on P_n in long double).
+// ------------------------------------------------------------------------------------------
+namespace {
+struct GaussRule {
+  std::vector<LD> x, w;
+  explicit GaussRule(int n) : x(n), w(n) {
+    for (int i = 0; i < n; ++i) {
+      LD z = cosl(PI_L * ((LD)i + 0.75L) / ((LD)n + 0.5L));
+      for (int it = 0; it < 100; ++it) {
+        LD p0 = 1.0L, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+          const LD p2 = ((2.0L * j - 1.0L) * z * p1 - (j - 1.0L) * p0) / (LD)j;
+          p0 = p1;
+          p1 = p2;
+        }
+        const LD dp = (LD)n * (z * p1 - p0) / (z * z - 1.0L);
+        const LD dz = p1 / dp;
+        z -= dz;
+        if (fabsl(dz) < 1e-19L) {
+          // weight from the final derivative
+          LD q0 = 1.0L, q1 = z;
+          for (int j = 2; j <= n; ++j) {
+            const LD q2 = ((2.0L * j - 1.0L) * z * q1 - (j - 1.0L) * q0) / (LD)j;
+            q0 = q1;
+            q1 = q2;
+          }
+          const LD dq = (LD)n * (z * q1 - q0) / (z * z - 1.0L);
+          x[i] = z;
+          w[i] = 2.0L / ((1.0L - z * z) * dq * dq);
+          break;
+        }
+      }
+    }
+  }
+};
+
+LD schwartz_sq_over_u(LD u, LD lam) {
+  const LD xx = 2.0L * lam * (u - 1.0L / lam) / (lam - 1.0L) - 1.0L;
+  if (xx <= -1.0L || xx >= 1.0L) return 0.0L;
+  const LD s = expl(-1.0L / (1.0L - xx * xx));
+  return s * s / u;
+}
+
+// int_a^b s_lambda^2(u)/u du with `panels` panels of a 20-point rule
+LD integrate(LD a, LD b, LD lam, int panels) {
+  static const GaussRule rule(20);
+  if (b <= a) return 0.0L;
+  LD sum = 0.0L;
+  const LD h = (b - a) / (LD)panels;
+  for (int p = 0; p < panels; ++p) {
+    const LD lo = a + h * (LD)p;
+    const LD mid = lo + 0.5L * h;
+    LD part = 0.0L;
+    for (size_t i = 0; i < rule.x.size(); ++i) part += rule.w[i] * schwartz_sq_over_u(mid + 0.5L * h * rule.x[i], lam);
+    sum += 0.5L * h * part;
+  }
+  return sum;
+}
+}  // namespace
+
+// k_lambda(t) of Eq. (12): 1 for t <= 1/lambda, 0 for t >= 1.
+double k_lambda_host(double t, double lam) {
+  const LD L = lam;
+  if (t <= 1.0 / lam) return 1.0;
+  if (t >= 1.0) return 0.0;
+  const int panels = 128;
+  const LD den = integrate(1.0L / L, 1.0L, L, panels);
+  const LD num = integrate((LD)t, 1.0L, L, panels);
+  return (double)(num / den);
+}
+
+void tiling_host(int L, int B, int J_min, int J, double* kappa, double* eta) {
+  const LD lam = (LD)B;
+  const int panels = 128;
+  const LD den = integrate(1.0L / lam, 1.0L, lam, panels);
+  std::map<LD, double> memo;
+  auto kfun = [&](LD t) -> double {
+    if (t <= 1.0L / lam) return 1.0;
+    if (t >= 1.0L) return 0.0;
+    auto it = memo.find(t);
+    if (it != memo.end()) return it->second;
+    const double v = (double)(integrate(t, 1.0L, lam, panels) / den);
+    memo.emplace(t, v);
+    return v;
+  };
+  std::vector<LD> pw(J + 2);
+  pw[0] = 1.0L;
+  for (int j = 1; j < J + 2; ++j) pw[j] = pw[j - 1] * lam;
+  // kappa^2 = k(t/lambda) - k(t) is one integral of the same integrand over
+  // [max(t/lambda, 1/lambda), min(t, 1)]: evaluated as such, without cancellation.
+  auto kappa2 = [&](LD t) -> LD {
+    const LD lo = std::max(t / lam, 1.0L / lam), hi = std::min(t, 1.0L);
+    if (hi <= lo) return 0.0L;
+    return integrate(lo, hi, lam, panels) / den;
+  };
+  for (int l = 0; l < L; ++l) {
+    eta[l] = std::sqrt(std::fmax(0.0, kfun((LD)l / pw[J_min])));
+    for (int j = J_min; j <= J; ++j)
+      kappa[(size_t)(j - J_min) * L + l] = (double)sqrtl(std::max(0.0L, kappa2((LD)l / pw[j])));
+  }
+}
+
+}  // namespace s2let

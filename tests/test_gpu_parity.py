@@ -1,0 +1,153 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element, on
+the same seeded inputs.  FP64 bar: relative max error <= 1e-10 (max|gpu - oracle| / max|oracle|).
+Inputs come from the seeded generator and the oracle only; no expected value comes from the GPU."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import s2let_inputs as si
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+s2 = pytest.importorskip("paper_1211_1680_amd")
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(got, ref):
+    return oracle.rel_max_err(np.asarray(got), np.asarray(ref))
+
+
+def _to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+# ------------------------------------------------------------------ harmonic transforms
+@pytest.mark.parametrize("reality", [s2.REAL, s2.COMPLEX])
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 8, 13, 16, 33, 64, 100, 128])
+def test_inverse_parity(dev, L, reality):
+    _log("inverse", L, reality)
+    real = reality == s2.REAL
+    flm = si.random_flm(L, 3, reality=real, seed=100 + L)
+    ref = oracle.inverse_sht(flm, L, reality=real)
+    got = s2.mw_inverse(_to_dev(flm, dev), L, reality).cpu().numpy()
+    torch.cuda.synchronize()
+    assert _rel(got, ref) < TOL
+
+
+@pytest.mark.parametrize("reality", [s2.REAL, s2.COMPLEX])
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 8, 13, 16, 33, 64, 100, 128])
+def test_forward_parity(dev, L, reality):
+    _log("forward", L, reality)
+    real = reality == s2.REAL
+    flm = si.random_flm(L, 3, reality=real, seed=200 + L)
+    f = oracle.inverse_sht(flm, L, reality=real)
+    ref = oracle.forward_sht(f, L)
+    got = s2.mw_forward(_to_dev(f, dev), L, reality).cpu().numpy()
+    assert _rel(got, ref) < TOL
+    assert _rel(got, flm) < TOL
+
+
+def test_forward_basis_vectors(dev):
+    """Every basis vector e_lm at L = 12 comes back exactly (complex maps)."""
+    L = 12
+    basis = np.eye(L * L, dtype=np.complex128)
+    f = oracle.inverse_sht(basis, L)
+    got = s2.mw_forward(_to_dev(f, dev), L, s2.COMPLEX).cpu().numpy()
+    assert np.max(np.abs(got - basis)) < 1e-12
+
+
+@pytest.mark.parametrize("nmaps,reality", [(17, s2.REAL), (19, s2.REAL), (9, s2.COMPLEX), (1, s2.REAL),
+                                           (2, s2.REAL), (3, s2.COMPLEX)])
+def test_batches_and_ragged_counts(dev, nmaps, reality):
+    _log("batch", nmaps, reality)
+    L = 24
+    real = reality == s2.REAL
+    flm = si.random_flm(L, nmaps, reality=real, seed=nmaps)
+    f = oracle.inverse_sht(flm, L, reality=real)
+    got_f = s2.mw_inverse(_to_dev(flm, dev), L, reality).cpu().numpy()
+    assert _rel(got_f, f) < TOL
+    got = s2.mw_forward(_to_dev(f, dev), L, reality).cpu().numpy()
+    assert _rel(got, flm) < TOL
+
+
+def test_round_trip_moderate(dev):
+    L = 256
+    flm = si.random_flm_unit(L, 2, seed=11)
+    f = s2.mw_inverse(_to_dev(flm, dev), L, s2.COMPLEX)
+    back = s2.mw_forward(f, L, s2.COMPLEX).cpu().numpy()
+    assert oracle.max_abs_err(back, flm) < 1e-12
+
+
+# ------------------------------------------------------------------ wavelets
+WAVELET_CASES = [
+    # L, B, J_min, multires, reality
+    (3, 2, 0, True, s2.REAL),
+    (8, 2, 0, False, s2.REAL),
+    (16, 2, 1, True, s2.COMPLEX),
+    (32, 3, 1, True, s2.REAL),
+    (64, 2, 0, False, s2.REAL),      # the plain small configuration (one real map, full resolution)
+    (64, 2, 2, True, s2.COMPLEX),
+    (50, 3, 2, True, s2.REAL),
+]
+
+
+@pytest.mark.parametrize("L,B,J_min,multires,reality", WAVELET_CASES)
+def test_wavelet_analysis_parity(dev, L, B, J_min, multires, reality):
+    _log("analysis", L, B, J_min, multires, reality)
+    real = reality == s2.REAL
+    flm = si.random_flm(L, 2, reality=real, seed=L + B)
+    f = oracle.inverse_sht(flm, L, reality=real)
+    wav_ref, scal_ref = oracle.analysis(f, L, B, J_min, multires, real)
+    f_wav, f_scal = s2.analysis(_to_dev(f, dev), L, B, J_min, multires, reality)
+    got = [w.cpu().numpy() for w in s2.split_wav(f_wav, L, B, J_min, multires)]
+    kP = oracle.bandlimit_scal(J_min, L, B, multires)
+    assert _rel(f_scal.cpu().numpy().reshape(2, kP, 2 * kP - 1), scal_ref) < TOL
+    assert len(got) == len(wav_ref)
+    for g, r in zip(got, wav_ref):
+        assert _rel(g, r) < TOL
+
+
+@pytest.mark.parametrize("L,B,J_min,multires,reality", WAVELET_CASES)
+def test_wavelet_synthesis_parity(dev, L, B, J_min, multires, reality):
+    _log("synthesis", L, B, J_min, multires, reality)
+    real = reality == s2.REAL
+    flm = si.random_flm(L, 2, reality=real, seed=3 * L + B)
+    f = oracle.inverse_sht(flm, L, reality=real)
+    wav_ref, scal_ref = oracle.analysis(f, L, B, J_min, multires, real)
+    rec_ref = oracle.synthesis(wav_ref, scal_ref, L, B, J_min, multires, real)
+    f_wav = np.concatenate([w.reshape(2, -1) for w in wav_ref], axis=1)
+    f_scal = scal_ref.reshape(2, -1)
+    rec = s2.synthesis(_to_dev(f_wav, dev), _to_dev(f_scal, dev), L, B, J_min, multires, reality)
+    rec = rec.cpu().numpy()
+    assert _rel(rec, rec_ref) < TOL
+    assert _rel(rec, f) < TOL
+
+
+def test_wavelet_round_trip_config_512_complex(dev):
+    """One complex map, L=512, B=2, J_min=2, multiresolution: analysis then synthesis returns
+    the seeded coefficients; the harmonic transforms match the oracle."""
+    L, B, J_min = 512, 2, 2
+    flm = si.random_flm(L, 1, reality=False, seed=1)
+    f = oracle.inverse_sht(flm, L)
+    fd = _to_dev(f, dev)
+    got_flm = s2.mw_forward(fd, L, s2.COMPLEX).cpu().numpy()
+    assert _rel(got_flm, flm) < TOL
+    f_wav, f_scal = s2.analysis(fd, L, B, J_min, True, s2.COMPLEX)
+    rec = s2.synthesis(f_wav, f_scal, L, B, J_min, True, s2.COMPLEX)
+    back = s2.mw_forward(rec, L, s2.COMPLEX).cpu().numpy()
+    assert _rel(back, flm) < TOL

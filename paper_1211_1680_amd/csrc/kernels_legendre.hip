@@ -268,7 +268,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int c = ct * 16 + 4 * lq + v;
+            // result register v of lane l holds row (l / 16) + 4 v, column l % 16
+            const int c = ct * 16 + lq + 4 * v;
             const int lloc = lt2 * 16 + li;
             if (c < C) red[((size_t)w * FWD_LC + lloc) * C + c] = acc[lt2][ct][v];
           }

@@ -28,8 +28,15 @@ def _log(*a):
     sys.stdout.flush()
 
 
-def _rel(got, ref):
-    return oracle.rel_max_err(np.asarray(got), np.asarray(ref))
+def _rel(got, ref, floor=0.0):
+    """max|got - ref| / max(max|ref|, floor).  The floor (a small fraction of the input's scale)
+    only matters for outputs that are zero in exact arithmetic, e.g. a scaling map at band-limit
+    1 of a signal without monopole, where both sides hold round-off."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    den = max(float(np.max(np.abs(ref))) if ref.size else 0.0, floor)
+    r = oracle.max_abs_err(got, ref) / den if den > 0 else oracle.max_abs_err(got, ref)
+    _log("  rel err %.3e" % r)
+    return r
 
 
 def _to_dev(a, dev):
@@ -90,7 +97,10 @@ def test_round_trip_moderate(dev):
     flm = si.random_flm_unit(L, 2, seed=11)
     f = s2.mw_inverse(_to_dev(flm, dev), L, s2.COMPLEX)
     back = s2.mw_forward(f, L, s2.COMPLEX).cpu().numpy()
-    assert oracle.max_abs_err(back, flm) < 1e-12
+    err = oracle.max_abs_err(back, flm)
+    _log("  round trip L=%d: %.3e" % (L, err))
+    # the paper finds round-trip errors growing as O(L) at floating-point level (Sect. 3.3)
+    assert err < 2e-14 * L
 
 
 # ------------------------------------------------------------------ wavelets
@@ -116,10 +126,11 @@ def test_wavelet_analysis_parity(dev, L, B, J_min, multires, reality):
     f_wav, f_scal = s2.analysis(_to_dev(f, dev), L, B, J_min, multires, reality)
     got = [w.cpu().numpy() for w in s2.split_wav(f_wav, L, B, J_min, multires)]
     kP = oracle.bandlimit_scal(J_min, L, B, multires)
-    assert _rel(f_scal.cpu().numpy().reshape(2, kP, 2 * kP - 1), scal_ref) < TOL
+    floor = 1e-6 * float(np.max(np.abs(f)))
+    assert _rel(f_scal.cpu().numpy().reshape(2, kP, 2 * kP - 1), scal_ref, floor) < TOL
     assert len(got) == len(wav_ref)
     for g, r in zip(got, wav_ref):
-        assert _rel(g, r) < TOL
+        assert _rel(g, r, floor) < TOL
 
 
 @pytest.mark.parametrize("L,B,J_min,multires,reality", WAVELET_CASES)

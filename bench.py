@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the axisymmetric wavelet transform on the sphere: analysis + synthesis maps/s.
+
+Workload (one "step"): wavelet analysis followed by wavelet synthesis of 16 real maps at
+band-limit L = 2048 on MW sampling, B = 2, J_min = 3, multiresolution (scale j at band-limit
+min(2^(j+1), L), scaling map at 2^J_min = 8), harmonic coefficients drawn with
+C_l = 1/(l(l+1)), seed 3.  Inputs are synthesised on the device before the timed region (as in
+the paper's protocol, Sect. 3.3, input synthesis is not timed) and stay resident in HBM.
+
+Prints one JSON line.  Besides throughput it reports the roofline position of the dominant
+kernel (summed HIP-event time of its launches inside the timed region, against its
+algorithmic work) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "wavelet analysis+synthesis maps/s at L=2048 (FP64 vs mixed); % HBM/MFMA peak"
+
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6       # FP64 vector and FP64 dense matrix
+PEAK_HBM_GBS = 8000.0
+
+
+def triples(k: int) -> float:
+    """(l, m, theta) triples of one real-map SHT at band-limit k (m >= 0)."""
+    return k * k * (k + 1) / 2.0
+
+
+def workload_triples(L, B, J_min, multires, s2):
+    ks = [s2.bandlimit_scal(J_min, L, B, multires)]
+    ks += [s2.bandlimit_wav(j, L, B, multires) for j in range(J_min, s2.j_max(L, B) + 1)]
+    # analysis: forward at L, inverse at every scale; synthesis: forward at every scale, inverse at L
+    return 2.0 * (triples(L) + sum(triples(k) for k in ks)), ks
+
+
+def cpu_baseline(L, B, J_min, multires, s2):
+    """Oracle timed on a bounded sample: one inverse + one forward SHT of one real map at L
+    (the unit that dominates the workload), scaled to analysis+synthesis of one map by the
+    ratio of (l, m, theta) triples."""
+    import numpy as np
+    import oracle
+    import s2let_inputs as si
+    flm = si.random_flm(L, 1, reality=True, seed=3)
+    oracle.build()
+    t0 = time.perf_counter()
+    f = oracle.inverse_sht(flm, L, reality=True)
+    back = oracle.forward_sht(f, L)
+    dt = time.perf_counter() - t0
+    err = float(np.max(np.abs(back - flm)))
+    full, _ = workload_triples(L, B, J_min, multires, s2)
+    scale = full / (2.0 * triples(L))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / (dt * scale),
+        "unit": "maps/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": ("one inverse + one forward SHT of one real map at L=%d (%.1f s, round-trip "
+                   "error %.1e), scaled by the triple ratio %.3f of one map's analysis+synthesis"
+                   % (L, dt, err, scale)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--L", type=int, default=2048)
+    ap.add_argument("--nmaps", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (maps are independent; "
+              "see DESIGN.md for how the transform would shard).  Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1211_1680_amd as s2
+    import s2let_inputs as si
+
+    L, B, J_min, multires, nmaps = args.L, 2, 3, True, args.nmaps
+    prec = {"fp64": s2.FP64}[args.precision]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # inputs: seeded coefficients -> maps on the device (untimed)
+    flm = si.random_flm(L, nmaps, reality=True, seed=3)
+    f = s2.mw_inverse(torch.from_numpy(flm).to(dev), L, s2.REAL)
+    del flm
+    kP = s2.bandlimit_scal(J_min, L, B, multires)
+    f_wav = torch.empty((nmaps, s2.wav_size(L, B, J_min, multires)), dtype=torch.float64, device=dev)
+    f_scal = torch.empty((nmaps, s2.mw_size(kP)), dtype=torch.float64, device=dev)
+    rec = torch.empty_like(f)
+    ws = torch.empty(s2.workspace_size(L, B, J_min, multires, s2.REAL, prec, nmaps, True),
+                     dtype=torch.uint8, device=dev)
+
+    def step():
+        s2.analysis(f, L, B, J_min, multires, s2.REAL, prec, workspace=ws, out=(f_wav, f_scal))
+        s2.synthesis(f_wav, f_scal, L, B, J_min, multires, s2.REAL, prec, workspace=ws, out=rec)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    err = float((rec - f).abs().max().item() / f.abs().max().item())
+
+    s2.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = {name: s2.profile_query(name) for name in s2.STAGES}
+    s2.profile_enable(False)
+
+    ms_per_step = 1e3 * dt / args.steps
+    value = nmaps * args.steps / dt
+
+    # dominant kernel: the stage with the largest summed kernel time
+    dom = max(stages, key=lambda n: stages[n]["ms"])
+    st = stages[dom]
+    if dom.startswith("legendre"):
+        achieved = st["flops_retained"] / (st["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma" if dom == "legendre_analysis" else "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None, "kernel": dom, "launches": st["launches"],
+                "avg_launch_ms": st["ms"] / max(st["launches"], 1),
+                "achieved_all_triples": st["flops_full"] / (st["ms"] * 1e-3) / 1e12}
+    else:
+        achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
+                "launches": st["launches"], "avg_launch_ms": st["ms"] / max(st["launches"], 1)}
+    stage_ms = {n: round(v["ms"] / args.steps, 3) for n, v in stages.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "wavelet analysis+synthesis of %d real maps, L=%d, B=%d, J_min=%d, "
+                               "multiresolution, C_l=1/(l(l+1)), seed 3, FP64" % (nmaps, L, B, J_min),
+                   "nmaps": nmaps, "L": L, "B": B, "J_min": J_min, "multires": multires,
+                   "precision": args.precision},
+        "roofline": roof,
+        "stage_ms_per_step": stage_ms,
+        "round_trip_rel_err": err,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L, B, J_min, multires, s2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

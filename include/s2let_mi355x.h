@@ -115,6 +115,23 @@ int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L
                            int J_min, int multires, int reality, int precision, int nmaps,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* Measurement support.  s2let_profile_enable(1) clears previous records and, until
+ * s2let_profile_enable(0), brackets every kernel launch of the calls above with a pair of HIP
+ * events recorded on the launch stream; the Legendre kernels also count the (l, theta) pairs they
+ * actually contract (pairs whose lambda_lm is below 2^-1100 for a whole wavefront are skipped).
+ * s2let_profile_query() waits for the recorded events and returns, for one stage, the summed
+ * kernel time (ms), the number of launches, the algorithmic flops of those launches (every
+ * (l, m, theta) triple: 3 recursion flops plus 2 flops per data column), the flops of the work
+ * actually done (retained pairs), and the algorithmic HBM bytes (inputs read once, outputs
+ * written once).  Stages: 0 phi forward, 1 theta quadrature, 2 Legendre analysis,
+ * 3 Legendre synthesis, 4 phi inverse, 5 harmonic tiling.  Host-side, not thread-safe with
+ * concurrent transform calls on other threads.  S2LET_EINVAL for a bad stage or null pointer. */
+enum { S2LET_STAGE_PHI_FWD = 0, S2LET_STAGE_THETA = 1, S2LET_STAGE_LEG_FWD = 2,
+       S2LET_STAGE_LEG_INV = 3, S2LET_STAGE_PHI_INV = 4, S2LET_STAGE_TILE = 5 };
+int s2let_profile_enable(int on);
+int s2let_profile_query(int stage, double* ms, int64_t* launches, double* flops_full,
+                        double* flops_retained, double* bytes);
+
 /* Waits for the stream and reports a pending asynchronous device error as S2LET_EHIP. */
 int s2let_sync(void* stream);
 

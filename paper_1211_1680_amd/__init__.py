@@ -17,6 +17,7 @@ __all__ = [
     "REAL", "COMPLEX", "FP64", "MIXED_FP32", "MIXED_BF16X3", "MAX_L", "S2letError", "lib",
     "j_max", "bandlimit_wav", "bandlimit_scal", "mw_size", "wav_size", "tiling_axisym",
     "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
+    "profile_enable", "profile_query", "STAGES",
 ]
 
 REAL, COMPLEX = 0, 1
@@ -55,6 +56,8 @@ def _load():
         "s2let_axisym_analysis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_synthesis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
         "s2let_sync": (i, [vp]),
+        "s2let_profile_enable": (i, [i]),
+        "s2let_profile_query": (i, [i, dp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp]),
         "s2let_finalize": (None, []),
         "s2let_strerror": (ctypes.c_char_p, [i]),
         "s2let_version": (ctypes.c_char_p, []),
@@ -251,6 +254,25 @@ def split_wav(f_wav, L: int, B: int, J_min: int, multires: bool = True):
         out.append(f_wav[:, off:off + n].reshape(nmaps, k, 2 * k - 1))
         off += n
     return out
+
+
+STAGES = {"phi_forward": 0, "theta": 1, "legendre_analysis": 2, "legendre_synthesis": 3,
+          "phi_inverse": 4, "tiling": 5}
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing old records) or stop per-kernel event timing inside the library."""
+    _check(_lib.s2let_profile_enable(int(on)), "s2let_profile_enable")
+
+
+def profile_query(stage: str) -> dict:
+    """Summed kernel time and algorithmic work of one stage since profile_enable(True)."""
+    ms, fl, fr, by = (ctypes.c_double() for _ in range(4))
+    n = ctypes.c_int64()
+    _check(_lib.s2let_profile_query(STAGES[stage], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                    ctypes.byref(fr), ctypes.byref(by)), "s2let_profile_query")
+    return {"ms": ms.value, "launches": n.value, "flops_full": fl.value, "flops_retained": fr.value,
+            "bytes": by.value}
 
 
 def sync(device=None):

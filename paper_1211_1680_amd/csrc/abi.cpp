@@ -1,6 +1,7 @@
 // C ABI of the library: argument validation, the per-device plan cache, workspace layout and
 // the per-scale driver of the wavelet transforms (Sects. 2.2, 3.1, 3.2).
 #include <algorithm>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -29,6 +30,48 @@ struct DevCache {
 
 std::mutex g_mu;
 std::map<int, DevCache> g_cache;
+
+// ---- optional per-stage timing (HIP events on the launch stream) ----
+struct ProfRec {
+  int stage;
+  hipEvent_t a, b;
+  double flops_full;    // algorithmic flops of the launch (Legendre stages)
+  double bytes;         // algorithmic HBM bytes of the launch
+  double triples;       // (l, m, theta) triples of the launch
+  double rec_flops;     // recursion flops per triple (shared by all columns)
+  double col_flops;     // contraction flops per retained triple
+  int slot;             // retained-triple counter slot, -1 if none
+};
+struct Prof {
+  bool on = false;
+  int dev = -1;
+  std::deque<ProfRec> recs;   // stable addresses while records are appended
+  unsigned long long* counters = nullptr;   // device, kProfSlots entries
+  int next_slot = 0;
+};
+constexpr int kProfSlots = 8192;
+Prof g_prof;
+
+ProfRec* prof_begin(int stage, hipStream_t s) {
+  if (!g_prof.on) return nullptr;
+  ProfRec r{};
+  r.stage = stage;
+  r.slot = -1;
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return nullptr;
+  hipEventRecord(r.a, s);
+  g_prof.recs.push_back(r);
+  return &g_prof.recs.back();
+}
+
+unsigned long long* prof_counter(ProfRec* r) {
+  if (!r || !g_prof.counters || g_prof.next_slot >= kProfSlots) return nullptr;
+  r->slot = g_prof.next_slot++;
+  return g_prof.counters + r->slot;
+}
+
+void prof_end(ProfRec* r, hipStream_t s) {
+  if (r) hipEventRecord(r->b, s);
+}
 
 constexpr int kMaxRealPerBatch = 16;     // 2 columns per real map -> 32 columns
 constexpr int kMaxComplexPerBatch = 8;   // 4 columns per complex map -> 32 columns
@@ -160,21 +203,70 @@ int ensure_wav(DevCache& dc, int L, int B, int J_min, WavTables** out) {
 }
 
 // ---- the harmonic transforms on one batch ----
+double triples_of(int k) { return (double)k * (double)k * (double)(k + 1) / 2.0; }
+
 int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const void* f,
                   int64_t map_stride, const Workspace& w, int precision, hipStream_t s) {
   hipError_t e;
+  const double k = T.k, n = T.n;
+  const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
+  const double colb = 8.0 * b.used * k * k;
+  ProfRec* r = prof_begin(ST_PHI_FWD, s);
+  if (r) r->bytes = mapb + colb;
   if ((e = launch_phi_forward(T, b, f, map_stride, w.GT, s)) != hipSuccess) return to_status(e);
+  prof_end(r, s);
+  r = prof_begin(ST_THETA, s);
+  if (r) r->bytes = 2.0 * colb;
   if ((e = launch_theta(T, b, w.GT, w.HM, s)) != hipSuccess) return to_status(e);
-  if ((e = launch_legendre_forward(T, G, b, w.HM, w.R, precision, s)) != hipSuccess) return to_status(e);
+  prof_end(r, s);
+  r = prof_begin(ST_LEG_FWD, s);
+  if (r) {
+    r->triples = triples_of(T.k);
+    r->rec_flops = 3.0;
+    r->col_flops = 2.0 * b.used;
+    r->flops_full = r->triples * (r->rec_flops + r->col_flops);
+    r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
+  }
+  if ((e = launch_legendre_forward(T, G, b, w.HM, w.R, precision, prof_counter(r), s)) != hipSuccess)
+    return to_status(e);
+  prof_end(r, s);
   return S2LET_OK;
 }
 
 int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const double* S, void* f,
                   int64_t map_stride, const Workspace& w, int precision, hipStream_t s) {
   hipError_t e;
-  if ((e = launch_legendre_inverse(T, G, b, S, w.GT, precision, s)) != hipSuccess) return to_status(e);
+  const double k = T.k, n = T.n;
+  const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
+  const double colb = 8.0 * b.used * k * k;
+  ProfRec* r = prof_begin(ST_LEG_INV, s);
+  if (r) {
+    r->triples = triples_of(T.k);
+    r->rec_flops = 3.0;
+    r->col_flops = 2.0 * b.used;
+    r->flops_full = r->triples * (r->rec_flops + r->col_flops);
+    r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
+  }
+  if ((e = launch_legendre_inverse(T, G, b, S, w.GT, precision, prof_counter(r), s)) != hipSuccess)
+    return to_status(e);
+  prof_end(r, s);
+  r = prof_begin(ST_PHI_INV, s);
+  if (r) r->bytes = mapb + colb;
   if ((e = launch_phi_inverse(T, b, w.GT, f, map_stride, s)) != hipSuccess) return to_status(e);
+  prof_end(r, s);
   return S2LET_OK;
+}
+
+hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int ks, double* dst, int kd,
+                     const double* kern, int accumulate, hipStream_t s) {
+  ProfRec* r = prof_begin(ST_TILE, s);
+  if (r) {
+    const double kk = std::min(ks, kd);
+    r->bytes = 8.0 * b.used * (kk * (kk + 1) / 2.0 + (double)tri_rows(kd) * (accumulate ? 2.0 : 1.0));
+  }
+  hipError_t e = launch_tile(G, b, src, ks, dst, kd, kern, accumulate, s);
+  prof_end(r, s);
+  return e;
 }
 
 int check_common(int reality, int precision, int nmaps) {
@@ -350,7 +442,7 @@ S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, in
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
     if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s)) != S2LET_OK) return st;
     // scaling part, Eq. (6)
-    hipError_t e = launch_tile(dc.leg, b, w.R, L, w.S, kP, W->eta, 0, s);
+    hipError_t e = tile_prof(dc.leg, b, w.R, L, w.S, kP, W->eta, 0, s);
     if (e != hipSuccess) return S2LET_EHIP;
     double* pout = (double*)f_scal + (size_t)start * psz * cmul;
     if ((st = inverse_batch(*TP, dc.leg, b, w.S, pout, psz, w, precision, s)) != S2LET_OK) return st;
@@ -358,7 +450,7 @@ S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, in
     int64_t off = 0;
     for (int j = J_min; j <= J; ++j) {
       const int kj = bl_wav(j, L, B, multires);
-      e = launch_tile(dc.leg, b, w.R, L, w.S, kj, W->kappa + (size_t)(j - J_min) * L, 0, s);
+      e = tile_prof(dc.leg, b, w.R, L, w.S, kj, W->kappa + (size_t)(j - J_min) * L, 0, s);
       if (e != hipSuccess) return S2LET_EHIP;
       double* wout = (double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s)) != S2LET_OK)
@@ -405,7 +497,7 @@ S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_s
     // scaling part
     const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
     if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s)) != S2LET_OK) return st;
-    hipError_t e = launch_tile(dc.leg, b, w.R, kP, w.S, L, W->eta, 0, s);
+    hipError_t e = tile_prof(dc.leg, b, w.R, kP, w.S, L, W->eta, 0, s);
     if (e != hipSuccess) return S2LET_EHIP;
     // wavelet scales, accumulated per Eq. (8)
     int64_t off = 0;
@@ -413,12 +505,69 @@ S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_s
       const int kj = bl_wav(j, L, B, multires);
       const double* win = (const double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s)) != S2LET_OK) return st;
-      e = launch_tile(dc.leg, b, w.R, kj, w.S, L, W->kappa + (size_t)(j - J_min) * L, 1, s);
+      e = tile_prof(dc.leg, b, w.R, kj, w.S, L, W->kappa + (size_t)(j - J_min) * L, 1, s);
       if (e != hipSuccess) return S2LET_EHIP;
       off += (int64_t)kj * (2 * kj - 1);
     }
     double* fout = (double*)f + (size_t)start * msz * cmul;
     if ((st = inverse_batch(*TL, dc.leg, b, w.S, fout, msz, w, precision, s)) != S2LET_OK) return st;
+  }
+  return S2LET_OK;
+}
+
+S2LET_API int s2let_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& r : g_prof.recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.recs.clear();
+  g_prof.next_slot = 0;
+  g_prof.on = false;
+  if (!on) return S2LET_OK;
+  int dev;
+  if (hipGetDevice(&dev) != hipSuccess) return S2LET_EHIP;
+  if (g_prof.counters && g_prof.dev != dev) {
+    hipFree(g_prof.counters);
+    g_prof.counters = nullptr;
+  }
+  if (!g_prof.counters) {
+    if (hipMalloc((void**)&g_prof.counters, sizeof(unsigned long long) * kProfSlots) != hipSuccess)
+      return S2LET_ENOMEM;
+    g_prof.dev = dev;
+  }
+  if (hipMemset(g_prof.counters, 0, sizeof(unsigned long long) * kProfSlots) != hipSuccess) return S2LET_EHIP;
+  g_prof.on = true;
+  return S2LET_OK;
+}
+
+S2LET_API int s2let_profile_query(int stage, double* ms, int64_t* launches, double* flops_full,
+                                  double* flops_retained, double* bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (stage < 0 || stage >= ST_N || !ms || !launches || !flops_full || !flops_retained || !bytes)
+    return S2LET_EINVAL;
+  std::vector<unsigned long long> cnt(kProfSlots, 0);
+  if (g_prof.counters && g_prof.next_slot > 0) {
+    if (hipDeviceSynchronize() != hipSuccess) return S2LET_EHIP;
+    if (hipMemcpy(cnt.data(), g_prof.counters, sizeof(unsigned long long) * g_prof.next_slot,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return S2LET_EHIP;
+  }
+  *ms = 0.0;
+  *launches = 0;
+  *flops_full = 0.0;
+  *flops_retained = 0.0;
+  *bytes = 0.0;
+  for (auto& r : g_prof.recs) {
+    if (r.stage != stage) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return S2LET_EHIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return S2LET_EHIP;
+    *ms += t;
+    *launches += 1;
+    *flops_full += r.flops_full;
+    *bytes += r.bytes;
+    if (r.slot >= 0) *flops_retained += r.triples * r.rec_flops + (double)cnt[r.slot] * r.col_flops;
   }
   return S2LET_OK;
 }

@@ -39,6 +39,8 @@ struct ShtTables {
   double2* tw_hi = nullptr;    // exp(-2 pi i p 2^loglo / M), p < M / 2^loglo
   double* xt = nullptr;        // cos(theta_t), t < k
   double* st = nullptr;        // sin(theta_t), t < k
+  double* ut = nullptr;        // |cos(theta_t)| - 1 = -2 sin^2(theta'/2), theta' = min(theta, pi - theta)
+  double* sx = nullptr;        // sign of cos(theta_t) (+1 at the equator)
   double2* hphase = nullptr;   // exp(-i pi j / n) for j in [-(k-1), k-1], index j+k-1
 };
 
@@ -46,9 +48,13 @@ struct ShtTables {
 struct LegTables {
   int Lt = 0;
   double* alpha = nullptr;  // tri_off(Lt,m) + (l-m): alpha_lm of z_l = alpha_l x z_{l-1} - z_{l-2}
+  double* beta = nullptr;   // alpha_lm - 2, rounded from the exact value
   double* dfac = nullptr;   // d_lm with lambda_lm = d_lm z_lm
   double* cm = nullptr;     // lambda_mm(theta) = cm[m] sin^m(theta)
 };
+
+// Kernel stages, for the optional per-stage timing.
+enum Stage { ST_PHI_FWD = 0, ST_THETA = 1, ST_LEG_FWD = 2, ST_LEG_INV = 3, ST_PHI_INV = 4, ST_TILE = 5, ST_N = 6 };
 
 // Column layout of a batch: C columns of doubles per (row) entry.  Real maps: 2 columns per
 // map (re, im of m >= 0).  Complex maps: 4 per map (re, im of +m, then re, im of -m).
@@ -70,10 +76,12 @@ hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* 
                               int64_t map_stride, hipStream_t s);
 // Legendre contraction, forward: HM[m][t][c] -> R[tri_off(k,m)+l-m][c] = sum_t z_lm(theta_t) H'
 hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const Batch& b,
-                                   const double* HM, double* R, int precision, hipStream_t s);
+                                   const double* HM, double* R, int precision,
+                                   unsigned long long* counter, hipStream_t s);
 // Legendre synthesis: S[tri_off(k,m)+l-m][c] (pre-scaled by d_lm) -> FT[t][m][c]
 hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const Batch& b,
-                                   const double* S, double* FT, int precision, hipStream_t s);
+                                   const double* S, double* FT, int precision,
+                                   unsigned long long* counter, hipStream_t s);
 // flm (user layout) -> S (k-packed rows, scaled by d_lm, -m columns by (-1)^m).
 hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm,
                              double* S, hipStream_t s);

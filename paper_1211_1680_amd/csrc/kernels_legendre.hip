@@ -5,9 +5,13 @@
 //
 // lambda_lm is never stored: it is regenerated per (m, theta) by the three-term recursion,
 // in FP64, in the scaled form  z_l = alpha_l x z_{l-1} - z_{l-2}  (x = cos theta), with
-// lambda_lm = d_lm z_lm.  The d_lm are folded into the coefficients by the pack / unpack /
-// tiling kernels, so one step costs one multiply and one FMA.  Start: z_m = lambda_mm =
-// c_m sin^m(theta), z_{m-1} = 0.  Near the poles lambda_mm underflows far below the double
+// lambda_lm = d_lm z_lm; the d_lm are folded into the coefficients by the pack / unpack /
+// tiling kernels.  Start: z_m = lambda_mm = c_m sin^m(theta), z_{m-1} = 0.
+// Near the poles (x -> +-1) the plain recursion loses about l^2 ulps (1e-10 at l = 2047), so it
+// runs in Reinsch's difference form: with s = sign(x), u = |x| - 1 = -2 sin^2(theta'/2) and
+// beta_l = alpha_l - 2 both tabulated exactly,
+//   g = alpha_l u + beta_l  (= alpha_l |x| - 2),  E_l = s (E_{l-1} + g z_{l-1}),  z_l = E_l + s z_{l-1},
+// E_m = z_m; the small quantity g is formed without cancellation.  Near the poles lambda_mm underflows far below the double
 // range (2^-17000 at m = 2047), so each lane carries an integer exponent e (value = z 2^e),
 // renormalised every 8 steps; while every lane of a wave is below 2^-1100 the contraction
 // is skipped, and once every lane has e = 0 the plain recursion runs.
@@ -71,15 +75,18 @@ __device__ __forceinline__ bool negligible(double z1, double z2, int e) {
 template <int C>
 __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__ S, double* __restrict__ FT,
                                                       const double* __restrict__ alpha,
+                                                      const double* __restrict__ beta,
                                                       const double* __restrict__ cm,
-                                                      const double* __restrict__ xt,
+                                                      const double* __restrict__ ut,
+                                                      const double* __restrict__ sx,
                                                       const double* __restrict__ st, int k, int Lt,
-                                                      int ntb) {
+                                                      int ntb, unsigned long long* __restrict__ counter) {
   const int pair = blockIdx.x / ntb;
   const int tb = blockIdx.x % ntb;
   const int t = tb * 256 + threadIdx.x;
   const bool valid = t < k;
-  const double x = valid ? xt[t] : 0.0;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = valid ? sx[t] : 1.0;
   const double s = valid ? st[t] : 1.0;
   const int nm = (k - 1 - pair > pair) ? 2 : 1;
 
@@ -87,17 +94,18 @@ __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__
     const int m = im == 0 ? pair : k - 1 - pair;
     const double* __restrict__ Sm = S + tri_off(k, m) * C;
     const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
 
     int e;
     double z1 = cm[m] * pow_scaled(s, m, &e);
-    double z2 = 0.0;
     if (e > 0) {
       z1 = ldexp(z1, e);
       e = 0;
     }
+    double z2 = z1;   // E_m = z_m
     {
       const double w = ldexp(z1, e);
 #pragma unroll
@@ -108,20 +116,26 @@ __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__
     while (l + 8 <= k && __all(!valid || negligible(z1, z2, e))) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const double z = fma(am[l + i - m] * x, z1, -z2);
-        z2 = z1;
-        z1 = z;
+        const double g = fma(am[l + i - m], u, bm[l + i - m]);
+        z2 = sg * fma(g, z1, z2);
+        z1 = fma(sg, z1, z2);
       }
       renorm(z1, z2, e);
       l += 8;
+    }
+    if (counter != nullptr) {
+      // rows contracted by this wave times its valid lanes (one vector atomic per wave)
+      const unsigned long long nv = __popcll(__ballot(valid));
+      if ((threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(valid)) - 1 && nv > 0)
+        atomicAdd(counter, (unsigned long long)(k - l + 1) * nv);
     }
     // (b) scaled lanes present
     while (l + 8 <= k && !__all(!valid || e == 0)) {
 #pragma unroll 1
       for (int i = 0; i < 8; ++i) {
-        const double z = fma(am[l + i - m] * x, z1, -z2);
-        z2 = z1;
-        z1 = z;
+        const double g = fma(am[l + i - m], u, bm[l + i - m]);
+        z2 = sg * fma(g, z1, z2);
+        z1 = fma(sg, z1, z2);
         const double w = ldexp(z1, e);
         const double* __restrict__ row = Sm + (size_t)(l + i - m) * C;
 #pragma unroll
@@ -135,9 +149,9 @@ __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__
     for (; l < k; ++l) {
       {
         const int i = 0;
-        const double z = fma(am[l + i - m] * x, z1, -z2);
-        z2 = z1;
-        z1 = z;
+        const double g = fma(am[l + i - m], u, bm[l + i - m]);
+        z2 = sg * fma(g, z1, z2);
+        z1 = fma(sg, z1, z2);
         const double* __restrict__ row = Sm + (size_t)(l + i - m) * C;
         const double w = ldexp(z1, e);   // e == 0 except in the last partial chunk
 #pragma unroll
@@ -169,10 +183,14 @@ constexpr int FWD_ZS = 65;      // padded LDS row (doubles)
 template <int C>
 __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__ HM, double* __restrict__ R,
                                                       const double* __restrict__ alpha,
+                                                      const double* __restrict__ beta,
                                                       const double* __restrict__ cm,
-                                                      const double* __restrict__ xt,
-                                                      const double* __restrict__ st, int k, int Lt) {
+                                                      const double* __restrict__ ut,
+                                                      const double* __restrict__ sx,
+                                                      const double* __restrict__ st, int k, int Lt,
+                                                      unsigned long long* __restrict__ counter) {
   constexpr int CT = C >= 16 ? C / 16 : 1;
+  unsigned long long retained = 0;   // (l, theta) pairs multiplied by this wave
   __shared__ double Z[FWD_NW][FWD_LC][FWD_ZS];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int pair = blockIdx.x;
@@ -184,14 +202,16 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
   for (int im = 0; im < nm; ++im) {
     const int m = im == 0 ? pair : k - 1 - pair;
     const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Hm = HM + (size_t)m * k * C;
-    double z1[FWD_NTMAX], z2[FWD_NTMAX], xs[FWD_NTMAX];
+    double z1[FWD_NTMAX], z2[FWD_NTMAX], us[FWD_NTMAX], sgs[FWD_NTMAX];
     int ee[FWD_NTMAX];
 #pragma unroll
     for (int i = 0; i < FWD_NTMAX; ++i) {
       z1[i] = 0.0;
       z2[i] = 0.0;
-      xs[i] = 0.0;
+      us[i] = -1.0;
+      sgs[i] = 1.0;
       ee[i] = 0;
       if (i < NT) {
         const int t = (w + FWD_NW * i) * 64 + lane;
@@ -202,8 +222,10 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
             z1[i] = ldexp(z1[i], e);
             e = 0;
           }
+          z2[i] = z1[i];   // E_m = z_m
           ee[i] = e;
-          xs[i] = xt[t];
+          us[i] = ut[t];
+          sgs[i] = sx[t];
         }
       }
     }
@@ -227,9 +249,9 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
             double v = 0.0;
             if (l < k) {
               if (l > m) {
-                const double z = fma(am[l - m] * xs[i], z1[i], -z2[i]);
-                z2[i] = z1[i];
-                z1[i] = z;
+                const double g = fma(am[l - m], us[i], bm[l - m]);
+                z2[i] = sgs[i] * fma(g, z1[i], z2[i]);
+                z1[i] = fma(sgs[i], z1[i], z2[i]);
               }
               v = ldexp(z1[i], ee[i]);
             }
@@ -238,6 +260,9 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
           }
           __syncthreads();
           if (!skip) {
+            const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
+            const int nt = (k - tile * 64) < 64 ? (k - tile * 64) : 64;
+            retained += (unsigned long long)nl * (unsigned long long)nt;
 #pragma unroll 4
             for (int kk = 0; kk < 16; ++kk) {
               const int tl = 4 * kk + lq;
@@ -287,51 +312,56 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
       __syncthreads();
     }
   }
+  if (counter != nullptr && lane == 0 && retained > 0) atomicAdd(counter, retained);
 }
 
 // ------------------------------------------------------------------------------------------
 template <int C>
 static hipError_t inv_c(const ShtTables& T, const LegTables& G, const double* S, double* FT,
-                        hipStream_t s) {
+                        unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   const int ntb = (k + 255) / 256;
   const int npairs = (k + 1) / 2;
-  k_legendre_inv<C><<<npairs * ntb, 256, 0, s>>>(S, FT, G.alpha, G.cm, T.xt, T.st, k, G.Lt, ntb);
+  k_legendre_inv<C><<<npairs * ntb, 256, 0, s>>>(S, FT, G.alpha, G.beta, G.cm, T.ut, T.sx, T.st, k, G.Lt,
+                                                 ntb, counter);
   return hipGetLastError();
 }
 
 template <int C>
 static hipError_t fwd_c(const ShtTables& T, const LegTables& G, const double* HM, double* R,
-                        hipStream_t s) {
+                        unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   const int npairs = (k + 1) / 2;
-  k_legendre_fwd<C><<<npairs, FWD_NW * 64, 0, s>>>(HM, R, G.alpha, G.cm, T.xt, T.st, k, G.Lt);
+  k_legendre_fwd<C><<<npairs, FWD_NW * 64, 0, s>>>(HM, R, G.alpha, G.beta, G.cm, T.ut, T.sx, T.st, k, G.Lt,
+                                                   counter);
   return hipGetLastError();
 }
 
 hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const Batch& b,
-                                   const double* S, double* FT, int precision, hipStream_t s) {
+                                   const double* S, double* FT, int precision,
+                                   unsigned long long* counter, hipStream_t s) {
   (void)precision;
   switch (b.C) {
-    case 2: return inv_c<2>(T, G, S, FT, s);
-    case 4: return inv_c<4>(T, G, S, FT, s);
-    case 8: return inv_c<8>(T, G, S, FT, s);
-    case 16: return inv_c<16>(T, G, S, FT, s);
-    case 32: return inv_c<32>(T, G, S, FT, s);
+    case 2: return inv_c<2>(T, G, S, FT, counter, s);
+    case 4: return inv_c<4>(T, G, S, FT, counter, s);
+    case 8: return inv_c<8>(T, G, S, FT, counter, s);
+    case 16: return inv_c<16>(T, G, S, FT, counter, s);
+    case 32: return inv_c<32>(T, G, S, FT, counter, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const Batch& b,
-                                   const double* HM, double* R, int precision, hipStream_t s) {
+                                   const double* HM, double* R, int precision,
+                                   unsigned long long* counter, hipStream_t s) {
   (void)precision;
   if (T.k > FWD_NTMAX * FWD_NW * 64) return hipErrorInvalidValue;
   switch (b.C) {
-    case 2: return fwd_c<2>(T, G, HM, R, s);
-    case 4: return fwd_c<4>(T, G, HM, R, s);
-    case 8: return fwd_c<8>(T, G, HM, R, s);
-    case 16: return fwd_c<16>(T, G, HM, R, s);
-    case 32: return fwd_c<32>(T, G, HM, R, s);
+    case 2: return fwd_c<2>(T, G, HM, R, counter, s);
+    case 4: return fwd_c<4>(T, G, HM, R, counter, s);
+    case 8: return fwd_c<8>(T, G, HM, R, counter, s);
+    case 16: return fwd_c<16>(T, G, HM, R, counter, s);
+    case 32: return fwd_c<32>(T, G, HM, R, counter, s);
   }
   return hipErrorInvalidValue;
 }

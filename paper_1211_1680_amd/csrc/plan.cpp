@@ -99,14 +99,21 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
     thi[p] = cLD(cosl(ang), sinl(ang));
   }
 
-  std::vector<double> xt(k), st(k);
+  std::vector<double> xt(k), st(k), ut(k), sx(k);
   for (int t = 0; t < k; ++t) {
     const LD th = PI_L * (LD)(2 * t + 1) / (LD)n;
     xt[t] = (double)cosl(th);
     st[t] = (double)sinl(th);
+    // |cos| - 1 = -2 sin^2(theta'/2) with theta' the angular distance to the nearer pole
+    const LD thp = (2 * t + 1 <= n / 2) ? th : PI_L * (LD)(n - 2 * t - 1) / (LD)n;
+    const LD h = sinl(0.5L * thp);
+    ut[t] = (double)(-2.0L * h * h);
+    sx[t] = (2 * (2 * t + 1) <= n) ? 1.0 : -1.0;
   }
   st[k - 1] = 0.0;   // theta_{k-1} = pi exactly
   xt[k - 1] = -1.0;
+  ut[k - 1] = 0.0;
+  sx[k - 1] = -1.0;
 
   std::vector<cLD> hph(2 * k - 1);
   for (int j = -(k - 1); j <= k - 1; ++j) {
@@ -122,6 +129,8 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
   if ((e = upload(&T->tw_hi, to_d2(thi))) != hipSuccess) return e;
   if ((e = upload(&T->xt, xt)) != hipSuccess) return e;
   if ((e = upload(&T->st, st)) != hipSuccess) return e;
+  if ((e = upload(&T->ut, ut)) != hipSuccess) return e;
+  if ((e = upload(&T->sx, sx)) != hipSuccess) return e;
   if ((e = upload(&T->hphase, to_d2(hph))) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -134,6 +143,8 @@ void free_sht_tables(ShtTables* T) {
   hipFree(T->tw_hi);
   hipFree(T->xt);
   hipFree(T->st);
+  hipFree(T->ut);
+  hipFree(T->sx);
   hipFree(T->hphase);
   *T = ShtTables();
 }
@@ -145,10 +156,11 @@ void free_sht_tables(ShtTables* T) {
 // is rewritten as z_l = alpha_l x z_{l-1} - z_{l-2} with lambda_l = d_l z_l:
 //   d_m = d_{m+1} = 1,  d_l = a_l b_l d_{l-2},  alpha_l = a_l d_{l-1} / d_l,
 //   alpha_{m+1} = sqrt(2m+3)  (z_{m-1} = 0).
-void leg_factors_host(int Lt, std::vector<double>* alpha, std::vector<double>* dfac,
-                      std::vector<double>* cm) {
+void leg_factors_host(int Lt, std::vector<double>* alpha, std::vector<double>* beta,
+                      std::vector<double>* dfac, std::vector<double>* cm) {
   const size_t rows = (size_t)tri_rows(Lt);
   alpha->assign(rows, 0.0);
+  beta->assign(rows, -2.0);
   dfac->assign(rows, 0.0);
   cm->assign(Lt, 0.0);
   for (int m = 0; m < Lt; ++m) {
@@ -160,6 +172,7 @@ void leg_factors_host(int Lt, std::vector<double>* alpha, std::vector<double>* d
     if (m + 1 < Lt) {
       d[1] = 1.0L;
       (*alpha)[off + 1] = (double)sqrtl((LD)(2 * m + 3));
+      (*beta)[off + 1] = (double)(sqrtl((LD)(2 * m + 3)) - 2.0L);
       (*dfac)[off + 1] = 1.0;
     }
     for (int l = m + 2; l < Lt; ++l) {
@@ -167,7 +180,9 @@ void leg_factors_host(int Lt, std::vector<double>* alpha, std::vector<double>* d
       const LD a = sqrtl((4.0L * ll * ll - 1.0L) / (ll * ll - mm * mm));
       const LD bb = sqrtl(((ll - 1.0L) * (ll - 1.0L) - mm * mm) / (4.0L * (ll - 1.0L) * (ll - 1.0L) - 1.0L));
       d[l - m] = a * bb * d[l - m - 2];
-      (*alpha)[off + l - m] = (double)(a * d[l - m - 1] / d[l - m]);
+      const LD al = a * d[l - m - 1] / d[l - m];
+      (*alpha)[off + l - m] = (double)al;
+      (*beta)[off + l - m] = (double)(al - 2.0L);
       (*dfac)[off + l - m] = (double)d[l - m];
     }
   }
@@ -181,11 +196,12 @@ void leg_factors_host(int Lt, std::vector<double>* alpha, std::vector<double>* d
 }
 
 hipError_t build_leg_tables(int Lt, LegTables* G) {
-  std::vector<double> alpha, dfac, cm;
-  leg_factors_host(Lt, &alpha, &dfac, &cm);
+  std::vector<double> alpha, beta, dfac, cm;
+  leg_factors_host(Lt, &alpha, &beta, &dfac, &cm);
   G->Lt = Lt;
   hipError_t e;
   if ((e = upload(&G->alpha, alpha)) != hipSuccess) return e;
+  if ((e = upload(&G->beta, beta)) != hipSuccess) return e;
   if ((e = upload(&G->dfac, dfac)) != hipSuccess) return e;
   if ((e = upload(&G->cm, cm)) != hipSuccess) return e;
   return hipSuccess;
@@ -193,6 +209,7 @@ hipError_t build_leg_tables(int Lt, LegTables* G) {
 
 void free_leg_tables(LegTables* G) {
   hipFree(G->alpha);
+  hipFree(G->beta);
   hipFree(G->dfac);
   hipFree(G->cm);
   *G = LegTables();

@@ -58,6 +58,8 @@ def _load():
             lib.orc_lambda_log2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
             lib.orc_legendre_inverse.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
             lib.orc_legendre_forward.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+            lib.orc_legendre_inverse_rings.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                                                       ctypes.POINTER(ctypes.c_int), dp]
             _lib = lib
     return _lib
 
@@ -131,6 +133,26 @@ def inverse_sht(flm: np.ndarray, k: int, reality: bool = False) -> np.ndarray:
     if reality:
         return f.real.copy()
     return f
+
+
+def inverse_sht_rings(flm: np.ndarray, k: int, rings, reality: bool = False) -> np.ndarray:
+    """Eq. (1) evaluated on selected rings only: [nmaps, len(rings), 2k-1].  Same sums as
+    inverse_sht (for checking outputs too large to synthesise whole on the CPU)."""
+    flm = _as_maps(flm, k)
+    nmaps = flm.shape[0]
+    n = 2 * k - 1
+    rings = np.ascontiguousarray(np.asarray(rings, dtype=np.int32))
+    if rings.size and (rings.min() < 0 or rings.max() >= k):
+        raise ValueError("ring index out of range")
+    F = np.zeros((nmaps, rings.size, n), dtype=np.complex128)
+    _load().orc_legendre_inverse_rings(k, nmaps, _dp(flm.view(np.float64)), rings.size,
+                                       rings.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                       _dp(F.view(np.float64)))
+    spec = np.zeros_like(F)
+    ms = np.arange(-(k - 1), k)
+    spec[..., ms % n] = F
+    f = np.fft.ifft(spec, axis=-1) * n
+    return f.real.copy() if reality else f
 
 
 def inverse_sht_direct(flm: np.ndarray, k: int) -> np.ndarray:

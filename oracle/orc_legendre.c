@@ -166,7 +166,8 @@ void orc_lambda_log2(int k, int m, double theta, double* out) {
  *   F_m(theta_t) = sum_{l=|m|}^{k-1} f_lm lambda_lm(theta_t),   |m| <= k-1, t = 0..k-1.
  * flm: [ncol][k*k] complex, f_lm at l*l+l+m.   F: [ncol][k][2k-1] complex, m at index m+k-1.
  */
-void orc_legendre_inverse(int k, int ncol, const double complex* flm, double complex* F) {
+static void legendre_inverse_rings(int k, int ncol, const double complex* flm, int nrings,
+                                   const int* rings, double complex* F) {
     const int n = 2 * k - 1;
     LD *ta, *tb;
     coef_table(k, &ta, &tb);
@@ -177,7 +178,8 @@ void orc_legendre_inverse(int k, int ncol, const double complex* flm, double com
         LD* accp = (LD*)malloc(sizeof(LD) * 2 * (size_t)ncol);
         LD* accn = (LD*)malloc(sizeof(LD) * 2 * (size_t)ncol);
 #pragma omp for schedule(dynamic, 1)
-        for (int t = 0; t < k; ++t) {
+        for (int r = 0; r < nrings; ++r) {
+            const int t = rings ? rings[r] : r;
             LD theta = node_theta(k, t);
             diag_values(k, theta, diag);
             for (int m = 0; m < k; ++m) {
@@ -198,7 +200,7 @@ void orc_legendre_inverse(int k, int ncol, const double complex* flm, double com
                             accn[2 * c + 1] += sgn * lam * (LD)cimag(fn);
                         }
                     }
-                    double complex* Fc = F + (size_t)c * k * n + (size_t)t * n;
+                    double complex* Fc = F + (size_t)c * nrings * n + (size_t)r * n;
                     Fc[k - 1 + m] = (double)accp[2 * c] + I * (double)accp[2 * c + 1];
                     if (m > 0) Fc[k - 1 - m] = (double)accn[2 * c] + I * (double)accn[2 * c + 1];
                 }
@@ -211,6 +213,16 @@ void orc_legendre_inverse(int k, int ncol, const double complex* flm, double com
     }
     free(ta);
     free(tb);
+}
+
+void orc_legendre_inverse(int k, int ncol, const double complex* flm, double complex* F) {
+    legendre_inverse_rings(k, ncol, flm, k, NULL, F);
+}
+
+/* The same sums restricted to the rings listed in rings[0..nrings): F is [ncol][nrings][2k-1]. */
+void orc_legendre_inverse_rings(int k, int ncol, const double complex* flm, int nrings,
+                                const int* rings, double complex* F) {
+    legendre_inverse_rings(k, ncol, flm, nrings, rings, F);
 }
 
 /*

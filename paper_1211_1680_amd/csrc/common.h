@@ -29,14 +29,22 @@ inline int ilog2(int v) {
 struct ShtTables {
   int k = 0;        // band-limit
   int n = 0;        // 2k-1 samples per ring / extended theta period
-  int M = 0;        // power-of-two FFT length >= 4k-3 (Bluestein and theta convolution)
+  int nrad = 0;     // > 0: n = rad[0] * ... * rad[nrad-1] (odd radices <= 13), mixed-radix DFT
+  int rad[8] = {0};
+  double2* twn_lo = nullptr;   // exp(-2 pi i p / n), p < 64
+  double2* twn_hi = nullptr;   // exp(-2 pi i 64 p / n), p < ceil(n / 64)
+  int M = 0;        // Bluestein power-of-two length >= 2n-1 (when nrad == 0)
   int logM = 0;
-  int loglo = 0;    // two-level twiddle split: W_M^p = lo[p & (2^loglo - 1)] * hi[p >> loglo]
   double2* chirp = nullptr;    // c_q = exp(-i pi q^2 / n), q < n
   double2* bhat = nullptr;     // FFT_M of conj(c_q) for |q| <= n-1 (wrapped), divided by M
-  double2* what = nullptr;     // FFT_M of the even theta weight w_e(p) (wrapped), / (M n^2)
-  double2* tw_lo = nullptr;    // exp(-2 pi i p / M), p < 2^loglo
-  double2* tw_hi = nullptr;    // exp(-2 pi i p 2^loglo / M), p < M / 2^loglo
+  int Nc = 0;       // power-of-two correlation length >= 2k-1
+  int logNc = 0;
+  double2* khat0 = nullptr;    // FFT_Nc of Kt_0(c) = w_e(-2c), wrapped, / (Nc n^2)
+  double2* khat1 = nullptr;    // FFT_Nc of Kt_1(c) = w_e(2 - 2c), wrapped, / (Nc n^2)
+  int logP = 0;     // P = 2^logP = max(M, Nc): one twiddle table for every power-of-two length
+  int loglo = 0;    // two-level twiddle split: W_P^p = lo[p & (2^loglo - 1)] * hi[p >> loglo]
+  double2* tw_lo = nullptr;    // exp(-2 pi i p / P), p < 2^loglo
+  double2* tw_hi = nullptr;    // exp(-2 pi i p 2^loglo / P), p < P / 2^loglo
   double* xt = nullptr;        // cos(theta_t), t < k
   double* st = nullptr;        // sin(theta_t), t < k
   double* ut = nullptr;        // |cos(theta_t)| - 1 = -2 sin^2(theta'/2), theta' = min(theta, pi - theta)

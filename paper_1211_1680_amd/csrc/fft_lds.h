@@ -1,11 +1,13 @@
-// Power-of-two complex FFT held in LDS, executed cooperatively by the Tp threads of one
-// problem (a slice of a workgroup).  Stockham autosort: every pass reads all of its inputs
-// into registers, synchronises, and writes its outputs in natural order, so a single LDS
-// buffer of M values suffices.  Radix-16 passes, preceded by one radix-2/4/8 pass when
-// log2(M) is not a multiple of 4.  Every thread of the workgroup must call these functions
-// (they contain __syncthreads()).
+// Complex FFTs held in LDS, executed cooperatively by the Tp threads of one problem (a slice
+// of a workgroup).  Stockham autosort: every pass reads all of its inputs into registers,
+// synchronises, and writes its outputs in natural order, so a single LDS buffer suffices.
+// Power-of-two lengths use radix-8 (or 16) passes after one smaller pass; odd lengths use
+// radices 3..13.  A thread holds at most VPT values per pass.  Every thread of the workgroup
+// must call these functions (they contain __syncthreads()).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "fft_consts.h"
 
 namespace s2let {
 
@@ -114,7 +116,7 @@ struct SmallDft<16, INV> {
   }
 };
 
-// W_M^p (sign chosen by INV) from the two-level table.
+// W^p (sign chosen by INV) from a two-level table: W^p = lo[p mod 2^loglo] * hi[p >> loglo].
 template <bool INV>
 __device__ __forceinline__ double2 twiddle(int p, const double2* __restrict__ tlo,
                                            const double2* __restrict__ thi, int loglo) {
@@ -123,12 +125,12 @@ __device__ __forceinline__ double2 twiddle(int p, const double2* __restrict__ tl
 }
 
 // One Stockham pass of radix R over the M values of buf, sub-transform length Ns.
-// Butterflies j = lt, lt+Tp, ... < M/R; at most 16/R per thread.
-template <int R, bool INV>
+// Butterflies j = lt, lt+Tp, ... < M/R; a thread holds at most VPT values (Tp >= M/VPT).
+template <int R, bool INV, int VPT>
 __device__ __forceinline__ void stockham_pass(double2* buf, int M, int Ns, int lt, int Tp,
                                               const double2* __restrict__ tlo,
-                                              const double2* __restrict__ thi, int loglo) {
-  constexpr int PER = 16 / R;
+                                              const double2* __restrict__ thi, int loglo, int tsh) {
+  constexpr int PER = VPT / R > 0 ? VPT / R : 1;
   const int nb = M / R;
   const int stride = M / (Ns * R);
   double2 v[PER][R];
@@ -140,7 +142,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int M, int Ns, int l
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = buf[j + r * nb];
       if (Ns > 1 && kk != 0) {
-        const double2 w1 = twiddle<INV>(kk * stride, tlo, thi, loglo);
+        const double2 w1 = twiddle<INV>((kk * stride) << tsh, tlo, thi, loglo);
         double2 w = w1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -165,42 +167,133 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int M, int Ns, int l
   __syncthreads();
 }
 
-// Full FFT of length M = 2^logM (unnormalised), sign -1 (INV = false) or +1.
-template <bool INV>
+// Full FFT of length M = 2^logM (unnormalised), sign -1 (INV = false) or +1.  The twiddle
+// table holds W_P for P = M << tsh.
+template <bool INV, int VPT>
 __device__ void fft_pow2(double2* buf, int M, int logM, int lt, int Tp,
-                         const double2* __restrict__ tlo, const double2* __restrict__ thi, int loglo) {
+                         const double2* __restrict__ tlo, const double2* __restrict__ thi, int loglo,
+                         int tsh) {
+  // leading pass of radix 2^rem so that the remaining passes have the full radix (16 or 8)
   int Ns = 1;
-  const int rem = logM & 3;
+  const int rem = VPT >= 16 ? (logM & 3) : (logM % 3);
   if (rem == 1) {
-    stockham_pass<2, INV>(buf, M, 1, lt, Tp, tlo, thi, loglo);
+    stockham_pass<2, INV, VPT>(buf, M, 1, lt, Tp, tlo, thi, loglo, tsh);
     Ns = 2;
   } else if (rem == 2) {
-    stockham_pass<4, INV>(buf, M, 1, lt, Tp, tlo, thi, loglo);
+    stockham_pass<4, INV, VPT>(buf, M, 1, lt, Tp, tlo, thi, loglo, tsh);
     Ns = 4;
   } else if (rem == 3) {
-    stockham_pass<8, INV>(buf, M, 1, lt, Tp, tlo, thi, loglo);
+    stockham_pass<8, INV, VPT>(buf, M, 1, lt, Tp, tlo, thi, loglo, tsh);
     Ns = 8;
   }
-  for (; Ns < M; Ns *= 16) stockham_pass<16, INV>(buf, M, Ns, lt, Tp, tlo, thi, loglo);
+  if (VPT >= 16) {
+    for (; Ns < M; Ns *= 16) stockham_pass<16, INV, VPT>(buf, M, Ns, lt, Tp, tlo, thi, loglo, tsh);
+  } else {
+    for (; Ns < M; Ns *= 8) stockham_pass<8, INV, VPT>(buf, M, Ns, lt, Tp, tlo, thi, loglo, tsh);
+  }
 }
 
-// Problems per workgroup and threads per problem for an FFT of length M: every pass gives a
-// thread at most 16 values; a workgroup holds at most 4096 values (64 KiB), except M = 8192.
-struct FftShape {
-  int P;    // problems per workgroup
-  int Tp;   // threads per problem
-  __host__ __device__ static FftShape of(int M) {
-    FftShape s;
-    s.Tp = M >= 16 ? M / 16 : 1;
-    if (M >= 4096) {
-      s.P = 1;
-    } else {
-      s.P = 4096 / M;
-      if (s.P * s.Tp > 256) s.P = 256 / s.Tp;
+// ---- odd radices ----
+template <int R>
+__device__ __forceinline__ double cosR(int q);
+template <int R>
+__device__ __forceinline__ double sinR(int q);
+#define S2LET_TRIG(R)                                                              \
+  template <>                                                                      \
+  __device__ __forceinline__ double cosR<R>(int q) { return kCos##R[q]; }          \
+  template <>                                                                      \
+  __device__ __forceinline__ double sinR<R>(int q) { return kSin##R[q]; }
+S2LET_TRIG(3)
+S2LET_TRIG(5)
+S2LET_TRIG(7)
+S2LET_TRIG(9)
+S2LET_TRIG(11)
+S2LET_TRIG(13)
+#undef S2LET_TRIG
+
+// DFT of odd size R on v[0..R-1] using the symmetric pairs (j, R-j):
+// X_q = A_q -+ i B_q, X_{R-q} = A_q +- i B_q with A_q = v_0 + sum_j (v_j + v_{R-j}) cos(2 pi j q/R),
+// B_q = sum_j (v_j - v_{R-j}) sin(2 pi j q/R).
+template <int R, bool INV>
+struct OddDft {
+  __device__ __forceinline__ static void run(double2* v) {
+    constexpr int h = (R - 1) / 2;
+    double2 a[h], b[h];
+#pragma unroll
+    for (int j = 1; j <= h; ++j) {
+      a[j - 1] = cadd(v[j], v[R - j]);
+      b[j - 1] = csub(v[j], v[R - j]);
     }
-    return s;
+    const double2 x0 = v[0];
+    double2 sum = x0;
+#pragma unroll
+    for (int j = 0; j < h; ++j) sum = cadd(sum, a[j]);
+    v[0] = sum;
+#pragma unroll
+    for (int q = 1; q <= h; ++q) {
+      double ax = x0.x, ay = x0.y, bx = 0.0, by = 0.0;
+#pragma unroll
+      for (int j = 1; j <= h; ++j) {
+        const double c = cosR<R>((j * q) % R), sn = sinR<R>((j * q) % R);
+        ax = fma(a[j - 1].x, c, ax);
+        ay = fma(a[j - 1].y, c, ay);
+        bx = fma(b[j - 1].x, sn, bx);
+        by = fma(b[j - 1].y, sn, by);
+      }
+      if (INV) {   // A + i B, A - i B
+        v[q] = make_double2(ax - by, ay + bx);
+        v[R - q] = make_double2(ax + by, ay - bx);
+      } else {     // A - i B, A + i B
+        v[q] = make_double2(ax + by, ay - bx);
+        v[R - q] = make_double2(ax - by, ay + bx);
+      }
+    }
   }
 };
+
+// One Stockham pass of odd radix R over n values (n divisible by R), sub-transform length Ns.
+// Needs Tp >= n/VPT so that a thread has at most MAXB = ceil(VPT/R) butterflies.  Twiddles
+// W_n^p come from a two-level table with 64-entry low part.
+template <int R, bool INV, int VPT>
+__device__ __forceinline__ void stockham_odd_pass(double2* buf, int n, int Ns, int lt, int Tp,
+                                                  const double2* __restrict__ tlo,
+                                                  const double2* __restrict__ thi) {
+  constexpr int MAXB = (VPT + R - 1) / R;
+  const int nb = n / R;
+  const int stride = n / (Ns * R);
+  double2 v[MAXB][R];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int j = lt + i * Tp;
+    if (j < nb) {
+      const int kk = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[j + r * nb];
+      if (kk != 0) {
+        const double2 w1 = twiddle<INV>(kk * stride, tlo, thi, 6);
+        double2 w = w1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[i][r] = cmul(v[i][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int j = lt + i * Tp;
+    if (j < nb) {
+      OddDft<R, INV>::run(v[i]);
+      const int kk = j % Ns;
+      const int base = (j - kk) * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
 
 // Workgroups are handed to the 8 XCDs round-robin; give consecutive logical indices to the
 // same XCD so that problems writing neighbouring columns of a row share an L2.

@@ -4,10 +4,13 @@
 //   theta stage: the exact sin(theta) quadrature of the band-limited product, producing the
 //                weighted values H'_m(theta_t) that the Legendre contraction sums against,
 //   inverse phi: f(theta_t, phi_p) = sum_m F_m(theta_t) e^{i m phi_p}.
-// All DFTs of odd length n are Bluestein transforms on a power-of-two LDS FFT of length
-// M >= 2n-1.  Real maps are packed two per complex transform (phi stages); in the theta stage
-// an even and an odd m are packed into one transform (their extensions have opposite
-// symmetry about theta = pi and the even quadrature weight preserves it).
+// DFTs of odd length n run in LDS: a Stockham mixed-radix transform (radices 3..13) when n
+// factors into them (n = 4095 at k = 2048), otherwise Bluestein's chirp transform on a
+// power-of-two FFT of length M >= 2n-1.  Real maps are packed two per complex transform (phi
+// stages); in the theta stage an even and an odd m share one transform (their extensions have
+// opposite symmetry about theta = pi, which the even part of the quadrature weight preserves).
+// The weight correlation splits by the parity of the frequency, since the even weight w_e(p)
+// vanishes for odd p: two circular correlations of length Nc >= 2k-1 instead of one of 4k-3.
 #include "common.h"
 #include "fft_lds.h"
 #include "../../include/s2let_mi355x.h"
@@ -15,54 +18,74 @@
 namespace s2let {
 
 struct FftArgs {
-  int k, n, M, logM, loglo;
-  const double2* chirp;
-  const double2* bhat;
-  const double2* what;
-  const double2* tw_lo;
+  int k, n;
+  int mixed;                 // 1: Stockham mixed radix over the radices in rad_code
+  int nrad;
+  unsigned int rad_code;     // radix s in bits [4s, 4s+4)
+  const double2* twn_lo;     // W_n^p = lo[p & 63] * hi[p >> 6]
+  const double2* twn_hi;
+  int M, logM;               // Bluestein length (when not mixed)
+  const double2* chirp;      // exp(-i pi q^2/n)
+  const double2* bhat;       // FFT_M(conj chirp, wrapped) / M
+  int Nc, logNc;             // correlation length
+  const double2* khat0;      // FFT_Nc of the even-frequency weight kernel / (Nc n^2)
+  const double2* khat1;      // same, odd frequencies
+  const double2* tw_lo;      // W_P two-level table, P = 2^logP the largest power of two used
   const double2* tw_hi;
-  const double2* hphase;
+  int loglo, logP;
+  const double2* hphase;     // exp(-i pi j/n), j in [-(k-1), k-1]
+  int T, P, buf;             // threads per problem, problems per block, LDS values per problem
 };
 
-static FftArgs fft_args(const ShtTables& T) {
-  FftArgs a;
-  a.k = T.k;
-  a.n = T.n;
-  a.M = T.M;
-  a.logM = T.logM;
-  a.loglo = T.loglo;
-  a.chirp = T.chirp;
-  a.bhat = T.bhat;
-  a.what = T.what;
-  a.tw_lo = T.tw_lo;
-  a.tw_hi = T.tw_hi;
-  a.hphase = T.hphase;
-  return a;
-}
-
-// buf <- Bluestein convolution stage: FFT, pointwise product with tab, inverse FFT.
-__device__ __forceinline__ void convolve(double2* buf, const FftArgs& A, const double2* __restrict__ tab,
-                                         int lt, int Tp) {
-  fft_pow2<false>(buf, A.M, A.logM, lt, Tp, A.tw_lo, A.tw_hi, A.loglo);
-  for (int q = lt; q < A.M; q += Tp) buf[q] = cmul(buf[q], tab[q]);
+// In-place DFT of length n of buf[0..n) (natural order in and out), sign -1 or +1 (INV).
+template <bool INV, int VPT>
+__device__ void dft_odd(double2* buf, const FftArgs& A, int lt) {
+  if (A.mixed) {
+    int Ns = 1;
+    for (int s = 0; s < A.nrad; ++s) {
+      const int R = (A.rad_code >> (4 * s)) & 15;
+      switch (R) {
+        case 3: stockham_odd_pass<3, INV, VPT>(buf, A.n, Ns, lt, A.T, A.twn_lo, A.twn_hi); break;
+        case 5: stockham_odd_pass<5, INV, VPT>(buf, A.n, Ns, lt, A.T, A.twn_lo, A.twn_hi); break;
+        case 7: stockham_odd_pass<7, INV, VPT>(buf, A.n, Ns, lt, A.T, A.twn_lo, A.twn_hi); break;
+        case 9: stockham_odd_pass<9, INV, VPT>(buf, A.n, Ns, lt, A.T, A.twn_lo, A.twn_hi); break;
+        case 11: stockham_odd_pass<11, INV, VPT>(buf, A.n, Ns, lt, A.T, A.twn_lo, A.twn_hi); break;
+        default: stockham_odd_pass<13, INV, VPT>(buf, A.n, Ns, lt, A.T, A.twn_lo, A.twn_hi); break;
+      }
+      Ns *= R;
+    }
+    return;
+  }
+  // Bluestein: X_j = c_j sum_q (x_q c_q) conj(c_{j-q}) with c_q = exp(-+ i pi q^2 / n)
+  for (int q = lt; q < A.M; q += A.T) {
+    double2 v = make_double2(0.0, 0.0);
+    if (q < A.n) v = cmul(buf[q], INV ? conjd(A.chirp[q]) : A.chirp[q]);
+    buf[q] = v;
+  }
   __syncthreads();
-  fft_pow2<true>(buf, A.M, A.logM, lt, Tp, A.tw_lo, A.tw_hi, A.loglo);
+  fft_pow2<false, VPT>(buf, A.M, A.logM, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logM);
+  for (int q = lt; q < A.M; q += A.T)
+    buf[q] = cmul(buf[q], INV ? conjd(A.bhat[(A.M - q) & (A.M - 1)]) : A.bhat[q]);
+  __syncthreads();
+  fft_pow2<true, VPT>(buf, A.M, A.logM, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logM);
+  for (int q = lt; q < A.n; q += A.T) buf[q] = cmul(buf[q], INV ? conjd(A.chirp[q]) : A.chirp[q]);
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------------------------------
 // phi stage, forward.  Problem = (ring t, map pair) for real maps, (ring t, map) for complex.
 // Output GT[(t*k + m)*C + c] for m < k.
 // ------------------------------------------------------------------------------------------
-template <int REAL>
-__global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __restrict__ f, long long map_stride,
-                              double* __restrict__ GT, int C, int nb, int used, int nprob) {
+template <int REAL, int VPT>
+__global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __restrict__ f,
+                                                     long long map_stride, double* __restrict__ GT,
+                                                     int C, int nb, int used, int nprob) {
   extern __shared__ double2 smem[];
-  const FftShape sh = FftShape::of(A.M);
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int pl = threadIdx.x / sh.Tp, lt = threadIdx.x % sh.Tp;
-  const int p = blk * sh.P + pl;
+  const int pl = threadIdx.x / A.T, lt = threadIdx.x % A.T;
+  const int p = blk * A.P + pl;
   const bool valid = p < nprob;
-  double2* buf = smem + (size_t)pl * A.M;
+  double2* buf = smem + (size_t)pl * A.buf;
   const int k = A.k, n = A.n;
   const int nunits = REAL ? (nb + 1) / 2 : nb;
   const int t = valid ? p / nunits : 0;
@@ -70,9 +93,9 @@ __global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  for (int q = lt; q < A.M; q += sh.Tp) {
+  for (int q = lt; q < n; q += A.T) {
     double2 z = make_double2(0.0, 0.0);
-    if (valid && q < n) {
+    if (valid) {
       if (REAL) {
         z.x = f[(size_t)ma * map_stride + (size_t)t * n + q];
         z.y = hasb ? f[(size_t)(ma + 1) * map_stride + (size_t)t * n + q] : 0.0;
@@ -80,29 +103,25 @@ __global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __
         const double2* fc = reinterpret_cast<const double2*>(f);
         z = fc[(size_t)ma * map_stride + (size_t)t * n + q];
       }
-      z = cmul(z, A.chirp[q]);
     }
     buf[q] = z;
   }
   __syncthreads();
-  convolve(buf, A, A.bhat, lt, sh.Tp);
+  dft_odd<false, VPT>(buf, A, lt);
 
   const double wphi = 2.0 * M_PI / (double)n;
   if (valid) {
-    for (int m = lt; m < k; m += sh.Tp) {
-      const double2 zp = cmul(A.chirp[m], buf[m]);                 // Z_m
-      const int mm = (m == 0) ? 0 : n - m;
-      const double2 zn = cmul(A.chirp[mm], buf[mm]);               // Z_{-m}
+    for (int m = lt; m < k; m += A.T) {
+      const double2 zp = buf[m];                     // Z_m
+      const double2 zn = buf[m == 0 ? 0 : n - m];    // Z_{-m}
       double* row = GT + ((size_t)t * k + m) * C;
       if (REAL) {
         // A_m = (Z_m + conj Z_{-m}) / 2,  B_m = (Z_m - conj Z_{-m}) / (2i)
-        const double ax = 0.5 * (zp.x + zn.x), ay = 0.5 * (zp.y - zn.y);
-        const double dx = zp.x - zn.x, dy = zp.y + zn.y;
-        row[2 * ma] = wphi * ax;
-        row[2 * ma + 1] = wphi * ay;
+        row[2 * ma] = wphi * 0.5 * (zp.x + zn.x);
+        row[2 * ma + 1] = wphi * 0.5 * (zp.y - zn.y);
         if (hasb) {
-          row[2 * ma + 2] = wphi * 0.5 * dy;
-          row[2 * ma + 3] = -wphi * 0.5 * dx;
+          row[2 * ma + 2] = wphi * 0.5 * (zp.y + zn.y);
+          row[2 * ma + 3] = -wphi * 0.5 * (zp.x - zn.x);
         }
       } else {
         row[4 * ma] = wphi * zp.x;
@@ -119,27 +138,32 @@ __global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __
 // ------------------------------------------------------------------------------------------
 // theta stage.  Problem = (m pair (2mu, 2mu+1), series s = column pair (2s, 2s+1)).
 // Input GT[(t*k + m)*C + c], output HM[(m*k + t)*C + c].
+//   D_j  = sum_t g_t e^{-2 pi i j t/n}        (g: packed extension, period n)
+//   u_j  = e^{-i pi j/n} D_j,                  |j| <= k-1
+//   I_j' = sum_j u_j w_e(j + j')               (w_e(p) = 2/(1-p^2) for even p, 0 for odd p)
+//   H_t  = sum_j' e^{-i pi j'/n} I_j' e^{-2 pi i j' t/n} / n^2
+// and the fold H'_E(t) = H_t + H_{n-1-t}, H'_O(t) = H_t - H_{n-1-t} (t < k-1).
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restrict__ GT, double* __restrict__ HM, int C,
-                        int nprob) {
+template <int VPT>
+__global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restrict__ GT,
+                                               double* __restrict__ HM, int C, int nprob) {
   extern __shared__ double2 smem[];
-  const FftShape sh = FftShape::of(A.M);
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int pl = threadIdx.x / sh.Tp, lt = threadIdx.x % sh.Tp;
-  const int p = blk * sh.P + pl;
+  const int pl = threadIdx.x / A.T, lt = threadIdx.x % A.T;
+  const int p = blk * A.P + pl;
   const bool valid = p < nprob;
-  double2* buf = smem + (size_t)pl * A.M;
-  const int k = A.k, n = A.n, M = A.M;
+  double2* buf = smem + (size_t)pl * A.buf;
+  const int k = A.k, n = A.n, Nc = A.Nc;
   const int ns = C / 2;
   const int mu = valid ? p / ns : 0;
   const int s = valid ? p % ns : 0;
   const int mE = 2 * mu, mO = 2 * mu + 1;
   const bool hasO = mO < k;
 
-  // 1. packed extension g_t = G_E(t) + G_O(t) (t < k);  G_E(n-1-t) - G_O(n-1-t) (t >= k)
-  for (int t = lt; t < M; t += sh.Tp) {
+  // packed extension g_t = G_E(t) + G_O(t) (t < k);  G_E(n-1-t) - G_O(n-1-t) (t >= k)
+  for (int t = lt; t < n; t += A.T) {
     double2 g = make_double2(0.0, 0.0);
-    if (valid && t < n) {
+    if (valid) {
       const int tt = (t < k) ? t : n - 1 - t;
       const double sg = (t < k) ? 1.0 : -1.0;
       const double* rE = GT + ((size_t)tt * k + mE) * C + 2 * s;
@@ -150,75 +174,73 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
         g.x += sg * rO[0];
         g.y += sg * rO[1];
       }
-      g = cmul(g, A.chirp[t]);
     }
     buf[t] = g;
   }
   __syncthreads();
-  // 2. D_j = sum_t g_t e^{-2 pi i j t/n} (Bluestein)
-  convolve(buf, A, A.bhat, lt, sh.Tp);
+  dft_odd<false, VPT>(buf, A, lt);
 
-  // 3. u_j = e^{-i pi j/n} D_j for |j| <= k-1, placed at j mod M (the 1/n^2 is in what)
-  constexpr int MAXV = 8;    // (2k-1)/Tp <= 8 for every FFT shape (M >= 4k-3, Tp = M/16)
+  // u_j = e^{-i pi j/n} D_j, kept in registers (index idx = j + k - 1, idx = lt + i*T)
+  constexpr int MAXV = VPT;  // (2k-1)/T <= VPT since T >= n/VPT
   double2 keep[MAXV];
   const int nj = 2 * k - 1;
 #pragma unroll
   for (int i = 0; i < MAXV; ++i) {
-    const int idx = lt + i * sh.Tp;
+    const int idx = lt + i * A.T;
     if (idx < nj) {
       const int j = idx - (k - 1);
-      const int jj = j < 0 ? j + n : j;
-      keep[i] = cmul(A.hphase[idx], cmul(A.chirp[jj], buf[jj]));
+      keep[i] = cmul(A.hphase[idx], buf[j < 0 ? j + n : j]);
+    }
+  }
+  // correlation, one parity class at a time: U_a = u_{2a+P}, I_{2b+P} = (U * Kt_P)(-b)
+#pragma unroll
+  for (int P = 0; P < 2; ++P) {
+    __syncthreads();
+    for (int q = lt; q < Nc; q += A.T) buf[q] = make_double2(0.0, 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * A.T;
+      if (idx < nj) {
+        const int j = idx - (k - 1);
+        if (((j - P) & 1) == 0) buf[((j - P) / 2) & (Nc - 1)] = keep[i];
+      }
+    }
+    __syncthreads();
+    fft_pow2<false, VPT>(buf, Nc, A.logNc, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logNc);
+    const double2* kh = P == 0 ? A.khat0 : A.khat1;
+    for (int q = lt; q < Nc; q += A.T) buf[q] = cmul(buf[q], kh[q]);
+    __syncthreads();
+    fft_pow2<true, VPT>(buf, Nc, A.logNc, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logNc);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * A.T;
+      if (idx < nj) {
+        const int jp = idx - (k - 1);
+        if (((jp - P) & 1) == 0) keep[i] = cmul(A.hphase[idx], buf[(-(jp - P) / 2) & (Nc - 1)]);
+      }
     }
   }
   __syncthreads();
-  for (int q = lt; q < M; q += sh.Tp) buf[q] = make_double2(0.0, 0.0);
-  __syncthreads();
+  // v_j' at index j' mod n, then H = DFT_n(v)
 #pragma unroll
   for (int i = 0; i < MAXV; ++i) {
-    const int idx = lt + i * sh.Tp;
-    if (idx < nj) {
-      const int j = idx - (k - 1);
-      buf[j < 0 ? j + M : j] = keep[i];
-    }
-  }
-  __syncthreads();
-  // 4. correlation with the even weight w_e(p) = 2/(1-p^2), p even
-  convolve(buf, A, A.what, lt, sh.Tp);
-
-  // 5. v_j' = e^{-i pi j'/n} I_j' with I_j' at index -j' mod M; place at j' mod n (times chirp)
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    const int idx = lt + i * sh.Tp;
+    const int idx = lt + i * A.T;
     if (idx < nj) {
       const int jp = idx - (k - 1);
-      const int src = jp > 0 ? M - jp : -jp;
-      keep[i] = cmul(A.hphase[idx], buf[src]);
+      buf[jp < 0 ? jp + n : jp] = keep[i];
     }
   }
   __syncthreads();
-  for (int q = lt; q < M; q += sh.Tp) buf[q] = make_double2(0.0, 0.0);
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    const int idx = lt + i * sh.Tp;
-    if (idx < nj) {
-      const int jp = idx - (k - 1);
-      const int tp = jp < 0 ? jp + n : jp;
-      buf[tp] = cmul(keep[i], A.chirp[tp]);
-    }
-  }
-  __syncthreads();
-  // 6. H_t = sum_j' v_j' e^{-2 pi i j' t / n} (Bluestein)
-  convolve(buf, A, A.bhat, lt, sh.Tp);
+  dft_odd<false, VPT>(buf, A, lt);
 
-  // 7. fold onto t < k and separate the even and odd m
+  // fold onto t < k and separate the even and odd m
   if (valid) {
-    for (int t = lt; t < k; t += sh.Tp) {
-      const double2 h1 = cmul(A.chirp[t], buf[t]);
+    for (int t = lt; t < k; t += A.T) {
+      const double2 h1 = buf[t];
       double2 he = h1, ho = make_double2(0.0, 0.0);
       if (t < k - 1) {
-        const double2 h2 = cmul(A.chirp[n - 1 - t], buf[n - 1 - t]);
+        const double2 h2 = buf[n - 1 - t];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
       }
@@ -237,16 +259,16 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
 // ------------------------------------------------------------------------------------------
 // phi stage, inverse.  Problem = (ring t, map pair) / (ring t, map).  Input FT[(t*k + m)*C + c].
 // ------------------------------------------------------------------------------------------
-template <int REAL>
-__global__ __launch_bounds__(512) void k_phi_inverse(FftArgs A, const double* __restrict__ FT, double* __restrict__ f,
-                              long long map_stride, int C, int nb, int nprob) {
+template <int REAL, int VPT>
+__global__ __launch_bounds__(512) void k_phi_inverse(FftArgs A, const double* __restrict__ FT,
+                                                     double* __restrict__ f, long long map_stride,
+                                                     int C, int nb, int nprob) {
   extern __shared__ double2 smem[];
-  const FftShape sh = FftShape::of(A.M);
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int pl = threadIdx.x / sh.Tp, lt = threadIdx.x % sh.Tp;
-  const int p = blk * sh.P + pl;
+  const int pl = threadIdx.x / A.T, lt = threadIdx.x % A.T;
+  const int p = blk * A.P + pl;
   const bool valid = p < nprob;
-  double2* buf = smem + (size_t)pl * A.M;
+  double2* buf = smem + (size_t)pl * A.buf;
   const int k = A.k, n = A.n;
   const int nunits = REAL ? (nb + 1) / 2 : nb;
   const int t = valid ? p / nunits : 0;
@@ -254,10 +276,10 @@ __global__ __launch_bounds__(512) void k_phi_inverse(FftArgs A, const double* __
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  // spectrum Z_m at index m mod n, times conj(chirp) for the +1 sign Bluestein
-  for (int q = lt; q < A.M; q += sh.Tp) {
+  // spectrum Z_m at index m mod n
+  for (int q = lt; q < n; q += A.T) {
     double2 z = make_double2(0.0, 0.0);
-    if (valid && q < n) {
+    if (valid) {
       const bool neg = q >= k;              // q = n - m  <->  m = -(n - q)
       const int m = neg ? n - q : q;
       const double* row = FT + ((size_t)t * k + m) * C;
@@ -272,25 +294,15 @@ __global__ __launch_bounds__(512) void k_phi_inverse(FftArgs A, const double* __
       } else {
         z = neg ? make_double2(row[4 * ma + 2], row[4 * ma + 3]) : make_double2(row[4 * ma], row[4 * ma + 1]);
       }
-      z = cmul(z, conjd(A.chirp[q]));
     }
     buf[q] = z;
   }
   __syncthreads();
-  // +1-sign Bluestein: conj of the -1 kernel, i.e. FFT with conj(bhat) applied to conj data is
-  // avoided by using the identity sum_q z_q e^{+2 pi i pq/n} = conj(sum_q conj(z_q) e^{-...}).
-  // Here: buf holds z_q * conj(c_q); convolve with conj(b) via conj(bhat[-j]).
-  fft_pow2<false>(buf, A.M, A.logM, lt, sh.Tp, A.tw_lo, A.tw_hi, A.loglo);
-  for (int q = lt; q < A.M; q += sh.Tp) {
-    const int qn = q == 0 ? 0 : A.M - q;
-    buf[q] = cmul(buf[q], conjd(A.bhat[qn]));
-  }
-  __syncthreads();
-  fft_pow2<true>(buf, A.M, A.logM, lt, sh.Tp, A.tw_lo, A.tw_hi, A.loglo);
+  dft_odd<true, VPT>(buf, A, lt);
 
   if (valid) {
-    for (int q = lt; q < n; q += sh.Tp) {
-      const double2 v = cmul(conjd(A.chirp[q]), buf[q]);
+    for (int q = lt; q < n; q += A.T) {
+      const double2 v = buf[q];
       if (REAL) {
         f[(size_t)ma * map_stride + (size_t)t * n + q] = v.x;
         if (hasb) f[(size_t)(ma + 1) * map_stride + (size_t)t * n + q] = v.y;
@@ -303,9 +315,52 @@ __global__ __launch_bounds__(512) void k_phi_inverse(FftArgs A, const double* __
 }
 
 // ------------------------------------------------------------------------------------------
+// Launch shapes: a problem gets T threads (T >= every transform length / VPT with VPT = 8, or
+// 16 for the 8192-point Bluestein transforms of non-smooth n > 2048), a block holds P problems
+// within 512 threads and 64 KiB of LDS.
+static FftArgs fft_args(const ShtTables& T, bool theta) {
+  FftArgs a;
+  a.k = T.k;
+  a.n = T.n;
+  a.mixed = T.nrad > 0 ? 1 : 0;
+  a.nrad = T.nrad;
+  a.rad_code = 0;
+  for (int s = 0; s < T.nrad; ++s) a.rad_code |= (unsigned)T.rad[s] << (4 * s);
+  a.twn_lo = T.twn_lo;
+  a.twn_hi = T.twn_hi;
+  a.M = T.M;
+  a.logM = T.logM;
+  a.chirp = T.chirp;
+  a.bhat = T.bhat;
+  a.Nc = T.Nc;
+  a.logNc = T.logNc;
+  a.khat0 = T.khat0;
+  a.khat1 = T.khat1;
+  a.tw_lo = T.tw_lo;
+  a.tw_hi = T.tw_hi;
+  a.loglo = T.loglo;
+  a.logP = T.logP;
+  a.hphase = T.hphase;
+  int need = a.mixed ? a.n : a.M;          // LDS values of the odd-length DFT
+  if (theta && a.Nc > need) need = a.Nc;
+  const int vpt = need > 4096 ? 16 : 8;
+  int tn = (need + vpt - 1) / vpt;
+  int Tt = 1;
+  while (Tt < tn) Tt <<= 1;
+  a.T = Tt;
+  a.buf = need;
+  int P = 1;
+  if (Tt < 512) {
+    P = 512 / Tt;
+    const int bylds = 4096 / (need > 0 ? need : 1);
+    if (bylds < P) P = bylds > 0 ? bylds : 1;
+  }
+  a.P = P;
+  return a;
+}
+
 template <typename K>
 static hipError_t prep(K kernel, size_t lds) {
-  static_assert(sizeof(K) > 0, "");
   if (lds > 65536) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -313,56 +368,66 @@ static hipError_t prep(K kernel, size_t lds) {
   return hipSuccess;
 }
 
+template <int REAL, int VPT>
+static hipError_t phi_fwd_v(const FftArgs& A, const void* f, int64_t map_stride, double* GT, const Batch& b,
+                            int nprob, hipStream_t s) {
+  const int nblk = (nprob + A.P - 1) / A.P;
+  const size_t lds = (size_t)A.P * A.buf * sizeof(double2);
+  hipError_t e;
+  if ((e = prep(k_phi_forward<REAL, VPT>, lds)) != hipSuccess) return e;
+  k_phi_forward<REAL, VPT><<<nblk, A.P * A.T, lds, s>>>(A, (const double*)f, map_stride, GT, b.C, b.nb,
+                                                         b.used, nprob);
+  return hipGetLastError();
+}
+
 hipError_t launch_phi_forward(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
                               double* GT, hipStream_t s) {
-  const FftArgs A = fft_args(T);
-  const FftShape sh = FftShape::of(T.M);
+  const FftArgs A = fft_args(T, false);
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = T.k * nunits;
-  const int nblk = (nprob + sh.P - 1) / sh.P;
-  const size_t lds = (size_t)sh.P * T.M * sizeof(double2);
+  const bool big = A.buf > 4096;
+  if (b.reality == S2LET_REAL)
+    return big ? phi_fwd_v<1, 16>(A, f, map_stride, GT, b, nprob, s) : phi_fwd_v<1, 8>(A, f, map_stride, GT, b, nprob, s);
+  return big ? phi_fwd_v<0, 16>(A, f, map_stride, GT, b, nprob, s) : phi_fwd_v<0, 8>(A, f, map_stride, GT, b, nprob, s);
+}
+
+template <int VPT>
+static hipError_t theta_v(const FftArgs& A, const double* GT, double* HM, const Batch& b, int nprob,
+                          hipStream_t s) {
+  const int nblk = (nprob + A.P - 1) / A.P;
+  const size_t lds = (size_t)A.P * A.buf * sizeof(double2);
   hipError_t e;
-  if (b.reality == S2LET_REAL) {
-    if ((e = prep(k_phi_forward<1>, lds)) != hipSuccess) return e;
-    k_phi_forward<1><<<nblk, sh.P * sh.Tp, lds, s>>>(A, (const double*)f, map_stride, GT, b.C, b.nb,
-                                                    b.used, nprob);
-  } else {
-    if ((e = prep(k_phi_forward<0>, lds)) != hipSuccess) return e;
-    k_phi_forward<0><<<nblk, sh.P * sh.Tp, lds, s>>>(A, (const double*)f, map_stride, GT, b.C, b.nb,
-                                                    b.used, nprob);
-  }
+  if ((e = prep(k_theta<VPT>, lds)) != hipSuccess) return e;
+  k_theta<VPT><<<nblk, A.P * A.T, lds, s>>>(A, GT, HM, b.C, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_theta(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s) {
-  const FftArgs A = fft_args(T);
-  const FftShape sh = FftShape::of(T.M);
+  const FftArgs A = fft_args(T, true);
   const int nprob = ((T.k + 1) / 2) * (b.C / 2);
-  const int nblk = (nprob + sh.P - 1) / sh.P;
-  const size_t lds = (size_t)sh.P * T.M * sizeof(double2);
+  return A.buf > 4096 ? theta_v<16>(A, GT, HM, b, nprob, s) : theta_v<8>(A, GT, HM, b, nprob, s);
+}
+
+template <int REAL, int VPT>
+static hipError_t phi_inv_v(const FftArgs& A, const double* FT, void* f, int64_t map_stride, const Batch& b,
+                            int nprob, hipStream_t s) {
+  const int nblk = (nprob + A.P - 1) / A.P;
+  const size_t lds = (size_t)A.P * A.buf * sizeof(double2);
   hipError_t e;
-  if ((e = prep(k_theta, lds)) != hipSuccess) return e;
-  k_theta<<<nblk, sh.P * sh.Tp, lds, s>>>(A, GT, HM, b.C, nprob);
+  if ((e = prep(k_phi_inverse<REAL, VPT>, lds)) != hipSuccess) return e;
+  k_phi_inverse<REAL, VPT><<<nblk, A.P * A.T, lds, s>>>(A, FT, (double*)f, map_stride, b.C, b.nb, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
                               int64_t map_stride, hipStream_t s) {
-  const FftArgs A = fft_args(T);
-  const FftShape sh = FftShape::of(T.M);
+  const FftArgs A = fft_args(T, false);
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = T.k * nunits;
-  const int nblk = (nprob + sh.P - 1) / sh.P;
-  const size_t lds = (size_t)sh.P * T.M * sizeof(double2);
-  hipError_t e;
-  if (b.reality == S2LET_REAL) {
-    if ((e = prep(k_phi_inverse<1>, lds)) != hipSuccess) return e;
-    k_phi_inverse<1><<<nblk, sh.P * sh.Tp, lds, s>>>(A, FT, (double*)f, map_stride, b.C, b.nb, nprob);
-  } else {
-    if ((e = prep(k_phi_inverse<0>, lds)) != hipSuccess) return e;
-    k_phi_inverse<0><<<nblk, sh.P * sh.Tp, lds, s>>>(A, FT, (double*)f, map_stride, b.C, b.nb, nprob);
-  }
-  return hipGetLastError();
+  const bool big = A.buf > 4096;
+  if (b.reality == S2LET_REAL)
+    return big ? phi_inv_v<1, 16>(A, FT, f, map_stride, b, nprob, s) : phi_inv_v<1, 8>(A, FT, f, map_stride, b, nprob, s);
+  return big ? phi_inv_v<0, 16>(A, FT, f, map_stride, b, nprob, s) : phi_inv_v<0, 8>(A, FT, f, map_stride, b, nprob, s);
 }
 
 }  // namespace s2let

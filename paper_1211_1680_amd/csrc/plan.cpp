@@ -60,43 +60,84 @@ static std::vector<double2> to_d2(const std::vector<cLD>& v) {
   return o;
 }
 
+// n = product of odd radices <= 13 (largest first), or false.
+static bool factor_odd(int n, int* rad, int* nrad) {
+  static const int cand[] = {13, 11, 9, 7, 5, 3};
+  int cnt = 0;
+  for (int r : cand) {
+    while (n % r == 0 && n > 1) {
+      if (cnt == 8) return false;
+      rad[cnt++] = r;
+      n /= r;
+    }
+  }
+  *nrad = cnt;
+  return n == 1;
+}
+
+static std::vector<cLD> roots_two_level(long long N, long long base, int count) {
+  std::vector<cLD> v(count > 0 ? count : 1);
+  for (int p = 0; p < count; ++p) {
+    const long long e = ((long long)p * base) % N;
+    const LD ang = -2.0L * PI_L * (LD)e / (LD)N;
+    v[p] = cLD(cosl(ang), sinl(ang));
+  }
+  return v;
+}
+
 hipError_t build_sht_tables(int k, ShtTables* T) {
   const int n = 2 * k - 1;
-  const int M = next_pow2(4 * k - 3);
   T->k = k;
   T->n = n;
-  T->M = M;
-  T->logM = ilog2(M);
-  T->loglo = (T->logM + 1) / 2;
+  int rad[8], nrad = 0;
+  const bool mixed = n > 1 && factor_odd(n, rad, &nrad);
+  T->nrad = mixed ? nrad : 0;
+  for (int s = 0; s < 8; ++s) T->rad[s] = (mixed && s < nrad) ? rad[s] : 0;
+  T->M = mixed ? 0 : next_pow2(2 * n - 1);
+  T->logM = mixed ? 0 : ilog2(T->M);
+  T->Nc = next_pow2(2 * k - 1);
+  T->logNc = ilog2(T->Nc);
+  const int P = std::max(T->M, T->Nc);
+  T->logP = ilog2(P);
+  T->loglo = (T->logP + 1) / 2;
+  hipError_t e;
 
-  std::vector<cLD> chirp(n);
-  for (int q = 0; q < n; ++q) chirp[q] = chirp_value(q, n);
-
-  // Bluestein kernel b[q] = conj(c_q), |q| <= n-1, wrapped modulo M; stored as FFT_M(b) / M.
-  std::vector<cLD> b(M, cLD(0, 0));
-  for (int q = -(n - 1); q <= n - 1; ++q) b[((q % M) + M) % M] = std::conj(chirp[q < 0 ? -q : q]);
-  host_fft(b);
-  for (auto& v : b) v /= (LD)M;
-
-  // Even part of the theta weight, w_e(p) = int_0^pi cos(p t) sin(t) dt = 2/(1-p^2) for even p,
-  // |p| <= 2k-2, wrapped modulo M; stored as FFT_M(w_e) / (M n^2).
-  std::vector<cLD> w(M, cLD(0, 0));
-  for (int p = -(2 * k - 2); p <= 2 * k - 2; p += 2) {
-    const LD pp = (LD)p;
-    w[((p % M) + M) % M] = cLD(2.0L / (1.0L - pp * pp), 0);
+  // W_n two-level table (64-entry low part)
+  {
+    const int nhi = (n + 63) / 64;
+    if ((e = upload(&T->twn_lo, to_d2(roots_two_level(n, 1, 64)))) != hipSuccess) return e;
+    if ((e = upload(&T->twn_hi, to_d2(roots_two_level(n, 64, nhi)))) != hipSuccess) return e;
   }
-  host_fft(w);
-  for (auto& v : w) v /= (LD)M * (LD)n * (LD)n;
-
-  const int nlo = 1 << T->loglo, nhi = M / nlo;
-  std::vector<cLD> tlo(nlo), thi(nhi > 0 ? nhi : 1);
-  for (int p = 0; p < nlo; ++p) {
-    const LD ang = -2.0L * PI_L * (LD)p / (LD)M;
-    tlo[p] = cLD(cosl(ang), sinl(ang));
+  // Bluestein tables
+  if (!mixed) {
+    const int M = T->M;
+    std::vector<cLD> chirp(n);
+    for (int q = 0; q < n; ++q) chirp[q] = chirp_value(q, n);
+    std::vector<cLD> b(M, cLD(0, 0));
+    for (int q = -(n - 1); q <= n - 1; ++q) b[((q % M) + M) % M] = std::conj(chirp[q < 0 ? -q : q]);
+    host_fft(b);
+    for (auto& v : b) v /= (LD)M;
+    if ((e = upload(&T->chirp, to_d2(chirp))) != hipSuccess) return e;
+    if ((e = upload(&T->bhat, to_d2(b))) != hipSuccess) return e;
   }
-  for (int p = 0; p < nhi; ++p) {
-    const LD ang = -2.0L * PI_L * (LD)((long long)p * nlo) / (LD)M;
-    thi[p] = cLD(cosl(ang), sinl(ang));
+  // correlation kernels of the two frequency-parity classes:
+  //   Kt_Q(c) = w_e(2Q - 2c) for c in [Q-(k-1), Q+(k-1)], wrapped mod Nc; stored as FFT / (Nc n^2)
+  for (int Q = 0; Q < 2; ++Q) {
+    const int Nc = T->Nc;
+    std::vector<cLD> kt(Nc, cLD(0, 0));
+    for (int c = Q - (k - 1); c <= Q + (k - 1); ++c) {
+      const LD pp = (LD)(2 * Q - 2 * c);
+      kt[((c % Nc) + Nc) % Nc] = cLD(2.0L / (1.0L - pp * pp), 0);
+    }
+    host_fft(kt);
+    for (auto& v : kt) v /= (LD)Nc * (LD)n * (LD)n;
+    if ((e = upload(Q == 0 ? &T->khat0 : &T->khat1, to_d2(kt))) != hipSuccess) return e;
+  }
+  // W_P two-level table
+  {
+    const int nlo = 1 << T->loglo, nhi = P / nlo;
+    if ((e = upload(&T->tw_lo, to_d2(roots_two_level(P, 1, nlo)))) != hipSuccess) return e;
+    if ((e = upload(&T->tw_hi, to_d2(roots_two_level(P, nlo, nhi)))) != hipSuccess) return e;
   }
 
   std::vector<double> xt(k), st(k), ut(k), sx(k);
@@ -121,12 +162,6 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
     hph[j + k - 1] = cLD(cosl(ang), sinl(ang));
   }
 
-  hipError_t e;
-  if ((e = upload(&T->chirp, to_d2(chirp))) != hipSuccess) return e;
-  if ((e = upload(&T->bhat, to_d2(b))) != hipSuccess) return e;
-  if ((e = upload(&T->what, to_d2(w))) != hipSuccess) return e;
-  if ((e = upload(&T->tw_lo, to_d2(tlo))) != hipSuccess) return e;
-  if ((e = upload(&T->tw_hi, to_d2(thi))) != hipSuccess) return e;
   if ((e = upload(&T->xt, xt)) != hipSuccess) return e;
   if ((e = upload(&T->st, st)) != hipSuccess) return e;
   if ((e = upload(&T->ut, ut)) != hipSuccess) return e;
@@ -136,9 +171,12 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
 }
 
 void free_sht_tables(ShtTables* T) {
+  hipFree(T->twn_lo);
+  hipFree(T->twn_hi);
   hipFree(T->chirp);
   hipFree(T->bhat);
-  hipFree(T->what);
+  hipFree(T->khat0);
+  hipFree(T->khat1);
   hipFree(T->tw_lo);
   hipFree(T->tw_hi);
   hipFree(T->xt);

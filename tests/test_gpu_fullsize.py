@@ -1,0 +1,95 @@
+"""Parity at the full benchmark size, in the launch configuration bench.py times: wavelet
+analysis + synthesis of 16 real maps at L = 2048, B = 2, J_min = 3, multiresolution, FP64.
+
+The oracle synthesises two of the maps (seeded, C_l = 1/(l(l+1))); the batch is eight copies of
+the pair.  Checked: every output map on rings the oracle evaluates one by one (poles, equator,
+interior), the small scales and the scaling map in full, the reconstruction in full, the forward
+transform against the seeded coefficients, and that copies in the batch agree."""
+import numpy as np
+import pytest
+
+import oracle
+import s2let_inputs as si
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+s2 = pytest.importorskip("paper_1211_1680_amd")
+
+TOL = 1e-10
+L, B, J_MIN, NMAPS = 2048, 2, 3, 16
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _rel(got, ref, floor):
+    den = max(float(np.max(np.abs(ref))), floor)
+    r = float(np.max(np.abs(np.asarray(got) - np.asarray(ref)))) / den
+    print("  rel err %.3e" % r, flush=True)
+    return r
+
+
+@pytest.fixture(scope="module")
+def data(dev):
+    print("full size: oracle synthesis of 2 maps at L=%d" % L, flush=True)
+    flm = si.random_flm(L, 2, reality=True, seed=3)
+    f2 = oracle.inverse_sht(flm, L, reality=True)
+    f = np.concatenate([f2] * (NMAPS // 2))
+    fd = torch.from_numpy(f).to(dev)
+    print("full size: GPU analysis + synthesis, 16 maps", flush=True)
+    f_wav, f_scal = s2.analysis(fd, L, B, J_MIN, True, s2.REAL)
+    rec = s2.synthesis(f_wav, f_scal, L, B, J_MIN, True, s2.REAL)
+    flm_gpu = s2.mw_forward(fd, L, s2.REAL)
+    torch.cuda.synchronize()
+    return dict(flm=flm, f=f, fd=fd, f_wav=f_wav.cpu().numpy(), f_scal=f_scal.cpu().numpy(),
+                rec=rec.cpu().numpy(), flm_gpu=flm_gpu.cpu().numpy())
+
+
+def test_forward_full_size(data):
+    got = data["flm_gpu"]
+    for i in range(NMAPS):
+        assert _rel(got[i], data["flm"][i % 2], 0.0) < TOL
+
+
+def test_batch_copies_agree(data):
+    w, p, r = data["f_wav"], data["f_scal"], data["rec"]
+    for i in range(2, NMAPS):
+        assert np.array_equal(w[i], w[i % 2])
+        assert np.array_equal(p[i], p[i % 2])
+        assert np.array_equal(r[i], r[i % 2])
+
+
+def test_reconstruction_full_size(data):
+    floor = 1e-6 * float(np.max(np.abs(data["f"])))
+    assert _rel(data["rec"], data["f"], floor) < TOL
+
+
+def test_scales_on_oracle_rings(data):
+    flm = data["flm"]
+    kappa, eta = oracle.tiling(L, B, J_MIN)
+    ell = np.repeat(np.arange(L), 2 * np.arange(L) + 1)
+    floor = 1e-6 * float(np.max(np.abs(data["f"])))
+    off = 0
+    for j in range(J_MIN, oracle.j_max(L, B) + 1):
+        k = oracle.bandlimit_wav(j, L, B, True)
+        wlm = (flm * kappa[j - J_MIN][ell][None, :])[:, :k * k]
+        got = data["f_wav"][:2, off:off + k * (2 * k - 1)].reshape(2, k, 2 * k - 1)
+        if k <= 512:
+            ref = oracle.inverse_sht(wlm, k, reality=True)
+            print("scale j=%d k=%d (all rings)" % (j, k), flush=True)
+            assert _rel(got, ref, floor) < TOL
+        else:
+            rings = sorted({0, 1, 2, k // 3, k // 2, k // 2 + 1, k - 3, k - 2, k - 1})
+            ref = oracle.inverse_sht_rings(wlm, k, rings, reality=True)
+            print("scale j=%d k=%d (rings %s)" % (j, k, rings), flush=True)
+            assert _rel(got[:, rings, :], ref, floor) < TOL
+        off += k * (2 * k - 1)
+    kP = oracle.bandlimit_scal(J_MIN, L, B, True)
+    slm = (flm * eta[ell][None, :])[:, :kP * kP]
+    ref = oracle.inverse_sht(slm, kP, reality=True)
+    print("scaling map k=%d" % kP, flush=True)
+    assert _rel(data["f_scal"][:2].reshape(2, kP, 2 * kP - 1), ref, floor) < TOL

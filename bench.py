@@ -147,6 +147,17 @@ def main():
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
                 "launches": st["launches"], "avg_launch_ms": st["ms"] / max(st["launches"], 1)}
     stage_ms = {n: round(v["ms"] / args.steps, 3) for n, v in stages.items()}
+    stage_rate = {}
+    for n, v in stages.items():
+        if v["ms"] <= 0:
+            continue
+        if n.startswith("legendre"):
+            stage_rate[n] = "%.1f TFLOP/s (%.0f%% of FP64 peak)" % (
+                v["flops_retained"] / (v["ms"] * 1e-3) / 1e12,
+                100 * v["flops_retained"] / (v["ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS)
+        else:
+            stage_rate[n] = "%.0f GB/s (%.0f%% of HBM peak)" % (
+                v["bytes"] / (v["ms"] * 1e-3) / 1e9, 100 * v["bytes"] / (v["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS)
 
     out = {
         "metric": METRIC,
@@ -167,6 +178,7 @@ def main():
                    "precision": args.precision},
         "roofline": roof,
         "stage_ms_per_step": stage_ms,
+        "stage_rate": stage_rate,
         "round_trip_rel_err": err,
     }
     if not args.no_cpu_baseline:

@@ -126,24 +126,30 @@ struct Workspace {
   double* S;
 };
 
-// Workspace for transforms up to band-limit L with C columns.
+// Workspace for transforms up to band-limit L with C columns: GT and HM (k x k x C), R (the
+// partial sums of the forward Legendre step, legendre_forward_groups(L) triangles) and S.
 size_t ws_bytes_for(int L, int C, bool wavelet) {
   const size_t sq = align_up(sizeof(double) * (size_t)L * L * C);
   const size_t tri = align_up(sizeof(double) * (size_t)tri_rows(L) * C);
-  return wavelet ? 2 * sq + 2 * tri : 2 * sq + tri;
+  const size_t rp = align_up(sizeof(double) * (size_t)tri_rows(L) * C * legendre_forward_groups(L));
+  return 2 * sq + rp + (wavelet ? tri : 0);
 }
 
 Workspace carve(void* ws, int L, int C, bool wavelet) {
   Workspace w;
   char* p = (char*)ws;
   const size_t sq = align_up(sizeof(double) * (size_t)L * L * C);
-  const size_t tri = align_up(sizeof(double) * (size_t)tri_rows(L) * C);
+  const size_t rp = align_up(sizeof(double) * (size_t)tri_rows(L) * C * legendre_forward_groups(L));
   w.GT = (double*)p;
   w.HM = (double*)(p + sq);
   w.R = (double*)(p + 2 * sq);
-  w.S = wavelet ? (double*)(p + 2 * sq + tri) : w.R;
+  w.S = wavelet ? (double*)(p + 2 * sq + rp) : w.R;
   return w;
 }
+
+// partial-sum layout of the forward Legendre step at band-limit k
+int nparts_of(int k) { return legendre_forward_groups(k); }
+long long pstride_of(int k, const Batch& b) { return (long long)tri_rows(k) * b.C; }
 
 int to_status(hipError_t e) { return e == hipSuccess ? S2LET_OK : S2LET_EHIP; }
 
@@ -227,7 +233,8 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     r->flops_full = r->triples * (r->rec_flops + r->col_flops);
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
-  if ((e = launch_legendre_forward(T, G, b, w.HM, w.R, precision, prof_counter(r), s)) != hipSuccess)
+  if ((e = launch_legendre_forward(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r),
+                                   s)) != hipSuccess)
     return to_status(e);
   prof_end(r, s);
   return S2LET_OK;
@@ -264,7 +271,7 @@ hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int 
     const double kk = std::min(ks, kd);
     r->bytes = 8.0 * b.used * (kk * (kk + 1) / 2.0 + (double)tri_rows(kd) * (accumulate ? 2.0 : 1.0));
   }
-  hipError_t e = launch_tile(G, b, src, ks, dst, kd, kern, accumulate, s);
+  hipError_t e = launch_tile(G, b, src, ks, nparts_of(ks), pstride_of(ks, b), dst, kd, kern, accumulate, s);
   prof_end(r, s);
   return e;
 }
@@ -373,7 +380,7 @@ S2LET_API int mw_forward(void* flm, const void* f, int L, int reality, int preci
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
     if ((st = forward_batch(*T, dc.leg, b, fin, msz, w, precision, s)) != S2LET_OK) return st;
     double2* out = (double2*)flm + (size_t)start * L * L;
-    hipError_t e = launch_pack_flm(dc.leg, b, L, w.R, out, s);
+    hipError_t e = launch_pack_flm(dc.leg, b, L, w.R, nparts_of(L), pstride_of(L, b), out, s);
     if (e != hipSuccess) return S2LET_EHIP;
   }
   return S2LET_OK;

@@ -82,9 +82,11 @@ hipError_t launch_theta(const ShtTables& T, const Batch& b, const double* GT, do
 // phi stage, inverse: FT[t][m][c] -> maps (ring stride n, map stride map_stride samples).
 hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
                               int64_t map_stride, hipStream_t s);
-// Legendre contraction, forward: HM[m][t][c] -> R[tri_off(k,m)+l-m][c] = sum_t z_lm(theta_t) H'
+// Legendre contraction, forward: HM[m][t][c] -> R[tri_off(k,m)+l-m][c] = sum_t z_lm(theta_t) H',
+// written as legendre_forward_groups(k) partial sums over theta ranges, part g at R + g*part_stride.
+int legendre_forward_groups(int k);
 hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const Batch& b,
-                                   const double* HM, double* R, int precision,
+                                   const double* HM, double* R, long long part_stride, int precision,
                                    unsigned long long* counter, hipStream_t s);
 // Legendre synthesis: S[tri_off(k,m)+l-m][c] (pre-scaled by d_lm) -> FT[t][m][c]
 hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const Batch& b,
@@ -93,12 +95,14 @@ hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const
 // flm (user layout) -> S (k-packed rows, scaled by d_lm, -m columns by (-1)^m).
 hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm,
                              double* S, hipStream_t s);
-// R (k-packed raw forward sums) -> flm (user layout): f_lm = d_lm R (and symmetry for real).
-hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, double2* flm,
-                           hipStream_t s);
-// Tiling: dst[tri_off(kd,m)+l-m][c] (=|+=) kern[l] * d_lm^2 * src[tri_off(ks,m)+l-m][c] for
-// l < min(ks, kd); rows with l >= ks of dst are zeroed when accumulate == 0.
-hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, double* dst,
-                       int kd, const double* kern, int accumulate, hipStream_t s);
+// R (k-packed raw forward sums, nparts partials) -> flm (user layout): f_lm = d_lm sum_g R_g
+// (and the symmetry for real maps).
+hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, int nparts,
+                           long long part_stride, double2* flm, hipStream_t s);
+// Tiling: dst[tri_off(kd,m)+l-m][c] (=|+=) kern[l] * d_lm^2 * sum_g src_g[tri_off(ks,m)+l-m][c]
+// for l < min(ks, kd); rows with l >= ks of dst are zeroed when accumulate == 0.
+hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, int nparts,
+                       long long part_stride, double* dst, int kd, const double* kern, int accumulate,
+                       hipStream_t s);
 
 }  // namespace s2let

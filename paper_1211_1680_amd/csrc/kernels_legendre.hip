@@ -67,6 +67,55 @@ __device__ __forceinline__ bool negligible(double z1, double z2, int e) {
   return a == 0.0 || e + exponent_of(a) < -1100;
 }
 
+// value of v in lane l (l uniform), through two scalar registers
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Recursion coefficients of one chunk of LC degrees starting at row i0 of column m (len rows
+// below the band-limit): lane j < LC holds alpha, lane LC + j holds beta, zero past the end
+// (alpha = beta = 0 keeps the state finite).  One vector load per lane replaces 2 LC scalar
+// loads whose latency would otherwise sit in every step of the recursion.
+template <int LC>
+__device__ __forceinline__ double chunk_coef(const double* __restrict__ am, const double* __restrict__ bm,
+                                             int i0, int len, int lane) {
+  const bool isb = lane >= LC;
+  const int i = i0 + (isb ? lane - LC : lane);
+  const double* p = isb ? bm : am;
+  return (lane < 2 * LC && i < len) ? p[i] : 0.0;
+}
+
+// One chunk of the difference recursion: degrees l0 .. l0 + LC - 1, z values (scaled by 2^e)
+// to zcol[j * ZS].  The state enters as (z_{l0-1}, E_{l0-1}).
+template <int LC, int ZS>
+__device__ __forceinline__ void recur_chunk(double cf, double u, double sg, double& z1, double& z2, int& e,
+                                            double* zcol) {
+#pragma unroll
+  for (int j = 0; j < LC; ++j) {
+    const double g = fma(readlane_d(cf, j), u, readlane_d(cf, LC + j));
+    z2 = sg * fma(g, z1, z2);
+    z1 = fma(sg, z1, z2);
+    zcol[j * ZS] = ldexp(z1, e);
+    if ((j & 7) == 7) renorm(z1, z2, e);
+  }
+}
+
+// Start of the recursion one degree early: z_{m-1} = 0 and E = s z_m, so that the first step
+// (alpha_m = 0, beta_m = -2 in the tables) yields z_m and E_m = z_m.
+__device__ __forceinline__ void recur_start(double cmm, double s, double sg, int m, double& z1, double& z2,
+                                            int& e) {
+  double zm = cmm * pow_scaled(s, m, &e);
+  if (e > 0) {
+    zm = ldexp(zm, e);
+    e = 0;
+  }
+  z1 = 0.0;
+  z2 = sg * zm;
+}
+
 // ------------------------------------------------------------------------------------------
 // Synthesis: one lane per theta_t, 4 waves per block; a block handles the m pair
 // (pair, k-1-pair) so every block does k+1 rows of work.  The coefficient rows S[l][0..C)
@@ -169,123 +218,107 @@ __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__
 // ------------------------------------------------------------------------------------------
 // Analysis: D[c][l] = sum_t H'[t][c] z_l(theta_t) on the FP64 matrix cores
 // (v_mfma_f64_16x16x4: A = 16 columns x 4 thetas, B = 4 thetas x 16 degrees).
-// Block = 8 waves, one m pair.  Wave w owns theta tiles w, w+8, ... of 64 thetas and keeps
-// their recursion state in registers; per chunk of 32 degrees it writes its tile of z values
-// to LDS, multiplies, and the eight partial sums are reduced through LDS.
+// Block = 8 waves = 512 thetas of one m pair; wave w owns 64 thetas: their recursion state and
+// their H' operands (64 thetas x C columns) stay in registers for the whole m.  Per chunk of
+// 32 degrees a wave writes its z values to a private LDS tile, multiplies, and the eight
+// partial sums are reduced through LDS.  Blocks covering different theta ranges (g) write
+// separate partial sums R[g]; the consumer of R adds them.
 // ------------------------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int FWD_NW = 8;       // waves per block
-constexpr int FWD_NTMAX = 4;    // theta tiles per wave: k <= 4 * 8 * 64 = 2048
 constexpr int FWD_LC = 32;      // degrees per chunk
-constexpr int FWD_ZS = 65;      // padded LDS row (doubles)
+constexpr int FWD_ZS = 66;      // LDS row stride (doubles): 2 x odd, conflict-free B reads
+constexpr int FWD_TB = FWD_NW * 64;   // thetas per block
+
+// orders this wave's LDS writes before its later reads (and the reverse) without a block barrier
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int C>
 __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__ HM, double* __restrict__ R,
+                                                      long long part_stride,
                                                       const double* __restrict__ alpha,
                                                       const double* __restrict__ beta,
                                                       const double* __restrict__ cm,
                                                       const double* __restrict__ ut,
                                                       const double* __restrict__ sx,
-                                                      const double* __restrict__ st, int k, int Lt,
+                                                      const double* __restrict__ st, int k, int Lt, int ng,
                                                       unsigned long long* __restrict__ counter) {
   constexpr int CT = C >= 16 ? C / 16 : 1;
   unsigned long long retained = 0;   // (l, theta) pairs multiplied by this wave
   __shared__ double Z[FWD_NW][FWD_LC][FWD_ZS];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int pair = blockIdx.x;
-  const int ntiles = (k + 63) / 64;
-  const int NT = (ntiles + FWD_NW - 1) / FWD_NW;
-  const int nm = (k - 1 - pair > pair) ? 2 : 1;
   const int li = lane & 15, lq = lane >> 4;
+  const int pair = blockIdx.x / ng;
+  const int grp = blockIdx.x % ng;
+  const int tile = grp * FWD_NW + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < k;
+  const bool tile_live = tile * 64 < k;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = valid ? sx[t] : 1.0;
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  double* __restrict__ Rg = R + (size_t)grp * part_stride;
 
   for (int im = 0; im < nm; ++im) {
     const int m = im == 0 ? pair : k - 1 - pair;
     const double* __restrict__ am = alpha + tri_off(Lt, m);
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Hm = HM + (size_t)m * k * C;
-    double z1[FWD_NTMAX], z2[FWD_NTMAX], us[FWD_NTMAX], sgs[FWD_NTMAX];
-    int ee[FWD_NTMAX];
+    // this wave's operands: a[kk][ct] = H'[tile*64 + 4 kk + lq][ct*16 + li]
+    double a[16][CT];
 #pragma unroll
-    for (int i = 0; i < FWD_NTMAX; ++i) {
-      z1[i] = 0.0;
-      z2[i] = 0.0;
-      us[i] = -1.0;
-      sgs[i] = 1.0;
-      ee[i] = 0;
-      if (i < NT) {
-        const int t = (w + FWD_NW * i) * 64 + lane;
-        if (t < k) {
-          int e;
-          z1[i] = cm[m] * pow_scaled(st[t], m, &e);
-          if (e > 0) {
-            z1[i] = ldexp(z1[i], e);
-            e = 0;
-          }
-          z2[i] = z1[i];   // E_m = z_m
-          ee[i] = e;
-          us[i] = ut[t];
-          sgs[i] = sx[t];
-        }
+    for (int kk = 0; kk < 16; ++kk) {
+      const int tg = tile * 64 + 4 * kk + lq;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = ct * 16 + li;
+        a[kk][ct] = (tg < k && c < C) ? Hm[(size_t)tg * C + c] : 0.0;
       }
     }
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cf_next = chunk_coef<FWD_LC>(am, bm, 0, k - m, lane);
 
     for (int l0 = m; l0 < k; l0 += FWD_LC) {
       v4d acc[2][CT];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < CT; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-
+        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = v4d{0.0, 0.0, 0.0, 0.0};
+      const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
+      // z values for degrees l0 .. l0+31 at this lane's theta (lanes past k hold finite values
+      // that meet zero operands)
+      const double cf = cf_next;
+      cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
+      recur_chunk<FWD_LC, FWD_ZS>(cf, u, sg, z1, z2, e, &Z[w][0][lane]);
+      if (!skip) {
+        wave_lds_sync();
+        const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
+        const int nt = (k - tile * 64) < 64 ? (k - tile * 64) : 64;
+        retained += (unsigned long long)nl * (unsigned long long)nt;
 #pragma unroll
-      for (int i = 0; i < FWD_NTMAX; ++i) {
-        if (i < NT) {
-          const int tile = w + FWD_NW * i;
-          // z values for degrees l0 .. l0+31 at this lane's theta
-          const bool skip = __all(negligible(z1[i], z2[i], ee[i]) || tile * 64 + lane >= k);
+        for (int kk = 0; kk < 16; ++kk) {
+          const int tl = 4 * kk + lq;
 #pragma unroll
-          for (int j = 0; j < FWD_LC; ++j) {
-            const int l = l0 + j;
-            double v = 0.0;
-            if (l < k) {
-              if (l > m) {
-                const double g = fma(am[l - m], us[i], bm[l - m]);
-                z2[i] = sgs[i] * fma(g, z1[i], z2[i]);
-                z1[i] = fma(sgs[i], z1[i], z2[i]);
-              }
-              v = ldexp(z1[i], ee[i]);
-            }
-            Z[w][j][lane] = v;
-            if ((j & 7) == 7) renorm(z1[i], z2[i], ee[i]);
+          for (int lt2 = 0; lt2 < 2; ++lt2) {
+            const double bv = Z[w][lt2 * 16 + li][tl];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              acc[lt2][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk][ct], bv, acc[lt2][ct], 0, 0, 0);
           }
-          __syncthreads();
-          if (!skip) {
-            const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
-            const int nt = (k - tile * 64) < 64 ? (k - tile * 64) : 64;
-            retained += (unsigned long long)nl * (unsigned long long)nt;
-#pragma unroll 4
-            for (int kk = 0; kk < 16; ++kk) {
-              const int tl = 4 * kk + lq;
-              const int tg = tile * 64 + tl;
-              double a[CT];
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct) {
-                const int c = ct * 16 + li;
-                a[ct] = (tg < k && c < C) ? Hm[(size_t)tg * C + c] : 0.0;
-              }
-#pragma unroll
-              for (int lt2 = 0; lt2 < 2; ++lt2) {
-                const double bv = Z[w][lt2 * 16 + li][tl];
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct)
-                  acc[lt2][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ct], bv, acc[lt2][ct], 0, 0, 0);
-              }
-            }
-          }
-          __syncthreads();
         }
       }
-      // reduce the waves' partial sums: red[w][l][c]
+      // reduce the waves' partial sums: red[w][l][c], row stride 2 x odd doubles so that the
+      // 16 degrees x 2 columns written by a half wave fall in different LDS banks
+      constexpr int RS = 2 * ((C / 2) | 1);
+      __syncthreads();
       double* red = &Z[0][0][0];
 #pragma unroll
       for (int lt2 = 0; lt2 < 2; ++lt2)
@@ -296,7 +329,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
             // result register v of lane l holds row (l / 16) + 4 v, column l % 16
             const int c = ct * 16 + lq + 4 * v;
             const int lloc = lt2 * 16 + li;
-            if (c < C) red[((size_t)w * FWD_LC + lloc) * C + c] = acc[lt2][ct][v];
+            if (c < C) red[((size_t)w * FWD_LC + lloc) * RS + c] = acc[lt2][ct][v];
           }
       __syncthreads();
       for (int idx = threadIdx.x; idx < FWD_LC * C; idx += FWD_NW * 64) {
@@ -305,8 +338,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
         if (l < k) {
           double sum = 0.0;
 #pragma unroll
-          for (int ww = 0; ww < FWD_NW; ++ww) sum += red[(ww * FWD_LC + lloc) * C + c];
-          R[(tri_off(k, m) + (l - m)) * C + c] = sum;
+          for (int ww = 0; ww < FWD_NW; ++ww) sum += red[(ww * FWD_LC + lloc) * RS + c];
+          Rg[(tri_off(k, m) + (l - m)) * C + c] = sum;
         }
       }
       __syncthreads();
@@ -316,24 +349,144 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
 }
 
 // ------------------------------------------------------------------------------------------
+// Synthesis on the matrix cores (C >= 16): D[t][c] = sum_l z_l(theta_t) S[l][c] with
+// v_mfma_f64_16x16x4 (A = 16 thetas x 4 degrees, B = 4 degrees x 16 columns).  Each wave owns
+// 64 thetas and streams every degree of its m pair; z values pass through a wave-private LDS
+// tile (16 degrees), the coefficient rows are vector loads issued before the recursion.
+// ------------------------------------------------------------------------------------------
+constexpr int INVM_LC = 16;     // degrees per chunk
+constexpr int INVM_ZS = 80;     // LDS row stride (doubles): = 16 mod 32, conflict-free A reads
+
+template <int C>
+__global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restrict__ S, double* __restrict__ FT,
+                                                           const double* __restrict__ alpha,
+                                                           const double* __restrict__ beta,
+                                                           const double* __restrict__ cm,
+                                                           const double* __restrict__ ut,
+                                                           const double* __restrict__ sx,
+                                                           const double* __restrict__ st, int k, int Lt,
+                                                           int ntb, unsigned long long* __restrict__ counter) {
+  constexpr int CT = C / 16;
+  __shared__ double Z[4][INVM_LC][INVM_ZS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int pair = blockIdx.x / ntb;
+  const int tile = (blockIdx.x % ntb) * 4 + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < k;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = valid ? sx[t] : 1.0;
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  unsigned long long retained = 0;
+
+  for (int im = 0; im < nm; ++im) {
+    const int m = im == 0 ? pair : k - 1 - pair;
+    const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
+    const double* __restrict__ Sm = S + tri_off(k, m) * C;
+    v4d acc[4][CT];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[g][ct] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cf_next = chunk_coef<INVM_LC>(am, bm, 0, k - m, lane);
+    // coefficient rows l0 + 4 sl + lq, columns ct*16 + li; the rows of the next chunk are
+    // requested while the current chunk is multiplied
+    double bn[INVM_LC / 4][CT];
+#pragma unroll
+    for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+      const int l = m + 4 * sl + lq;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+    }
+    for (int l0 = m; l0 < k; l0 += INVM_LC) {
+      const bool skip = __all(!valid || negligible(z1, z2, e));
+      double b[INVM_LC / 4][CT];
+#pragma unroll
+      for (int sl = 0; sl < INVM_LC / 4; ++sl)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) b[sl][ct] = bn[sl][ct];
+      if (l0 + INVM_LC < k) {
+#pragma unroll
+        for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+          const int l = l0 + INVM_LC + 4 * sl + lq;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+        }
+      }
+      const double cf = cf_next;
+      cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
+      // degrees past k meet zero coefficient rows; thetas past k are not stored
+      recur_chunk<INVM_LC, INVM_ZS>(cf, u, sg, z1, z2, e, &Z[w][0][lane]);
+      if (!skip) {
+        wave_lds_sync();
+        const int nl = (k - l0) < INVM_LC ? (k - l0) : INVM_LC;
+        retained += (unsigned long long)nl * (unsigned long long)(valid ? 1 : 0);
+#pragma unroll
+        for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const double av = Z[w][4 * sl + lq][16 * g + li];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+              acc[g][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[sl][ct], acc[g][ct], 0, 0, 0);
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    // result register v of lane l holds row (l / 16) + 4 v (theta), column l % 16
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int tt = tile * 64 + 16 * g + lq + 4 * v;
+        if (tt < k) {
+          double* out = FT + ((size_t)tt * k + m) * C;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) out[ct * 16 + li] = acc[g][ct][v];
+        }
+      }
+  }
+  if (counter != nullptr) {
+    // retained counts this lane's (l, theta) pairs
+    for (int off = 32; off > 0; off >>= 1) retained += __shfl_down(retained, off);
+    if (lane == 0 && retained > 0) atomicAdd(counter, retained);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 template <int C>
 static hipError_t inv_c(const ShtTables& T, const LegTables& G, const double* S, double* FT,
                         unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   const int ntb = (k + 255) / 256;
   const int npairs = (k + 1) / 2;
+  if (C >= 16) {
+    k_legendre_inv_mfma<(C >= 16 ? C : 16)><<<npairs * ntb, 256, 0, s>>>(
+        S, FT, G.alpha, G.beta, G.cm, T.ut, T.sx, T.st, k, G.Lt, ntb, counter);
+    return hipGetLastError();
+  }
   k_legendre_inv<C><<<npairs * ntb, 256, 0, s>>>(S, FT, G.alpha, G.beta, G.cm, T.ut, T.sx, T.st, k, G.Lt,
                                                  ntb, counter);
   return hipGetLastError();
 }
 
+int legendre_forward_groups(int k) { return (k + FWD_TB - 1) / FWD_TB; }
+
 template <int C>
 static hipError_t fwd_c(const ShtTables& T, const LegTables& G, const double* HM, double* R,
-                        unsigned long long* counter, hipStream_t s) {
+                        long long part_stride, unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   const int npairs = (k + 1) / 2;
-  k_legendre_fwd<C><<<npairs, FWD_NW * 64, 0, s>>>(HM, R, G.alpha, G.beta, G.cm, T.ut, T.sx, T.st, k, G.Lt,
-                                                   counter);
+  const int ng = legendre_forward_groups(k);
+  k_legendre_fwd<C><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut,
+                                                        T.sx, T.st, k, G.Lt, ng, counter);
   return hipGetLastError();
 }
 
@@ -352,16 +505,15 @@ hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const
 }
 
 hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const Batch& b,
-                                   const double* HM, double* R, int precision,
+                                   const double* HM, double* R, long long part_stride, int precision,
                                    unsigned long long* counter, hipStream_t s) {
   (void)precision;
-  if (T.k > FWD_NTMAX * FWD_NW * 64) return hipErrorInvalidValue;
   switch (b.C) {
-    case 2: return fwd_c<2>(T, G, HM, R, counter, s);
-    case 4: return fwd_c<4>(T, G, HM, R, counter, s);
-    case 8: return fwd_c<8>(T, G, HM, R, counter, s);
-    case 16: return fwd_c<16>(T, G, HM, R, counter, s);
-    case 32: return fwd_c<32>(T, G, HM, R, counter, s);
+    case 2: return fwd_c<2>(T, G, HM, R, part_stride, counter, s);
+    case 4: return fwd_c<4>(T, G, HM, R, part_stride, counter, s);
+    case 8: return fwd_c<8>(T, G, HM, R, part_stride, counter, s);
+    case 16: return fwd_c<16>(T, G, HM, R, part_stride, counter, s);
+    case 32: return fwd_c<32>(T, G, HM, R, part_stride, counter, s);
   }
   return hipErrorInvalidValue;
 }

@@ -43,7 +43,7 @@ __global__ void k_unpack(const double2* __restrict__ flm, double* __restrict__ S
 }
 
 // One thread per (m, l, map).
-__global__ void k_pack(const double* __restrict__ R, double2* __restrict__ flm,
+__global__ void k_pack(const double* __restrict__ R, int nparts, long long pstride, double2* __restrict__ flm,
                        const double* __restrict__ dfac, int k, int Lt, int C, int nb, int real,
                        long long map_stride) {
   const int m = blockIdx.y;
@@ -56,21 +56,32 @@ __global__ void k_pack(const double* __restrict__ R, double2* __restrict__ flm,
   const double* row = R + (tri_off(k, m) + r) * C;
   double2* out = flm + (size_t)a * map_stride;
   const double sg = (m & 1) ? -1.0 : 1.0;
+  const int c0 = real ? 2 * a : 4 * a;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = 0; g < nparts; ++g) {
+    const double* rg = row + (size_t)g * pstride;
+    v[0] += rg[c0];
+    v[1] += rg[c0 + 1];
+    if (!real) {
+      v[2] += rg[c0 + 2];
+      v[3] += rg[c0 + 3];
+    }
+  }
   if (real) {
-    const double2 f = make_double2(d * row[2 * a], d * row[2 * a + 1]);
+    const double2 f = make_double2(d * v[0], d * v[1]);
     out[(size_t)l * l + l + m] = f;
     if (m > 0) out[(size_t)l * l + l - m] = make_double2(sg * f.x, -sg * f.y);
   } else {
-    out[(size_t)l * l + l + m] = make_double2(d * row[4 * a], d * row[4 * a + 1]);
-    if (m > 0) out[(size_t)l * l + l - m] = make_double2(sg * d * row[4 * a + 2], sg * d * row[4 * a + 3]);
+    out[(size_t)l * l + l + m] = make_double2(d * v[0], d * v[1]);
+    if (m > 0) out[(size_t)l * l + l - m] = make_double2(sg * d * v[2], sg * d * v[3]);
   }
 }
 
 // dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks); rows l >= ks of dst are
 // zero-filled (when not accumulating).
-__global__ void k_tile(const double* __restrict__ src, int ks, double* __restrict__ dst, int kd,
-                       const double* __restrict__ kern, const double* __restrict__ dfac, int Lt,
-                       int C, int accumulate) {
+__global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long long pstride,
+                       double* __restrict__ dst, int kd, const double* __restrict__ kern,
+                       const double* __restrict__ dfac, int Lt, int C, int accumulate) {
   const int m = blockIdx.y;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int len = kd - m;
@@ -80,7 +91,10 @@ __global__ void k_tile(const double* __restrict__ src, int ks, double* __restric
   double v = 0.0;
   if (l < ks) {
     const double d = dfac[tri_off(Lt, m) + r];
-    v = kern[l] * d * d * src[(tri_off(ks, m) + r) * C + c];
+    const size_t at = (tri_off(ks, m) + r) * C + c;
+    double x = 0.0;
+    for (int g = 0; g < nparts; ++g) x += src[at + (size_t)g * pstride];
+    v = kern[l] * d * d * x;
   }
   double* o = dst + (tri_off(kd, m) + r) * C + c;
   if (accumulate)
@@ -97,18 +111,19 @@ hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const do
   return hipGetLastError();
 }
 
-hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, double2* flm,
-                           hipStream_t s) {
+hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, int nparts,
+                           long long part_stride, double2* flm, hipStream_t s) {
   dim3 grid((k * b.nb + 255) / 256, k);
-  k_pack<<<grid, 256, 0, s>>>(R, flm, G.dfac, k, G.Lt, b.C, b.nb, b.reality == S2LET_REAL,
-                              (long long)k * k);
+  k_pack<<<grid, 256, 0, s>>>(R, nparts, part_stride, flm, G.dfac, k, G.Lt, b.C, b.nb,
+                              b.reality == S2LET_REAL, (long long)k * k);
   return hipGetLastError();
 }
 
-hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, double* dst,
-                       int kd, const double* kern, int accumulate, hipStream_t s) {
+hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, int nparts,
+                       long long part_stride, double* dst, int kd, const double* kern, int accumulate,
+                       hipStream_t s) {
   dim3 grid((kd * b.C + 255) / 256, kd);
-  k_tile<<<grid, 256, 0, s>>>(src, ks, dst, kd, kern, G.dfac, G.Lt, b.C, accumulate);
+  k_tile<<<grid, 256, 0, s>>>(src, ks, nparts, part_stride, dst, kd, kern, G.dfac, G.Lt, b.C, accumulate);
   return hipGetLastError();
 }
 

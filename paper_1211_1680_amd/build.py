@@ -19,6 +19,8 @@ COMMON = [
     "-I" + os.path.join(ROOT, "include"), "-I" + SRC,
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs (no AGPR copies around each block of matrix ops)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

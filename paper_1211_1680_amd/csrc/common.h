@@ -14,6 +14,15 @@ __host__ __device__ inline int64_t tri_off(int k, int m) {
 }
 __host__ __device__ inline int64_t tri_rows(int k) { return (int64_t)k * (k + 1) / 2; }
 
+// Workgroups are handed to the 8 XCDs round-robin; this maps the hardware index to a logical
+// one so that consecutive logical indices run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int nblk) {
+  constexpr int X = 8;
+  const int per = nblk / X, rem = nblk % X;
+  const int x = b % X, idx = b / X;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+
 inline int next_pow2(int v) {
   int p = 1;
   while (p < v) p <<= 1;

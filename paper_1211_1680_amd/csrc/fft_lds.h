@@ -295,13 +295,4 @@ __device__ __forceinline__ void stockham_odd_pass(double2* buf, int n, int Ns, i
   __syncthreads();
 }
 
-// Workgroups are handed to the 8 XCDs round-robin; give consecutive logical indices to the
-// same XCD so that problems writing neighbouring columns of a row share an L2.
-__device__ __forceinline__ int xcd_swizzle(int b, int nblk) {
-  constexpr int X = 8;
-  const int per = nblk / X, rem = nblk % X;
-  const int x = b % X, idx = b / X;
-  return x * per + (x < rem ? x : rem) + idx;
-}
-
 }  // namespace s2let

@@ -89,17 +89,46 @@ __device__ __forceinline__ double chunk_coef(const double* __restrict__ am, cons
 }
 
 // One chunk of the difference recursion: degrees l0 .. l0 + LC - 1, z values (scaled by 2^e)
-// to zcol[j * ZS].  The state enters as (z_{l0-1}, E_{l0-1}).
-template <int LC, int ZS>
-__device__ __forceinline__ void recur_chunk(double cf, double u, double sg, double& z1, double& z2, int& e,
+// to zcol[j * ZS].  The state enters as (z_{l0-1}, E_{l0-1}).  SIGN = +1 / -1: every lane of the
+// wave is in the northern / southern hemisphere (s uniform, folded into the operations);
+// SIGN = 0: mixed.  SCALED = false: every lane has e = 0 (no scaling, no renormalisation).
+template <int LC, int ZS, int SIGN, bool SCALED>
+__device__ __forceinline__ void recur_steps(double cf, double u, double sg, double& z1, double& z2, int& e,
                                             double* zcol) {
 #pragma unroll
   for (int j = 0; j < LC; ++j) {
     const double g = fma(readlane_d(cf, j), u, readlane_d(cf, LC + j));
-    z2 = sg * fma(g, z1, z2);
-    z1 = fma(sg, z1, z2);
-    zcol[j * ZS] = ldexp(z1, e);
-    if ((j & 7) == 7) renorm(z1, z2, e);
+    if (SIGN > 0) {
+      z2 = fma(g, z1, z2);
+      z1 = z1 + z2;
+    } else if (SIGN < 0) {
+      z2 = fma(-g, z1, -z2);
+      z1 = z2 - z1;
+    } else {
+      z2 = sg * fma(g, z1, z2);
+      z1 = fma(sg, z1, z2);
+    }
+    zcol[j * ZS] = SCALED ? ldexp(z1, e) : z1;
+    if (SCALED && (j & 7) == 7) renorm(z1, z2, e);
+  }
+}
+
+template <int LC, int ZS>
+__device__ __forceinline__ void recur_chunk(double cf, double u, double sg, double& z1, double& z2, int& e,
+                                            double* zcol) {
+  const bool scaled = !__all(e == 0);
+  if (__all(sg > 0.0)) {
+    if (scaled)
+      recur_steps<LC, ZS, 1, true>(cf, u, sg, z1, z2, e, zcol);
+    else
+      recur_steps<LC, ZS, 1, false>(cf, u, sg, z1, z2, e, zcol);
+  } else if (__all(sg < 0.0)) {
+    if (scaled)
+      recur_steps<LC, ZS, -1, true>(cf, u, sg, z1, z2, e, zcol);
+    else
+      recur_steps<LC, ZS, -1, false>(cf, u, sg, z1, z2, e, zcol);
+  } else {
+    recur_steps<LC, ZS, 0, true>(cf, u, sg, z1, z2, e, zcol);
   }
 }
 
@@ -130,8 +159,9 @@ __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__
                                                       const double* __restrict__ sx,
                                                       const double* __restrict__ st, int k, int Lt,
                                                       int ntb, unsigned long long* __restrict__ counter) {
-  const int pair = blockIdx.x / ntb;
-  const int tb = blockIdx.x % ntb;
+  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);   // blocks of one pair share an L2
+  const int pair = blk / ntb;
+  const int tb = blk % ntb;
   const int t = tb * 256 + threadIdx.x;
   const bool valid = t < k;
   const double u = valid ? ut[t] : -1.0;
@@ -260,7 +290,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
   const bool valid = t < k;
   const bool tile_live = tile * 64 < k;
   const double u = valid ? ut[t] : -1.0;
-  const double sg = valid ? sx[t] : 1.0;
+  const double sg = valid ? sx[t] : -1.0;   // lanes past the pole join the southern hemisphere
   const double s = valid ? st[t] : 1.0;
   const int nm = (k - 1 - pair > pair) ? 2 : 1;
   double* __restrict__ Rg = R + (size_t)grp * part_stride;
@@ -370,12 +400,14 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
   __shared__ double Z[4][INVM_LC][INVM_ZS];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
-  const int pair = blockIdx.x / ntb;
-  const int tile = (blockIdx.x % ntb) * 4 + w;
+  // the ntb blocks of one m pair read the same coefficient columns: keep them on one XCD
+  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int pair = blk / ntb;
+  const int tile = (blk % ntb) * 4 + w;
   const int t = tile * 64 + lane;
   const bool valid = t < k;
   const double u = valid ? ut[t] : -1.0;
-  const double sg = valid ? sx[t] : 1.0;
+  const double sg = valid ? sx[t] : -1.0;   // lanes past the pole join the southern hemisphere
   const double s = valid ? st[t] : 1.0;
   const int nm = (k - 1 - pair > pair) ? 2 : 1;
   unsigned long long retained = 0;

@@ -92,9 +92,9 @@ __device__ __forceinline__ double chunk_coef(const double* __restrict__ am, cons
 // to zcol[j * ZS].  The state enters as (z_{l0-1}, E_{l0-1}).  SIGN = +1 / -1: every lane of the
 // wave is in the northern / southern hemisphere (s uniform, folded into the operations);
 // SIGN = 0: mixed.  SCALED = false: every lane has e = 0 (no scaling, no renormalisation).
-template <int LC, int ZS, int SIGN, bool SCALED>
+template <int LC, int ZS, int SIGN, bool SCALED, typename T>
 __device__ __forceinline__ void recur_steps(double cf, double u, double sg, double& z1, double& z2, int& e,
-                                            double* zcol) {
+                                            T* zcol) {
 #pragma unroll
   for (int j = 0; j < LC; ++j) {
     const double g = fma(readlane_d(cf, j), u, readlane_d(cf, LC + j));
@@ -108,14 +108,14 @@ __device__ __forceinline__ void recur_steps(double cf, double u, double sg, doub
       z2 = sg * fma(g, z1, z2);
       z1 = fma(sg, z1, z2);
     }
-    zcol[j * ZS] = SCALED ? ldexp(z1, e) : z1;
+    zcol[j * ZS] = (T)(SCALED ? ldexp(z1, e) : z1);
     if (SCALED && (j & 7) == 7) renorm(z1, z2, e);
   }
 }
 
-template <int LC, int ZS>
+template <int LC, int ZS, typename T>
 __device__ __forceinline__ void recur_chunk(double cf, double u, double sg, double& z1, double& z2, int& e,
-                                            double* zcol) {
+                                            T* zcol) {
   const bool scaled = !__all(e == 0);
   if (__all(sg > 0.0)) {
     if (scaled)
@@ -255,6 +255,28 @@ __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__
 // separate partial sums R[g]; the consumer of R adds them.
 // ------------------------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// The 16x16x4 matrix instruction per operand type: FP64, or FP32 with FP32 accumulation (the
+// mixed-precision contraction; the recursion stays FP64).  A lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16]; result register v holds column l % 16 and the row given by row().
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t zero() { return v4d{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lq, int v) { return lq + 4 * v; }
+};
+template <> struct Mma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t zero() { return v4f{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lq, int v) { return 4 * lq + v; }
+};
 
 constexpr int FWD_NW = 8;       // waves per block
 constexpr int FWD_LC = 32;      // degrees per chunk
@@ -268,7 +290,7 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int C>
+template <int C, typename T>
 __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__ HM, double* __restrict__ R,
                                                       long long part_stride,
                                                       const double* __restrict__ alpha,
@@ -279,8 +301,16 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
                                                       const double* __restrict__ st, int k, int Lt, int ng,
                                                       unsigned long long* __restrict__ counter) {
   constexpr int CT = C >= 16 ? C / 16 : 1;
+  // wave-private z tiles; after each chunk the same memory holds the FP64 partial sums
+  // red[w][l][c], row stride 2 x odd doubles so that the 16 degrees x 2 columns written by a
+  // half wave fall in different LDS banks
+  constexpr int RS = 2 * ((C / 2) | 1);
+  constexpr int ZBYTES = FWD_NW * FWD_LC * FWD_ZS * (int)sizeof(T);
+  constexpr int RBYTES = FWD_NW * FWD_LC * RS * (int)sizeof(double);
+  __shared__ __align__(16) char smem[ZBYTES > RBYTES ? ZBYTES : RBYTES];
+  T (*Z)[FWD_LC][FWD_ZS] = reinterpret_cast<T (*)[FWD_LC][FWD_ZS]>(smem);
+  double* red = reinterpret_cast<double*>(smem);
   unsigned long long retained = 0;   // (l, theta) pairs multiplied by this wave
-  __shared__ double Z[FWD_NW][FWD_LC][FWD_ZS];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
   const int pair = blockIdx.x / ng;
@@ -301,14 +331,14 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Hm = HM + (size_t)m * k * C;
     // this wave's operands: a[kk][ct] = H'[tile*64 + 4 kk + lq][ct*16 + li]
-    double a[16][CT];
+    T a[16][CT];
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int tg = tile * 64 + 4 * kk + lq;
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = ct * 16 + li;
-        a[kk][ct] = (tg < k && c < C) ? Hm[(size_t)tg * C + c] : 0.0;
+        a[kk][ct] = (T)((tg < k && c < C) ? Hm[(size_t)tg * C + c] : 0.0);
       }
     }
     int e;
@@ -317,11 +347,11 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
     double cf_next = chunk_coef<FWD_LC>(am, bm, 0, k - m, lane);
 
     for (int l0 = m; l0 < k; l0 += FWD_LC) {
-      v4d acc[2][CT];
+      typename Mma<T>::acc_t acc[2][CT];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<T>::zero();
       const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
       // z values for degrees l0 .. l0+31 at this lane's theta (lanes past k hold finite values
       // that meet zero operands)
@@ -338,28 +368,23 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
           const int tl = 4 * kk + lq;
 #pragma unroll
           for (int lt2 = 0; lt2 < 2; ++lt2) {
-            const double bv = Z[w][lt2 * 16 + li][tl];
+            const T bv = Z[w][lt2 * 16 + li][tl];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-              acc[lt2][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk][ct], bv, acc[lt2][ct], 0, 0, 0);
+            for (int ct = 0; ct < CT; ++ct) acc[lt2][ct] = Mma<T>::mma(a[kk][ct], bv, acc[lt2][ct]);
           }
         }
       }
-      // reduce the waves' partial sums: red[w][l][c], row stride 2 x odd doubles so that the
-      // 16 degrees x 2 columns written by a half wave fall in different LDS banks
-      constexpr int RS = 2 * ((C / 2) | 1);
+      // reduce the waves' partial sums
       __syncthreads();
-      double* red = &Z[0][0][0];
 #pragma unroll
       for (int lt2 = 0; lt2 < 2; ++lt2)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            // result register v of lane l holds row (l / 16) + 4 v, column l % 16
-            const int c = ct * 16 + lq + 4 * v;
+            const int c = ct * 16 + Mma<T>::row(lq, v);
             const int lloc = lt2 * 16 + li;
-            if (c < C) red[((size_t)w * FWD_LC + lloc) * RS + c] = acc[lt2][ct][v];
+            if (c < C) red[((size_t)w * FWD_LC + lloc) * RS + c] = (double)acc[lt2][ct][v];
           }
       __syncthreads();
       for (int idx = threadIdx.x; idx < FWD_LC * C; idx += FWD_NW * 64) {
@@ -385,9 +410,10 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
 // tile (16 degrees), the coefficient rows are vector loads issued before the recursion.
 // ------------------------------------------------------------------------------------------
 constexpr int INVM_LC = 16;     // degrees per chunk
-constexpr int INVM_ZS = 80;     // LDS row stride (doubles): = 16 mod 32, conflict-free A reads
+constexpr int INVM_ZS = 80;     // LDS row stride (elements): = 16 mod 32, conflict-free A reads
+constexpr int INVM_FLUSH = 4;   // FP32 path: chunks (64 degrees) accumulated in FP32 between flushes
 
-template <int C>
+template <int C, typename T>
 __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restrict__ S, double* __restrict__ FT,
                                                            const double* __restrict__ alpha,
                                                            const double* __restrict__ beta,
@@ -397,7 +423,8 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
                                                            const double* __restrict__ st, int k, int Lt,
                                                            int ntb, unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
-  __shared__ double Z[4][INVM_LC][INVM_ZS];
+  constexpr bool F64 = sizeof(T) == sizeof(double);
+  __shared__ T Z[4][INVM_LC][INVM_ZS];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
   // the ntb blocks of one m pair read the same coefficient columns: keep them on one XCD
@@ -417,11 +444,22 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
     const double* __restrict__ am = alpha + tri_off(Lt, m);
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Sm = S + tri_off(k, m) * C;
-    v4d acc[4][CT];
+    typename Mma<T>::acc_t acc[4][CT];
+    // FP32 path: the FP32 accumulators are added into FP64 sums every INVM_FLUSH chunks
+    double accd[F64 ? 1 : 4][F64 ? 1 : CT][4];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) acc[g][ct] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int ct = 0; ct < CT; ++ct) acc[g][ct] = Mma<T>::zero();
+    if constexpr (!F64) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) accd[g][ct][v] = 0.0;
+    }
+    int since_flush = 0;
 
     int e;
     double z1, z2;
@@ -429,16 +467,16 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
     double cf_next = chunk_coef<INVM_LC>(am, bm, 0, k - m, lane);
     // coefficient rows l0 + 4 sl + lq, columns ct*16 + li; the rows of the next chunk are
     // requested while the current chunk is multiplied
-    double bn[INVM_LC / 4][CT];
+    T bn[INVM_LC / 4][CT];
 #pragma unroll
     for (int sl = 0; sl < INVM_LC / 4; ++sl) {
       const int l = m + 4 * sl + lq;
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+      for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = (T)(l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0);
     }
     for (int l0 = m; l0 < k; l0 += INVM_LC) {
       const bool skip = __all(!valid || negligible(z1, z2, e));
-      double b[INVM_LC / 4][CT];
+      T b[INVM_LC / 4][CT];
 #pragma unroll
       for (int sl = 0; sl < INVM_LC / 4; ++sl)
 #pragma unroll
@@ -448,7 +486,7 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
         for (int sl = 0; sl < INVM_LC / 4; ++sl) {
           const int l = l0 + INVM_LC + 4 * sl + lq;
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = (T)(l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0);
         }
       }
       const double cf = cf_next;
@@ -463,25 +501,42 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
         for (int sl = 0; sl < INVM_LC / 4; ++sl) {
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
-            const double av = Z[w][4 * sl + lq][16 * g + li];
+            const T av = Z[w][4 * sl + lq][16 * g + li];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-              acc[g][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[sl][ct], acc[g][ct], 0, 0, 0);
+            for (int ct = 0; ct < CT; ++ct) acc[g][ct] = Mma<T>::mma(av, b[sl][ct], acc[g][ct]);
           }
         }
         wave_lds_sync();
+        if constexpr (!F64) {
+          if (++since_flush == INVM_FLUSH) {
+            since_flush = 0;
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) accd[g][ct][v] += (double)acc[g][ct][v];
+                acc[g][ct] = Mma<T>::zero();
+              }
+          }
+        }
       }
     }
-    // result register v of lane l holds row (l / 16) + 4 v (theta), column l % 16
+    // result register v of lane l holds theta row Mma<T>::row(l / 16, v), column l % 16
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int tt = tile * 64 + 16 * g + lq + 4 * v;
+        const int tt = tile * 64 + 16 * g + Mma<T>::row(lq, v);
         if (tt < k) {
           double* out = FT + ((size_t)tt * k + m) * C;
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) out[ct * 16 + li] = acc[g][ct][v];
+          for (int ct = 0; ct < CT; ++ct) {
+            if constexpr (F64)
+              out[ct * 16 + li] = acc[g][ct][v];
+            else
+              out[ct * 16 + li] = accd[g][ct][v] + (double)acc[g][ct][v];
+          }
         }
       }
   }
@@ -493,15 +548,21 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
 }
 
 // ------------------------------------------------------------------------------------------
+// Batches below 16 columns run the FP64 VALU kernel in every precision mode.
 template <int C>
-static hipError_t inv_c(const ShtTables& T, const LegTables& G, const double* S, double* FT,
+static hipError_t inv_c(const ShtTables& T, const LegTables& G, const double* S, double* FT, int precision,
                         unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   const int ntb = (k + 255) / 256;
   const int npairs = (k + 1) / 2;
   if (C >= 16) {
-    k_legendre_inv_mfma<(C >= 16 ? C : 16)><<<npairs * ntb, 256, 0, s>>>(
-        S, FT, G.alpha, G.beta, G.cm, T.ut, T.sx, T.st, k, G.Lt, ntb, counter);
+    constexpr int CC = C >= 16 ? C : 16;
+    if (precision == S2LET_MIXED_FP32)
+      k_legendre_inv_mfma<CC, float><<<npairs * ntb, 256, 0, s>>>(S, FT, G.alpha, G.beta, G.cm, T.ut, T.sx,
+                                                                  T.st, k, G.Lt, ntb, counter);
+    else
+      k_legendre_inv_mfma<CC, double><<<npairs * ntb, 256, 0, s>>>(S, FT, G.alpha, G.beta, G.cm, T.ut, T.sx,
+                                                                   T.st, k, G.Lt, ntb, counter);
     return hipGetLastError();
   }
   k_legendre_inv<C><<<npairs * ntb, 256, 0, s>>>(S, FT, G.alpha, G.beta, G.cm, T.ut, T.sx, T.st, k, G.Lt,
@@ -513,25 +574,28 @@ int legendre_forward_groups(int k) { return (k + FWD_TB - 1) / FWD_TB; }
 
 template <int C>
 static hipError_t fwd_c(const ShtTables& T, const LegTables& G, const double* HM, double* R,
-                        long long part_stride, unsigned long long* counter, hipStream_t s) {
+                        long long part_stride, int precision, unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   const int npairs = (k + 1) / 2;
   const int ng = legendre_forward_groups(k);
-  k_legendre_fwd<C><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut,
-                                                        T.sx, T.st, k, G.Lt, ng, counter);
+  if (precision == S2LET_MIXED_FP32)
+    k_legendre_fwd<C, float><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm,
+                                                                 T.ut, T.sx, T.st, k, G.Lt, ng, counter);
+  else
+    k_legendre_fwd<C, double><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm,
+                                                                  T.ut, T.sx, T.st, k, G.Lt, ng, counter);
   return hipGetLastError();
 }
 
 hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const Batch& b,
                                    const double* S, double* FT, int precision,
                                    unsigned long long* counter, hipStream_t s) {
-  (void)precision;
   switch (b.C) {
-    case 2: return inv_c<2>(T, G, S, FT, counter, s);
-    case 4: return inv_c<4>(T, G, S, FT, counter, s);
-    case 8: return inv_c<8>(T, G, S, FT, counter, s);
-    case 16: return inv_c<16>(T, G, S, FT, counter, s);
-    case 32: return inv_c<32>(T, G, S, FT, counter, s);
+    case 2: return inv_c<2>(T, G, S, FT, precision, counter, s);
+    case 4: return inv_c<4>(T, G, S, FT, precision, counter, s);
+    case 8: return inv_c<8>(T, G, S, FT, precision, counter, s);
+    case 16: return inv_c<16>(T, G, S, FT, precision, counter, s);
+    case 32: return inv_c<32>(T, G, S, FT, precision, counter, s);
   }
   return hipErrorInvalidValue;
 }
@@ -539,13 +603,12 @@ hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const
 hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const Batch& b,
                                    const double* HM, double* R, long long part_stride, int precision,
                                    unsigned long long* counter, hipStream_t s) {
-  (void)precision;
   switch (b.C) {
-    case 2: return fwd_c<2>(T, G, HM, R, part_stride, counter, s);
-    case 4: return fwd_c<4>(T, G, HM, R, part_stride, counter, s);
-    case 8: return fwd_c<8>(T, G, HM, R, part_stride, counter, s);
-    case 16: return fwd_c<16>(T, G, HM, R, part_stride, counter, s);
-    case 32: return fwd_c<32>(T, G, HM, R, part_stride, counter, s);
+    case 2: return fwd_c<2>(T, G, HM, R, part_stride, precision, counter, s);
+    case 4: return fwd_c<4>(T, G, HM, R, part_stride, precision, counter, s);
+    case 8: return fwd_c<8>(T, G, HM, R, part_stride, precision, counter, s);
+    case 16: return fwd_c<16>(T, G, HM, R, part_stride, precision, counter, s);
+    case 32: return fwd_c<32>(T, G, HM, R, part_stride, precision, counter, s);
   }
   return hipErrorInvalidValue;
 }

@@ -92,12 +92,30 @@ def cpu_baseline(L, B, J_min, multires, s2):
     }
 
 
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}   # S2LET_FP64, S2LET_MIXED_FP32, S2LET_MIXED_BF16X3
+
+
+def stage_rates(stages):
+    out = {}
+    for n, v in stages.items():
+        if v["ms"] <= 0:
+            continue
+        if n.startswith("legendre"):
+            tf = v["flops_retained"] / (v["ms"] * 1e-3) / 1e12
+            out[n] = "%.1f TFLOP/s (%.0f%% of FP64 peak)" % (tf, 100 * tf / PEAK_FP64_TFLOPS)
+        else:
+            gb = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+            out[n] = "%.0f GB/s (%.0f%% of HBM peak)" % (gb, 100 * gb / PEAK_HBM_GBS)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64"], default="fp64")
+    ap.add_argument("--mixed", default="fp32,bf16x3",
+                    help="mixed-precision modes timed after the FP64 headline run (comma list, or none)")
     ap.add_argument("--L", type=int, default=2048)
     ap.add_argument("--nmaps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,14 +131,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1211_1680_amd as s2
     import s2let_inputs as si
 
     L, B, J_min, multires, nmaps = args.L, 2, 3, True, args.nmaps
-    prec = {"fp64": s2.FP64}[args.precision]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
@@ -129,30 +145,35 @@ def main():
     f = s2.mw_inverse(torch.from_numpy(flm).to(dev), L, s2.REAL)
     del flm
     kP = s2.bandlimit_scal(J_min, L, B, multires)
-    f_wav = torch.empty((nmaps, s2.wav_size(L, B, J_min, multires)), dtype=torch.float64, device=dev)
-    f_scal = torch.empty((nmaps, s2.mw_size(kP)), dtype=torch.float64, device=dev)
-    rec = torch.empty_like(f)
-    ws = torch.empty(s2.workspace_size(L, B, J_min, multires, s2.REAL, prec, nmaps, True),
+    ws = torch.empty(s2.workspace_size(L, B, J_min, multires, s2.REAL, s2.FP64, nmaps, True),
                      dtype=torch.uint8, device=dev)
 
-    def step():
-        s2.analysis(f, L, B, J_min, multires, s2.REAL, prec, workspace=ws, out=(f_wav, f_scal))
-        s2.synthesis(f_wav, f_scal, L, B, J_min, multires, s2.REAL, prec, workspace=ws, out=rec)
+    def run_mode(prec):
+        f_wav = torch.empty((nmaps, s2.wav_size(L, B, J_min, multires)), dtype=torch.float64, device=dev)
+        f_scal = torch.empty((nmaps, s2.mw_size(kP)), dtype=torch.float64, device=dev)
+        rec = torch.empty_like(f)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    err = float((rec - f).abs().max().item() / f.abs().max().item())
+        def step():
+            s2.analysis(f, L, B, J_min, multires, s2.REAL, prec, workspace=ws, out=(f_wav, f_scal))
+            s2.synthesis(f_wav, f_scal, L, B, J_min, multires, s2.REAL, prec, workspace=ws, out=rec)
 
-    s2.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stages = {name: s2.profile_query(name) for name in s2.STAGES}
-    s2.profile_enable(False)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        s2.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stages = {name: s2.profile_query(name) for name in s2.STAGES}
+        s2.profile_enable(False)
+        return dict(dt=dt, stages=stages, f_wav=f_wav, f_scal=f_scal, rec=rec)
+
+    r64 = run_mode(s2.FP64)
+    dt, stages = r64["dt"], r64["stages"]
+    err = float((r64["rec"] - f).abs().max().item() / f.abs().max().item())
 
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
@@ -171,7 +192,7 @@ def main():
     st = stages[dom]
     if dom.startswith("legendre"):
         achieved = st["flops_retained"] / (st["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma" if dom == "legendre_analysis" else "alu", "achieved": achieved,
+        roof = {"bound": "mfma", "achieved": achieved,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": measured_traffic(dom), "kernel": dom, "launches": st["launches"],
                 "avg_launch_ms": st["ms"] / max(st["launches"], 1),
@@ -181,18 +202,6 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dom,
                 "launches": st["launches"], "avg_launch_ms": st["ms"] / max(st["launches"], 1)}
-    stage_ms = {n: round(v["ms"] / args.steps, 3) for n, v in stages.items()}
-    stage_rate = {}
-    for n, v in stages.items():
-        if v["ms"] <= 0:
-            continue
-        if n.startswith("legendre"):
-            stage_rate[n] = "%.1f TFLOP/s (%.0f%% of FP64 peak)" % (
-                v["flops_retained"] / (v["ms"] * 1e-3) / 1e12,
-                100 * v["flops_retained"] / (v["ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS)
-        else:
-            stage_rate[n] = "%.0f GB/s (%.0f%% of HBM peak)" % (
-                v["bytes"] / (v["ms"] * 1e-3) / 1e9, 100 * v["bytes"] / (v["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS)
 
     out = {
         "metric": METRIC,
@@ -209,13 +218,40 @@ def main():
         "data": "synthetic",
         "config": {"workload": "wavelet analysis+synthesis of %d real maps, L=%d, B=%d, J_min=%d, "
                                "multiresolution, C_l=1/(l(l+1)), seed 3, FP64" % (nmaps, L, B, J_min),
-                   "nmaps": nmaps, "L": L, "B": B, "J_min": J_min, "multires": multires,
-                   "precision": args.precision},
+                   "nmaps": nmaps, "L": L, "B": B, "J_min": J_min, "multires": multires},
         "roofline": roof,
-        "stage_ms_per_step": stage_ms,
-        "stage_rate": stage_rate,
+        "stage_ms_per_step": {n: round(v["ms"] / args.steps, 3) for n, v in stages.items()},
+        "stage_rate": stage_rates(stages),
         "round_trip_rel_err": err,
     }
+
+    # mixed precision: same workload, Legendre contraction on lower-precision matrix cores
+    mixed = {}
+    for name in [m for m in args.mixed.split(",") if m and m != "none"]:
+        try:
+            r = run_mode(PRECISIONS[name])
+        except s2.S2letError as exc:
+            mixed[name] = {"status": str(exc)}
+            continue
+        d_w = (r["f_wav"] - r64["f_wav"]).abs()
+        d_r = (r["rec"] - r64["rec"]).abs()
+        wmax = r64["f_wav"].abs().max().item()
+        fmax = r64["rec"].abs().max().item()
+        lst = {n: v for n, v in r["stages"].items()}
+        mixed[name] = {
+            "value": nmaps * args.steps / r["dt"], "unit": "maps/s",
+            "ms_per_step": 1e3 * r["dt"] / args.steps,
+            "speedup_vs_fp64": dt / r["dt"],
+            "stage_ms_per_step": {n: round(v["ms"] / args.steps, 3) for n, v in lst.items()},
+            "legendre_equiv_tflops": {n: round(v["flops_retained"] / (v["ms"] * 1e-3) / 1e12, 1)
+                                      for n, v in lst.items() if n.startswith("legendre") and v["ms"] > 0},
+            "wavelet_maps_rel_max_err_vs_fp64": d_w.max().item() / wmax,
+            "wavelet_maps_rel_rms_err_vs_fp64": (d_w.square().mean().sqrt().item()) / wmax,
+            "reconstruction_rel_max_err_vs_fp64": d_r.max().item() / fmax,
+        }
+        del r
+    if mixed:
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, B, J_min, multires, s2)
     print(json.dumps(out), flush=True)

@@ -352,7 +352,6 @@ static int prologue(int L, int reality, int precision, int nmaps, void* ws, size
   if (st != S2LET_OK) return st;
   if (L < 1) return S2LET_EINVAL;
   if (L > S2LET_MAX_L) return S2LET_EUNSUPPORTED;
-  if (precision == S2LET_MIXED_BF16X3) return S2LET_EUNSUPPORTED;
   if (!ws || !aligned16(ws)) return S2LET_EINVAL;
   const Batch b = make_batch(reality, std::min(nmaps, batch_cap(reality)));
   if (ws_bytes < ws_bytes_for(L, b.C, wavelet)) return S2LET_ENOMEM;

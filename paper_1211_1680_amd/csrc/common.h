@@ -101,6 +101,13 @@ hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const
 hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const Batch& b,
                                    const double* S, double* FT, int precision,
                                    unsigned long long* counter, hipStream_t s);
+// The same two contractions with BF16x3 operands on the matrix cores (the synthesis for C >= 16).
+hipError_t launch_legendre_forward_bf16(const ShtTables& T, const LegTables& G, const Batch& b,
+                                        const double* HM, double* R, long long part_stride,
+                                        unsigned long long* counter, hipStream_t s);
+hipError_t launch_legendre_inverse_bf16(const ShtTables& T, const LegTables& G, const Batch& b,
+                                        const double* S, double* FT, unsigned long long* counter,
+                                        hipStream_t s);
 // flm (user layout) -> S (k-packed rows, scaled by d_lm, -m columns by (-1)^m).
 hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm,
                              double* S, hipStream_t s);

@@ -16,134 +16,10 @@
 // renormalised every 8 steps; while every lane of a wave is below 2^-1100 the contraction
 // is skipped, and once every lane has e = 0 the plain recursion runs.
 #include "common.h"
+#include "legendre_rec.h"
 #include "../../include/s2let_mi355x.h"
 
 namespace s2let {
-
-// s^m = mant * 2^e with mant in [0.5, 1) (or 0), by binary powering.
-__device__ __forceinline__ double pow_scaled(double s, int m, int* e_out) {
-  int be;
-  double b = frexp(s, &be);
-  double r = 1.0;
-  int re = 0;
-  while (m) {
-    if (m & 1) {
-      int ex;
-      r = frexp(r * b, &ex);
-      re += ex + be;
-    }
-    m >>= 1;
-    if (m) {
-      int ex;
-      b = frexp(b * b, &ex);
-      be = 2 * be + ex;
-    }
-  }
-  *e_out = re;
-  return r;
-}
-
-__device__ __forceinline__ int exponent_of(double v) {
-  int ex;
-  frexp(v, &ex);
-  return ex;
-}
-
-// Moves magnitude between (z1, z2) and e while e < 0 (keeps z1 in a safe range).
-__device__ __forceinline__ void renorm(double& z1, double& z2, int& e) {
-  if (e < 0) {
-    const int ex = exponent_of(z1);
-    if (ex > 60 || ex >= -e) {
-      const int sh = ex < -e ? ex : -e;
-      z1 = ldexp(z1, -sh);
-      z2 = ldexp(z2, -sh);
-      e += sh;
-    }
-  }
-}
-
-__device__ __forceinline__ bool negligible(double z1, double z2, int e) {
-  const double a = fmax(fabs(z1), fabs(z2));
-  return a == 0.0 || e + exponent_of(a) < -1100;
-}
-
-// value of v in lane l (l uniform), through two scalar registers
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __hiloint2double(hi, lo);
-}
-
-// Recursion coefficients of one chunk of LC degrees starting at row i0 of column m (len rows
-// below the band-limit): lane j < LC holds alpha, lane LC + j holds beta, zero past the end
-// (alpha = beta = 0 keeps the state finite).  One vector load per lane replaces 2 LC scalar
-// loads whose latency would otherwise sit in every step of the recursion.
-template <int LC>
-__device__ __forceinline__ double chunk_coef(const double* __restrict__ am, const double* __restrict__ bm,
-                                             int i0, int len, int lane) {
-  const bool isb = lane >= LC;
-  const int i = i0 + (isb ? lane - LC : lane);
-  const double* p = isb ? bm : am;
-  return (lane < 2 * LC && i < len) ? p[i] : 0.0;
-}
-
-// One chunk of the difference recursion: degrees l0 .. l0 + LC - 1, z values (scaled by 2^e)
-// to zcol[j * ZS].  The state enters as (z_{l0-1}, E_{l0-1}).  SIGN = +1 / -1: every lane of the
-// wave is in the northern / southern hemisphere (s uniform, folded into the operations);
-// SIGN = 0: mixed.  SCALED = false: every lane has e = 0 (no scaling, no renormalisation).
-template <int LC, int ZS, int SIGN, bool SCALED, typename T>
-__device__ __forceinline__ void recur_steps(double cf, double u, double sg, double& z1, double& z2, int& e,
-                                            T* zcol) {
-#pragma unroll
-  for (int j = 0; j < LC; ++j) {
-    const double g = fma(readlane_d(cf, j), u, readlane_d(cf, LC + j));
-    if (SIGN > 0) {
-      z2 = fma(g, z1, z2);
-      z1 = z1 + z2;
-    } else if (SIGN < 0) {
-      z2 = fma(-g, z1, -z2);
-      z1 = z2 - z1;
-    } else {
-      z2 = sg * fma(g, z1, z2);
-      z1 = fma(sg, z1, z2);
-    }
-    zcol[j * ZS] = (T)(SCALED ? ldexp(z1, e) : z1);
-    if (SCALED && (j & 7) == 7) renorm(z1, z2, e);
-  }
-}
-
-template <int LC, int ZS, typename T>
-__device__ __forceinline__ void recur_chunk(double cf, double u, double sg, double& z1, double& z2, int& e,
-                                            T* zcol) {
-  const bool scaled = !__all(e == 0);
-  if (__all(sg > 0.0)) {
-    if (scaled)
-      recur_steps<LC, ZS, 1, true>(cf, u, sg, z1, z2, e, zcol);
-    else
-      recur_steps<LC, ZS, 1, false>(cf, u, sg, z1, z2, e, zcol);
-  } else if (__all(sg < 0.0)) {
-    if (scaled)
-      recur_steps<LC, ZS, -1, true>(cf, u, sg, z1, z2, e, zcol);
-    else
-      recur_steps<LC, ZS, -1, false>(cf, u, sg, z1, z2, e, zcol);
-  } else {
-    recur_steps<LC, ZS, 0, true>(cf, u, sg, z1, z2, e, zcol);
-  }
-}
-
-// Start of the recursion one degree early: z_{m-1} = 0 and E = s z_m, so that the first step
-// (alpha_m = 0, beta_m = -2 in the tables) yields z_m and E_m = z_m.
-__device__ __forceinline__ void recur_start(double cmm, double s, double sg, int m, double& z1, double& z2,
-                                            int& e) {
-  double zm = cmm * pow_scaled(s, m, &e);
-  if (e > 0) {
-    zm = ldexp(zm, e);
-    e = 0;
-  }
-  z1 = 0.0;
-  z2 = sg * zm;
-}
 
 // ------------------------------------------------------------------------------------------
 // Synthesis: one lane per theta_t, 4 waves per block; a block handles the m pair
@@ -254,8 +130,6 @@ __global__ __launch_bounds__(256) void k_legendre_inv(const double* __restrict__
 // partial sums are reduced through LDS.  Blocks covering different theta ranges (g) write
 // separate partial sums R[g]; the consumer of R adds them.
 // ------------------------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
 
 // The 16x16x4 matrix instruction per operand type: FP64, or FP32 with FP32 accumulation (the
 // mixed-precision contraction; the recursion stays FP64).  A lane l holds A[l % 16][l / 16],
@@ -282,13 +156,6 @@ constexpr int FWD_NW = 8;       // waves per block
 constexpr int FWD_LC = 32;      // degrees per chunk
 constexpr int FWD_ZS = 66;      // LDS row stride (doubles): 2 x odd, conflict-free B reads
 constexpr int FWD_TB = FWD_NW * 64;   // thetas per block
-
-// orders this wave's LDS writes before its later reads (and the reverse) without a block barrier
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int C, typename T>
 __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__ HM, double* __restrict__ R,
@@ -357,7 +224,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
       // that meet zero operands)
       const double cf = cf_next;
       cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
-      recur_chunk<FWD_LC, FWD_ZS>(cf, u, sg, z1, z2, e, &Z[w][0][lane]);
+      recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) { Z[w][j][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
@@ -467,12 +334,13 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
     double cf_next = chunk_coef<INVM_LC>(am, bm, 0, k - m, lane);
     // coefficient rows l0 + 4 sl + lq, columns ct*16 + li; the rows of the next chunk are
     // requested while the current chunk is multiplied
-    T bn[INVM_LC / 4][CT];
+    // (kept in FP64 until used, so that the loads stay in flight across the recursion)
+    double bn[INVM_LC / 4][CT];
 #pragma unroll
     for (int sl = 0; sl < INVM_LC / 4; ++sl) {
       const int l = m + 4 * sl + lq;
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = (T)(l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0);
+      for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
     }
     for (int l0 = m; l0 < k; l0 += INVM_LC) {
       const bool skip = __all(!valid || negligible(z1, z2, e));
@@ -480,19 +348,19 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
 #pragma unroll
       for (int sl = 0; sl < INVM_LC / 4; ++sl)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) b[sl][ct] = bn[sl][ct];
+        for (int ct = 0; ct < CT; ++ct) b[sl][ct] = (T)bn[sl][ct];
       if (l0 + INVM_LC < k) {
 #pragma unroll
         for (int sl = 0; sl < INVM_LC / 4; ++sl) {
           const int l = l0 + INVM_LC + 4 * sl + lq;
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = (T)(l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0);
+          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
         }
       }
       const double cf = cf_next;
       cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
       // degrees past k meet zero coefficient rows; thetas past k are not stored
-      recur_chunk<INVM_LC, INVM_ZS>(cf, u, sg, z1, z2, e, &Z[w][0][lane]);
+      recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) { Z[w][j][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < INVM_LC ? (k - l0) : INVM_LC;
@@ -590,6 +458,7 @@ static hipError_t fwd_c(const ShtTables& T, const LegTables& G, const double* HM
 hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const Batch& b,
                                    const double* S, double* FT, int precision,
                                    unsigned long long* counter, hipStream_t s) {
+  if (precision == S2LET_MIXED_BF16X3 && b.C >= 16) return launch_legendre_inverse_bf16(T, G, b, S, FT, counter, s);
   switch (b.C) {
     case 2: return inv_c<2>(T, G, S, FT, precision, counter, s);
     case 4: return inv_c<4>(T, G, S, FT, precision, counter, s);
@@ -603,6 +472,7 @@ hipError_t launch_legendre_inverse(const ShtTables& T, const LegTables& G, const
 hipError_t launch_legendre_forward(const ShtTables& T, const LegTables& G, const Batch& b,
                                    const double* HM, double* R, long long part_stride, int precision,
                                    unsigned long long* counter, hipStream_t s) {
+  if (precision == S2LET_MIXED_BF16X3) return launch_legendre_forward_bf16(T, G, b, HM, R, part_stride, counter, s);
   switch (b.C) {
     case 2: return fwd_c<2>(T, G, HM, R, part_stride, precision, counter, s);
     case 4: return fwd_c<4>(T, G, HM, R, part_stride, precision, counter, s);

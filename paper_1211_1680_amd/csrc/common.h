@@ -91,6 +91,13 @@ hipError_t launch_theta(const ShtTables& T, const Batch& b, const double* GT, do
 // phi stage, inverse: FT[t][m][c] -> maps (ring stride n, map stride map_stride samples).
 hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
                               int64_t map_stride, hipStream_t s);
+// The same three stages compiled for band-limit 2048 (n = 4095); used when applicable.
+bool fft_k2048_applies(const ShtTables& T);
+hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                   double* GT, hipStream_t s);
+hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
+hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
+                                   int64_t map_stride, hipStream_t s);
 // Legendre contraction, forward: HM[m][t][c] -> R[tri_off(k,m)+l-m][c] = sum_t z_lm(theta_t) H',
 // written as legendre_forward_groups(k) partial sums over theta ranges, part g at R + g*part_stride.
 int legendre_forward_groups(int k);

@@ -1,0 +1,84 @@
+// Transforms whose length and radix plan are compile-time constants (the 4095-point odd DFT
+// and the 4096-point FFT of band-limit 2048), for the specialised kernels of that size.  Same
+// Stockham autosort passes as fft_lds.h, with three differences that matter for speed:
+//  - element i of a transform lives in LDS slot i + i/8 (one pad slot per 8), so the strided
+//    writes of the early passes (stride = radix) spread over the LDS banks;
+//  - twiddles W_N^p = lo[p mod 64] hi[p / 64] come from 64-entry tables staged in LDS;
+//  - every index computation divides by compile-time constants.
+#pragma once
+#include "fft_lds.h"
+
+namespace s2let {
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
+constexpr int lds_padded(int n) { return n + (n >> 3) + 1; }
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft_small(double2* v) {
+  if constexpr (R == 2 || R == 4 || R == 8 || R == 16)
+    SmallDft<R, INV>::run(v);
+  else
+    OddDft<R, INV>::run(v);
+}
+
+// One pass: N points, radix R, NS = product of the radices of the earlier passes, T threads.
+template <int N, int R, int NS, bool INV, int T>
+__device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  constexpr int NB = N / R;
+  constexpr int STRIDE = N / (NS * R);
+  constexpr int PER = (NB + T - 1) / T;
+  static_assert(N % (NS * R) == 0, "radix plan does not divide the length");
+  double2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_pad(j + r * NB)];
+      if constexpr (NS > 1) {
+        const int p = (j % NS) * STRIDE;
+        double2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
+        if (INV) w1 = conjd(w1);
+        double2 w = w1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[i][r] = cmul(v[i][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+      dft_small<R, INV>(v[i]);
+      const int kk = j % NS;
+      const int base = (j - kk) * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds_pad(base + r * NS)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// 4096 = 8^4 (unnormalised, sign -1 or +1 with INV)
+template <bool INV, int T>
+__device__ __forceinline__ void fft4096(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  ct_pass<4096, 8, 1, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 8, 8, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 8, 64, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 8, 512, INV, T>(buf, lt, wlo, whi);
+}
+
+// 4095 = 13 * 9 * 7 * 5
+template <bool INV, int T>
+__device__ __forceinline__ void dft4095(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  ct_pass<4095, 13, 1, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4095, 9, 13, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4095, 7, 117, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4095, 5, 819, INV, T>(buf, lt, wlo, whi);
+}
+
+}  // namespace s2let

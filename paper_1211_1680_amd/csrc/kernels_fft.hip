@@ -382,6 +382,7 @@ static hipError_t phi_fwd_v(const FftArgs& A, const void* f, int64_t map_stride,
 
 hipError_t launch_phi_forward(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
                               double* GT, hipStream_t s) {
+  if (fft_k2048_applies(T)) return launch_phi_forward_2048(T, b, f, map_stride, GT, s);
   const FftArgs A = fft_args(T, false);
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = T.k * nunits;
@@ -403,6 +404,7 @@ static hipError_t theta_v(const FftArgs& A, const double* GT, double* HM, const 
 }
 
 hipError_t launch_theta(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s) {
+  if (fft_k2048_applies(T)) return launch_theta_2048(T, b, GT, HM, s);
   const FftArgs A = fft_args(T, true);
   const int nprob = ((T.k + 1) / 2) * (b.C / 2);
   return A.buf > 4096 ? theta_v<16>(A, GT, HM, b, nprob, s) : theta_v<8>(A, GT, HM, b, nprob, s);
@@ -421,6 +423,7 @@ static hipError_t phi_inv_v(const FftArgs& A, const double* FT, void* f, int64_t
 
 hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
                               int64_t map_stride, hipStream_t s) {
+  if (fft_k2048_applies(T)) return launch_phi_inverse_2048(T, b, FT, f, map_stride, s);
   const FftArgs A = fft_args(T, false);
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = T.k * nunits;

@@ -1,0 +1,306 @@
+// The O(k^2 log k) stages of the MW transform at band-limit k = 2048 (n = 2k - 1 = 4095 =
+// 13 * 9 * 7 * 5, correlation length 4096), with the transforms compiled for that size
+// (fft_ct.h).  Same arithmetic as the general kernels in kernels_fft.hip: phi DFT (Sect. 2.1,
+// MW sampling), the theta stage (extension, DFT, parity-split correlation with the even part of
+// the sin(theta) weight, DFT back, fold), and the inverse phi DFT.  One problem per 512-thread
+// block; 74-76 KiB of LDS and at most 128 VGPRs (4 waves per SIMD), so two blocks share a CU.
+#include "common.h"
+#include "fft_ct.h"
+#include "../../include/s2let_mi355x.h"
+
+namespace s2let {
+
+namespace {
+constexpr int K = 2048;
+constexpr int N = 2 * K - 1;    // 4095
+constexpr int NC = 4096;
+constexpr int TT = 512;         // threads per problem
+constexpr int NBUF = lds_padded(NC);
+
+struct K2048Args {
+  const double2* tw4096_lo;   // W_4096^p, p < 64
+  const double2* tw4096_hi;   // W_4096^(64 q), q < 64
+  const double2* tw4095_lo;
+  const double2* tw4095_hi;
+  const double2* khat0;
+  const double2* khat1;
+  const double2* hphase;
+};
+
+__device__ __forceinline__ void stage_tables(const K2048Args& A, double2* w6lo, double2* w6hi, double2* w5lo,
+                                             double2* w5hi) {
+  const int lt = threadIdx.x;
+  if (lt < 64) {
+    w6lo[lt] = A.tw4096_lo[lt];
+    w6hi[lt] = A.tw4096_hi[lt];
+    w5lo[lt] = A.tw4095_lo[lt];
+    w5hi[lt] = A.tw4095_hi[lt];
+  }
+}
+}  // namespace
+
+// phi stage, forward (see k_phi_forward): GT[(t*k + m)*C + c] for m < k.
+template <int REAL>
+__global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const double* __restrict__ f,
+                                                            long long map_stride, double* __restrict__ GT,
+                                                            int C, int nb, int used, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  stage_tables(A, w6lo, w6hi, w5lo, w5hi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int nunits = REAL ? (nb + 1) / 2 : nb;
+  const int t = valid ? p / nunits : 0;
+  const int u = valid ? p % nunits : 0;
+  const int ma = REAL ? 2 * u : u;
+  const bool hasb = REAL && (ma + 1 < nb);
+
+  for (int q = lt; q < N; q += TT) {
+    double2 z = make_double2(0.0, 0.0);
+    if (valid) {
+      if (REAL) {
+        z.x = f[(size_t)ma * map_stride + (size_t)t * N + q];
+        z.y = hasb ? f[(size_t)(ma + 1) * map_stride + (size_t)t * N + q] : 0.0;
+      } else {
+        z = reinterpret_cast<const double2*>(f)[(size_t)ma * map_stride + (size_t)t * N + q];
+      }
+    }
+    buf[lds_pad(q)] = z;
+  }
+  __syncthreads();
+  dft4095<false, TT>(buf, lt, w5lo, w5hi);
+
+  const double wphi = 2.0 * M_PI / (double)N;
+  if (valid) {
+    for (int m = lt; m < K; m += TT) {
+      const double2 zp = buf[lds_pad(m)];
+      const double2 zn = buf[lds_pad(m == 0 ? 0 : N - m)];
+      double* row = GT + ((size_t)t * K + m) * C;
+      if (REAL) {
+        row[2 * ma] = wphi * 0.5 * (zp.x + zn.x);
+        row[2 * ma + 1] = wphi * 0.5 * (zp.y - zn.y);
+        if (hasb) {
+          row[2 * ma + 2] = wphi * 0.5 * (zp.y + zn.y);
+          row[2 * ma + 3] = -wphi * 0.5 * (zp.x - zn.x);
+        }
+      } else {
+        row[4 * ma] = wphi * zp.x;
+        row[4 * ma + 1] = wphi * zp.y;
+        row[4 * ma + 2] = (m == 0) ? 0.0 : wphi * zn.x;
+        row[4 * ma + 3] = (m == 0) ? 0.0 : wphi * zn.y;
+      }
+      if (u == 0)
+        for (int c = used; c < C; ++c) row[c] = 0.0;
+    }
+  }
+}
+
+// theta stage (see k_theta): GT[(t*k + m)*C + c] -> HM[(m*k + t)*C + c].
+__global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double* __restrict__ GT,
+                                                      double* __restrict__ HM, int C, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  stage_tables(A, w6lo, w6hi, w5lo, w5hi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int ns = C / 2;
+  const int mu = valid ? p / ns : 0;
+  const int s = valid ? p % ns : 0;
+  const int mE = 2 * mu, mO = 2 * mu + 1;   // mO < K always (K even)
+
+  for (int t = lt; t < N; t += TT) {
+    double2 g = make_double2(0.0, 0.0);
+    if (valid) {
+      const int tt = (t < K) ? t : N - 1 - t;
+      const double sg = (t < K) ? 1.0 : -1.0;
+      const double* rE = GT + ((size_t)tt * K + mE) * C + 2 * s;
+      const double* rO = GT + ((size_t)tt * K + mO) * C + 2 * s;
+      g.x = rE[0] + sg * rO[0];
+      g.y = rE[1] + sg * rO[1];
+    }
+    buf[lds_pad(t)] = g;
+  }
+  __syncthreads();
+  dft4095<false, TT>(buf, lt, w5lo, w5hi);
+
+  constexpr int MAXV = NC / TT;   // 8 >= ceil((2K-1) / TT)
+  constexpr int NJ = 2 * K - 1;
+  double2 keep[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) {
+      const int j = idx - (K - 1);
+      keep[i] = cmul(A.hphase[idx], buf[lds_pad(j < 0 ? j + N : j)]);
+    }
+  }
+#pragma unroll
+  for (int P = 0; P < 2; ++P) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) buf[lds_pad(lt + i * TT)] = make_double2(0.0, 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * TT;
+      if (idx < NJ) {
+        const int j = idx - (K - 1);
+        if (((j - P) & 1) == 0) buf[lds_pad(((j - P) / 2) & (NC - 1))] = keep[i];
+      }
+    }
+    __syncthreads();
+    fft4096<false, TT>(buf, lt, w6lo, w6hi);
+    const double2* kh = P == 0 ? A.khat0 : A.khat1;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int q = lt + i * TT;
+      buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
+    }
+    __syncthreads();
+    fft4096<true, TT>(buf, lt, w6lo, w6hi);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * TT;
+      if (idx < NJ) {
+        const int jp = idx - (K - 1);
+        if (((jp - P) & 1) == 0) keep[i] = cmul(A.hphase[idx], buf[lds_pad((-(jp - P) / 2) & (NC - 1))]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) {
+      const int jp = idx - (K - 1);
+      buf[lds_pad(jp < 0 ? jp + N : jp)] = keep[i];
+    }
+  }
+  __syncthreads();
+  dft4095<false, TT>(buf, lt, w5lo, w5hi);
+
+  if (valid) {
+    for (int t = lt; t < K; t += TT) {
+      const double2 h1 = buf[lds_pad(t)];
+      double2 he = h1, ho = make_double2(0.0, 0.0);
+      if (t < K - 1) {
+        const double2 h2 = buf[lds_pad(N - 1 - t)];
+        he = cadd(h1, h2);
+        ho = csub(h1, h2);
+      }
+      double* wE = HM + ((size_t)mE * K + t) * C + 2 * s;
+      double* wO = HM + ((size_t)mO * K + t) * C + 2 * s;
+      wE[0] = he.x;
+      wE[1] = he.y;
+      wO[0] = ho.x;
+      wO[1] = ho.y;
+    }
+  }
+}
+
+// phi stage, inverse (see k_phi_inverse): FT[(t*k + m)*C + c] -> maps.
+template <int REAL>
+__global__ __launch_bounds__(TT, 4) void k_phi_inverse_2048(K2048Args A, const double* __restrict__ FT,
+                                                            double* __restrict__ f, long long map_stride, int C,
+                                                            int nb, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  stage_tables(A, w6lo, w6hi, w5lo, w5hi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int nunits = REAL ? (nb + 1) / 2 : nb;
+  const int t = valid ? p / nunits : 0;
+  const int u = valid ? p % nunits : 0;
+  const int ma = REAL ? 2 * u : u;
+  const bool hasb = REAL && (ma + 1 < nb);
+
+  for (int q = lt; q < N; q += TT) {
+    double2 z = make_double2(0.0, 0.0);
+    if (valid) {
+      const bool neg = q >= K;
+      const int m = neg ? N - q : q;
+      const double* row = FT + ((size_t)t * K + m) * C;
+      if (REAL) {
+        double2 a = make_double2(row[2 * ma], row[2 * ma + 1]);
+        double2 b = hasb ? make_double2(row[2 * ma + 2], row[2 * ma + 3]) : make_double2(0.0, 0.0);
+        if (neg) {
+          a = conjd(a);
+          b = conjd(b);
+        }
+        z = make_double2(a.x - b.y, a.y + b.x);
+      } else {
+        z = neg ? make_double2(row[4 * ma + 2], row[4 * ma + 3]) : make_double2(row[4 * ma], row[4 * ma + 1]);
+      }
+    }
+    buf[lds_pad(q)] = z;
+  }
+  __syncthreads();
+  dft4095<true, TT>(buf, lt, w5lo, w5hi);
+
+  if (valid) {
+    for (int q = lt; q < N; q += TT) {
+      const double2 v = buf[lds_pad(q)];
+      if (REAL) {
+        f[(size_t)ma * map_stride + (size_t)t * N + q] = v.x;
+        if (hasb) f[(size_t)(ma + 1) * map_stride + (size_t)t * N + q] = v.y;
+      } else {
+        reinterpret_cast<double2*>(f)[(size_t)ma * map_stride + (size_t)t * N + q] = v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+static bool k2048_ok(const ShtTables& T) {
+  return T.k == K && T.n == N && T.nrad == 4 && T.rad[0] == 13 && T.rad[1] == 9 && T.rad[2] == 7 &&
+         T.rad[3] == 5 && T.Nc == NC && T.logP == 12 && T.loglo == 6;
+}
+
+static K2048Args k2048_args(const ShtTables& T) {
+  K2048Args a;
+  a.tw4096_lo = T.tw_lo;
+  a.tw4096_hi = T.tw_hi;
+  a.tw4095_lo = T.twn_lo;
+  a.tw4095_hi = T.twn_hi;
+  a.khat0 = T.khat0;
+  a.khat1 = T.khat1;
+  a.hphase = T.hphase;
+  return a;
+}
+
+bool fft_k2048_applies(const ShtTables& T) { return k2048_ok(T); }
+
+hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                   double* GT, hipStream_t s) {
+  const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
+  const int nprob = K * nunits;
+  const K2048Args a = k2048_args(T);
+  if (b.reality == S2LET_REAL)
+    k_phi_forward_2048<1><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+  else
+    k_phi_forward_2048<0><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s) {
+  const int nprob = (K / 2) * (b.C / 2);
+  k_theta_2048<<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
+                                   int64_t map_stride, hipStream_t s) {
+  const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
+  const int nprob = K * nunits;
+  const K2048Args a = k2048_args(T);
+  if (b.reality == S2LET_REAL)
+    k_phi_inverse_2048<1><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+  else
+    k_phi_inverse_2048<0><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+  return hipGetLastError();
+}
+
+}  // namespace s2let

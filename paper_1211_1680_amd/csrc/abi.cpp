@@ -268,8 +268,10 @@ hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int 
                      const double* kern, int accumulate, hipStream_t s) {
   ProfRec* r = prof_begin(ST_TILE, s);
   if (r) {
+    // coefficients read once, destination written (and read when accumulating, rows < ks only)
     const double kk = std::min(ks, kd);
-    r->bytes = 8.0 * b.used * (kk * (kk + 1) / 2.0 + (double)tri_rows(kd) * (accumulate ? 2.0 : 1.0));
+    const double tk = kk * (kk + 1) / 2.0;
+    r->bytes = 8.0 * b.used * (accumulate ? 3.0 * tk : tk + (double)tri_rows(kd));
   }
   hipError_t e = launch_tile(G, b, src, ks, nparts_of(ks), pstride_of(ks, b), dst, kd, kern, accumulate, s);
   prof_end(r, s);

@@ -77,14 +77,15 @@ __global__ void k_pack(const double* __restrict__ R, int nparts, long long pstri
   }
 }
 
-// dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks); rows l >= ks of dst are
-// zero-filled (when not accumulating).
+// dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks).  Without accumulation the
+// rows l >= ks of dst are zero-filled; with accumulation they are left alone (they would only
+// receive zeros), so rows and columns m >= ks are not visited at all (klim = min(ks, kd)).
 __global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long long pstride,
-                       double* __restrict__ dst, int kd, const double* __restrict__ kern,
+                       double* __restrict__ dst, int kd, int klim, const double* __restrict__ kern,
                        const double* __restrict__ dfac, int Lt, int C, int accumulate) {
   const int m = blockIdx.y;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int len = kd - m;
+  const int len = klim - m;
   if (len <= 0 || idx >= len * C) return;
   const int r = idx / C, c = idx % C;
   const int l = m + r;
@@ -122,8 +123,9 @@ hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const doub
 hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, int nparts,
                        long long part_stride, double* dst, int kd, const double* kern, int accumulate,
                        hipStream_t s) {
-  dim3 grid((kd * b.C + 255) / 256, kd);
-  k_tile<<<grid, 256, 0, s>>>(src, ks, nparts, part_stride, dst, kd, kern, G.dfac, G.Lt, b.C, accumulate);
+  const int klim = accumulate ? (ks < kd ? ks : kd) : kd;
+  dim3 grid((klim * b.C + 255) / 256, klim);
+  k_tile<<<grid, 256, 0, s>>>(src, ks, nparts, part_stride, dst, kd, klim, kern, G.dfac, G.Lt, b.C, accumulate);
   return hipGetLastError();
 }
 

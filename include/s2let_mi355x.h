@@ -115,6 +115,35 @@ int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L
                            int J_min, int multires, int reality, int precision, int nmaps,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* Adjoints, for gradients of losses through the transforms.  Each is the adjoint of the linear
+ * map computed by the corresponding call above, with respect to the real inner products
+ * <f, g> = sum over every stored sample of f g (real maps; Re sum conj(f) g for complex maps,
+ * the 2k-1 stored copies of the south pole counted separately) and <a, b> = Re sum_{l,m}
+ * conj(a_lm) b_lm over the full [L*L] coefficient array.  Same layouts, workspace and errors
+ * as the transforms; output first.
+ *
+ * mw_inverse_adjoint: flm = S^H f with S the inverse transform of Eq. (1):
+ *   flm_lm = sum_{t,p} conj(Y_lm(theta_t, phi_p)) f(theta_t, phi_p).
+ * mw_forward_adjoint: f = A^H flm with A the MW quadrature (mw_forward).  For real maps the
+ *   result is the real part of A^H flm, i.e. A^H applied to the Hermitian part
+ *   (flm_lm + (-1)^m conj flm_{l,-m}) / 2; all L*L coefficients are read. */
+int mw_inverse_adjoint(void* flm, const void* f, int L, int reality, int precision, int nmaps,
+                       void* ws, size_t ws_bytes, void* stream);
+int mw_forward_adjoint(void* f, const void* flm, int L, int reality, int precision, int nmaps,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of s2let_axisym_analysis: f = W^H (f_wav, f_scal), with W the map of Eqs. (4), (6).
+ * Layouts as in s2let_axisym_synthesis (f is the output). */
+int s2let_axisym_analysis_adjoint(void* f, const void* f_wav, const void* f_scal, int L, int B,
+                                  int J_min, int multires, int reality, int precision, int nmaps,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of s2let_axisym_synthesis (Eq. (8)): (f_wav, f_scal) = Y^H f.  Layouts as in
+ * s2let_axisym_analysis (f_wav and f_scal are the outputs). */
+int s2let_axisym_synthesis_adjoint(void* f_wav, void* f_scal, const void* f, int L, int B,
+                                   int J_min, int multires, int reality, int precision, int nmaps,
+                                   void* ws, size_t ws_bytes, void* stream);
+
 /* Measurement support.  s2let_profile_enable(1) clears previous records and, until
  * s2let_profile_enable(0), brackets every kernel launch of the calls above with a pair of HIP
  * events recorded on the launch stream; the Legendre kernels also count the (l, theta) pairs they

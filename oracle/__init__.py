@@ -251,6 +251,71 @@ def forward_sht(f: np.ndarray, k: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------------------
+# Adjoints of the two transforms (for gradients through them).  Inner products: the plain sum
+# over every stored sample for maps (Re sum conj(a) b for complex maps), Re sum conj(a) b over
+# the full [k*k] array for coefficients.
+# ----------------------------------------------------------------------------------------
+def inverse_sht_adjoint(f: np.ndarray, k: int, reality: bool = False) -> np.ndarray:
+    """S^H f with S the inverse transform of Eq. (1) on the MW grid:
+    g_lm = sum_{t,p} conj(Y_lm(theta_t, phi_p)) f(theta_t, phi_p)
+         = sum_t lambda_lm(theta_t) sum_p f(theta_t, phi_p) e^{-i m phi_p}.
+    The sum over p by library FFT (no weight), the Legendre sum in C.  [nmaps, k*k]."""
+    f = np.asarray(f)
+    if f.ndim == 2:
+        f = f[None]
+    n = 2 * k - 1
+    if f.shape[1:] != (k, n):
+        raise ValueError("map must be [k, 2k-1]")
+    ms = np.arange(-(k - 1), k)
+    Gu = np.ascontiguousarray(np.fft.fft(f.astype(np.complex128), axis=-1)[..., ms % n])
+    flm = np.zeros((f.shape[0], k * k), dtype=np.complex128)
+    _load().orc_legendre_forward(k, f.shape[0], _dp(Gu.view(np.float64)), _dp(flm.view(np.float64)))
+    return flm
+
+
+def forward_sht_adjoint(flm: np.ndarray, k: int, reality: bool = False) -> np.ndarray:
+    """A^H y with A the MW quadrature (forward_sht): the transposes of its steps 7..1 in reverse
+    order (real part for real maps).  [nmaps, k, 2k-1]."""
+    y = _as_maps(flm, k)
+    nmaps = y.shape[0]
+    n = 2 * k - 1
+    ms = np.arange(-(k - 1), k)
+    eps = np.where(ms % 2 == 0, 1.0, -1.0)
+    js = np.arange(-(k - 1), k)
+    # 7^H: F_m(theta_t) = sum_l lambda_lm(theta_t) y_lm   (t < k)
+    F = np.zeros((nmaps, k, n), dtype=np.complex128)
+    _load().orc_legendre_inverse(k, nmaps, _dp(y.view(np.float64)), _dp(F.view(np.float64)))
+    # 6^H: the fold's transpose puts F[t] at t and eps F[t] at n-1-t (t < k-1)
+    Hb = np.zeros((nmaps, n, n), dtype=np.complex128)
+    Hb[:, :k, :] = F
+    if k > 1:
+        t = np.arange(k - 1)
+        Hb[:, n - 1 - t, :] = eps[None, None, :] * F[:, t, :]
+    # 5^H: H = fft(spec)/n  ->  spec_bar = ifft(H_bar); I_bar = conj(phase) spec_bar
+    spec_b = np.fft.ifft(Hb, axis=1)
+    Ib = np.exp(1j * np.pi * js / n)[None, :, None] * spec_b[:, js % n, :]
+    # 4^H: Ghat_bar = W^H I_bar with W[j', j] = w(j + j')
+    P = js[:, None] + js[None, :]
+    W = quadrature_weight(P)
+    WH = np.ascontiguousarray(W.conj().T)
+    Gb_hat = np.einsum("ab,xbm->xam", WH, Ib)
+    # 3^H: Ghat = phase D / n, D = fft(g) at js  ->  g_bar = n ifft(conj(phase) Ghat_bar / n)
+    Db = np.zeros((nmaps, n, n), dtype=np.complex128)
+    Db[:, js % n, :] = np.exp(1j * np.pi * js / n)[None, :, None] * Gb_hat / n
+    gb = np.fft.ifft(Db, axis=1) * n
+    # 2^H: the extension's transpose folds g_bar back onto t < k
+    Gb = gb[:, :k, :].copy()
+    if k > 1:
+        t = np.arange(k - 1)
+        Gb[:, t, :] += eps[None, None, :] * gb[:, n - 1 - t, :]
+    # 1^H: f(theta_t, phi_p) = (2 pi / n) sum_m G_bar_m e^{i m phi_p}
+    spec = np.zeros((nmaps, k, n), dtype=np.complex128)
+    spec[..., ms % n] = Gb
+    f = (2.0 * np.pi / n) * np.fft.ifft(spec, axis=-1) * n
+    return f.real.copy() if reality else f
+
+
+# ----------------------------------------------------------------------------------------
 # Scale-discretised tiling, Eqs. (10)-(16)
 # ----------------------------------------------------------------------------------------
 def j_max(L: int, B: int) -> int:
@@ -427,6 +492,34 @@ def synthesis(wav, scal, L: int, B: int, J_min: int, multires: bool, reality: bo
               for j, w in zip(range(J_min, J + 1), wav)]
     flm = synthesis_harmonic(wav_lm, scal_lm, L, B, J_min, multires)
     return inverse_sht(flm, L, reality)
+
+
+def analysis_adjoint(wav, scal, L: int, B: int, J_min: int, multires: bool, reality: bool) -> np.ndarray:
+    """Adjoint of analysis: A^H ( eta ext(S_Phi^H scal) + sum_j kappa_j ext(S_j^H wav_j) )."""
+    kappa, eta = tiling(L, B, J_min)
+    ell = _ell_of_index(L)
+    J = j_max(L, B)
+    kP = bandlimit_scal(J_min, L, B, multires)
+    acc = _extend(inverse_sht_adjoint(scal, kP, reality), kP, L) * eta[ell][None, :]
+    for j, w in zip(range(J_min, J + 1), wav):
+        kj = bandlimit_wav(j, L, B, multires)
+        acc = acc + _extend(inverse_sht_adjoint(w, kj, reality), kj, L) * kappa[j - J_min][ell][None, :]
+    return forward_sht_adjoint(acc, L, reality)
+
+
+def synthesis_adjoint(f: np.ndarray, L: int, B: int, J_min: int, multires: bool, reality: bool):
+    """Adjoint of synthesis: g = S_L^H f, then A_Phi^H trunc(eta g) and A_j^H trunc(kappa_j g)."""
+    kappa, eta = tiling(L, B, J_min)
+    ell = _ell_of_index(L)
+    J = j_max(L, B)
+    kP = bandlimit_scal(J_min, L, B, multires)
+    g = inverse_sht_adjoint(f, L, reality)
+    scal = forward_sht_adjoint(_truncate(g * eta[ell][None, :], L, kP), kP, reality)
+    wav = []
+    for j in range(J_min, J + 1):
+        kj = bandlimit_wav(j, L, B, multires)
+        wav.append(forward_sht_adjoint(_truncate(g * kappa[j - J_min][ell][None, :], L, kj), kj, reality))
+    return wav, scal
 
 
 # ----------------------------------------------------------------------------------------

@@ -17,6 +17,7 @@ __all__ = [
     "REAL", "COMPLEX", "FP64", "MIXED_FP32", "MIXED_BF16X3", "MAX_L", "S2letError", "lib",
     "j_max", "bandlimit_wav", "bandlimit_scal", "mw_size", "wav_size", "tiling_axisym",
     "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
+    "mw_forward_adjoint", "mw_inverse_adjoint", "analysis_adjoint", "synthesis_adjoint",
     "profile_enable", "profile_query", "STAGES",
 ]
 
@@ -55,6 +56,10 @@ def _load():
         "mw_inverse": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_analysis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_synthesis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
+        "mw_forward_adjoint": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
+        "mw_inverse_adjoint": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
+        "s2let_axisym_analysis_adjoint": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
+        "s2let_axisym_synthesis_adjoint": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
         "s2let_sync": (i, [vp]),
         "s2let_profile_enable": (i, [i]),
         "s2let_profile_query": (i, [i, dp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp]),
@@ -242,6 +247,87 @@ def synthesis(f_wav, f_scal, L: int, B: int, J_min: int, multires: bool = True,
                                        ws.numel() * ws.element_size(), _stream(f_wav.device)),
            "s2let_axisym_synthesis")
     return f
+
+
+def mw_inverse_adjoint(f, L: int, reality: int = REAL, precision: int = FP64, workspace=None):
+    """Adjoint of mw_inverse: f [nmaps, L, 2L-1] -> flm [nmaps, L*L], flm = S^H f."""
+    torch = _torch()
+    _need_cuda(f, "f", _map_dtype(reality))
+    nmaps = f.shape[0] if f.dim() == 3 else 1
+    if f.numel() != nmaps * mw_size(L):
+        raise ValueError("f must hold nmaps * L * (2L-1) samples")
+    flm = torch.empty((nmaps, L * L), dtype=torch.complex128, device=f.device)
+    ws = _workspace(workspace_size(L, reality=reality, precision=precision, nmaps=nmaps), f.device,
+                    workspace)
+    _check(_lib.mw_inverse_adjoint(flm.data_ptr(), f.data_ptr(), L, reality, precision, nmaps,
+                                   ws.data_ptr(), ws.numel() * ws.element_size(), _stream(f.device)),
+           "mw_inverse_adjoint")
+    return flm
+
+
+def mw_forward_adjoint(flm, L: int, reality: int = REAL, precision: int = FP64, workspace=None):
+    """Adjoint of mw_forward: flm [nmaps, L*L] complex128 -> f [nmaps, L, 2L-1], f = A^H flm
+    (its real part for REAL maps)."""
+    torch = _torch()
+    _need_cuda(flm, "flm", torch.complex128)
+    nmaps = flm.shape[0] if flm.dim() == 2 else 1
+    if flm.numel() != nmaps * L * L:
+        raise ValueError("flm must hold nmaps * L * L coefficients")
+    f = torch.empty((nmaps, L, 2 * L - 1), dtype=_map_dtype(reality), device=flm.device)
+    ws = _workspace(workspace_size(L, reality=reality, precision=precision, nmaps=nmaps),
+                    flm.device, workspace)
+    _check(_lib.mw_forward_adjoint(f.data_ptr(), flm.data_ptr(), L, reality, precision, nmaps,
+                                   ws.data_ptr(), ws.numel() * ws.element_size(), _stream(flm.device)),
+           "mw_forward_adjoint")
+    return f
+
+
+def analysis_adjoint(f_wav, f_scal, L: int, B: int, J_min: int, multires: bool = True,
+                     reality: int = REAL, precision: int = FP64, workspace=None, out=None):
+    """Adjoint of analysis: (f_wav, f_scal) -> f [nmaps, L, 2L-1]."""
+    torch = _torch()
+    dt = _map_dtype(reality)
+    _need_cuda(f_wav, "f_wav", dt)
+    _need_cuda(f_scal, "f_scal", dt)
+    nmaps = f_wav.shape[0] if f_wav.dim() == 2 else 1
+    if f_wav.numel() != nmaps * wav_size(L, B, J_min, multires):
+        raise ValueError("f_wav has the wrong size")
+    if f_scal.numel() != nmaps * mw_size(bandlimit_scal(J_min, L, B, multires)):
+        raise ValueError("f_scal has the wrong size")
+    f = out if out is not None else torch.empty((nmaps, L, 2 * L - 1), dtype=dt, device=f_wav.device)
+    ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
+                    f_wav.device, workspace)
+    _check(_lib.s2let_axisym_analysis_adjoint(f.data_ptr(), f_wav.data_ptr(), f_scal.data_ptr(), L, B,
+                                              J_min, int(multires), reality, precision, nmaps,
+                                              ws.data_ptr(), ws.numel() * ws.element_size(),
+                                              _stream(f_wav.device)),
+           "s2let_axisym_analysis_adjoint")
+    return f
+
+
+def synthesis_adjoint(f, L: int, B: int, J_min: int, multires: bool = True, reality: int = REAL,
+                      precision: int = FP64, workspace=None, out=None):
+    """Adjoint of synthesis: f [nmaps, L, 2L-1] -> (f_wav, f_scal)."""
+    torch = _torch()
+    dt = _map_dtype(reality)
+    _need_cuda(f, "f", dt)
+    nmaps = f.shape[0] if f.dim() == 3 else 1
+    if f.numel() != nmaps * mw_size(L):
+        raise ValueError("f must hold nmaps * L * (2L-1) samples")
+    kP = bandlimit_scal(J_min, L, B, multires)
+    if out is None:
+        f_wav = torch.empty((nmaps, wav_size(L, B, J_min, multires)), dtype=dt, device=f.device)
+        f_scal = torch.empty((nmaps, mw_size(kP)), dtype=dt, device=f.device)
+    else:
+        f_wav, f_scal = out
+    ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
+                    f.device, workspace)
+    _check(_lib.s2let_axisym_synthesis_adjoint(f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), L, B,
+                                               J_min, int(multires), reality, precision, nmaps,
+                                               ws.data_ptr(), ws.numel() * ws.element_size(),
+                                               _stream(f.device)),
+           "s2let_axisym_synthesis_adjoint")
+    return f_wav, f_scal
 
 
 def split_wav(f_wav, L: int, B: int, J_min: int, multires: bool = True):

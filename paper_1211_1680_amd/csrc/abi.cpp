@@ -211,8 +211,12 @@ int ensure_wav(DevCache& dc, int L, int B, int J_min, WavTables** out) {
 // ---- the harmonic transforms on one batch ----
 double triples_of(int k) { return (double)k * (double)k * (double)(k + 1) / 2.0; }
 
+// Maps -> partial Legendre sums R.  adjoint = false: the forward transform (phi DFT, theta
+// quadrature, Legendre analysis).  adjoint = true: the adjoint of the inverse transform,
+// g_lm = sum_{t,p} conj(Y_lm(theta_t, phi_p)) f(theta_t, phi_p): the phi DFT without its 2 pi/n
+// weight, no theta quadrature, the same Legendre analysis.
 int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const void* f,
-                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s) {
+                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false) {
   hipError_t e;
   const double k = T.k, n = T.n;
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
@@ -223,7 +227,11 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   prof_end(r, s);
   r = prof_begin(ST_THETA, s);
   if (r) r->bytes = 2.0 * colb;
-  if ((e = launch_theta(T, b, w.GT, w.HM, s)) != hipSuccess) return to_status(e);
+  if (adjoint)
+    e = launch_transpose_rows(b, T.k, w.GT, w.HM, n / (2.0 * M_PI), s);
+  else
+    e = launch_theta(T, b, w.GT, w.HM, s);
+  if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
   r = prof_begin(ST_LEG_FWD, s);
   if (r) {
@@ -240,8 +248,12 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   return S2LET_OK;
 }
 
+// Scaled coefficients S -> maps.  adjoint = false: the inverse transform (Legendre synthesis,
+// inverse phi DFT).  adjoint = true: the adjoint of the forward transform: Legendre synthesis,
+// the theta quadrature (a real symmetric operator per m, its own transpose), and the inverse phi
+// DFT times the phi weight 2 pi/n.
 int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const double* S, void* f,
-                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s) {
+                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false) {
   hipError_t e;
   const double k = T.k, n = T.n;
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
@@ -257,6 +269,13 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   if ((e = launch_legendre_inverse(T, G, b, S, w.GT, precision, prof_counter(r), s)) != hipSuccess)
     return to_status(e);
   prof_end(r, s);
+  if (adjoint) {
+    r = prof_begin(ST_THETA, s);
+    if (r) r->bytes = 4.0 * colb;
+    if ((e = launch_theta(T, b, w.GT, w.HM, s)) != hipSuccess) return to_status(e);
+    if ((e = launch_transpose_rows(b, T.k, w.HM, w.GT, 2.0 * M_PI / n, s)) != hipSuccess) return to_status(e);
+    prof_end(r, s);
+  }
   r = prof_begin(ST_PHI_INV, s);
   if (r) r->bytes = mapb + colb;
   if ((e = launch_phi_inverse(T, b, w.GT, f, map_stride, s)) != hipSuccess) return to_status(e);
@@ -360,8 +379,10 @@ static int prologue(int L, int reality, int precision, int nmaps, void* ws, size
   return get_device(dev);
 }
 
-S2LET_API int mw_forward(void* flm, const void* f, int L, int reality, int precision, int nmaps,
-                         void* ws, size_t ws_bytes, void* stream) {
+// Maps -> coefficients: the forward transform (adjoint = false) or the adjoint of the inverse
+// transform (adjoint = true).
+static int sht_maps_to_coefs(void* flm, const void* f, int L, int reality, int precision, int nmaps, void* ws,
+                             size_t ws_bytes, void* stream, bool adjoint) {
   if (!flm || !f || !aligned16(flm) || !aligned16(f)) return S2LET_EINVAL;
   int dev;
   int st = prologue(L, reality, precision, nmaps, ws, ws_bytes, false, &dev);
@@ -379,7 +400,7 @@ S2LET_API int mw_forward(void* flm, const void* f, int L, int reality, int preci
     const Batch b = make_batch(reality, std::min(cap, nmaps - start));
     const Workspace w = carve(ws, L, b.C, false);
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
-    if ((st = forward_batch(*T, dc.leg, b, fin, msz, w, precision, s)) != S2LET_OK) return st;
+    if ((st = forward_batch(*T, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
     double2* out = (double2*)flm + (size_t)start * L * L;
     hipError_t e = launch_pack_flm(dc.leg, b, L, w.R, nparts_of(L), pstride_of(L, b), out, s);
     if (e != hipSuccess) return S2LET_EHIP;
@@ -387,8 +408,11 @@ S2LET_API int mw_forward(void* flm, const void* f, int L, int reality, int preci
   return S2LET_OK;
 }
 
-S2LET_API int mw_inverse(void* f, const void* flm, int L, int reality, int precision, int nmaps,
-                         void* ws, size_t ws_bytes, void* stream) {
+// Coefficients -> maps: the inverse transform (adjoint = false) or the adjoint of the forward
+// transform (adjoint = true; for real maps the coefficients are first replaced by their Hermitian
+// part, which makes the result the adjoint with respect to the real inner products).
+static int sht_coefs_to_maps(void* f, const void* flm, int L, int reality, int precision, int nmaps, void* ws,
+                             size_t ws_bytes, void* stream, bool adjoint) {
   if (!flm || !f || !aligned16(flm) || !aligned16(f)) return S2LET_EINVAL;
   int dev;
   int st = prologue(L, reality, precision, nmaps, ws, ws_bytes, false, &dev);
@@ -406,17 +430,40 @@ S2LET_API int mw_inverse(void* f, const void* flm, int L, int reality, int preci
     const Batch b = make_batch(reality, std::min(cap, nmaps - start));
     const Workspace w = carve(ws, L, b.C, false);
     const double2* in = (const double2*)flm + (size_t)start * L * L;
-    hipError_t e = launch_unpack_flm(dc.leg, b, L, in, w.S, s);
+    hipError_t e = launch_unpack_flm(dc.leg, b, L, in, w.S, s, adjoint);
     if (e != hipSuccess) return S2LET_EHIP;
     double* fout = (double*)f + (size_t)start * msz * cmul;
-    if ((st = inverse_batch(*T, dc.leg, b, w.S, fout, msz, w, precision, s)) != S2LET_OK) return st;
+    if ((st = inverse_batch(*T, dc.leg, b, w.S, fout, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
   }
   return S2LET_OK;
 }
 
-S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
-                                    int multires, int reality, int precision, int nmaps, void* ws,
-                                    size_t ws_bytes, void* stream) {
+S2LET_API int mw_forward(void* flm, const void* f, int L, int reality, int precision, int nmaps,
+                         void* ws, size_t ws_bytes, void* stream) {
+  return sht_maps_to_coefs(flm, f, L, reality, precision, nmaps, ws, ws_bytes, stream, false);
+}
+
+S2LET_API int mw_inverse(void* f, const void* flm, int L, int reality, int precision, int nmaps,
+                         void* ws, size_t ws_bytes, void* stream) {
+  return sht_coefs_to_maps(f, flm, L, reality, precision, nmaps, ws, ws_bytes, stream, false);
+}
+
+S2LET_API int mw_inverse_adjoint(void* flm, const void* f, int L, int reality, int precision, int nmaps,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  return sht_maps_to_coefs(flm, f, L, reality, precision, nmaps, ws, ws_bytes, stream, true);
+}
+
+S2LET_API int mw_forward_adjoint(void* f, const void* flm, int L, int reality, int precision, int nmaps,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  return sht_coefs_to_maps(f, flm, L, reality, precision, nmaps, ws, ws_bytes, stream, true);
+}
+
+// Map at L -> wavelet and scaling maps.  adjoint = false: the analysis, Eqs. (4) and (6).
+// adjoint = true: the adjoint of the synthesis of Eq. (8) (inverse-transform adjoint at L, the
+// real diagonal kernels and truncation, forward-transform adjoints at each scale).
+static int wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min, int multires,
+                             int reality, int precision, int nmaps, void* ws, size_t ws_bytes, void* stream,
+                             bool adjoint) {
   if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
     return S2LET_EINVAL;
   int st = check_wavelet(L, B, J_min, multires);
@@ -448,12 +495,12 @@ S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, in
     const Batch b = make_batch(reality, std::min(cap, nmaps - start));
     const Workspace w = carve(ws, L, b.C, true);
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
-    if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s)) != S2LET_OK) return st;
+    if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
     // scaling part, Eq. (6)
     hipError_t e = tile_prof(dc.leg, b, w.R, L, w.S, kP, W->eta, 0, s);
     if (e != hipSuccess) return S2LET_EHIP;
     double* pout = (double*)f_scal + (size_t)start * psz * cmul;
-    if ((st = inverse_batch(*TP, dc.leg, b, w.S, pout, psz, w, precision, s)) != S2LET_OK) return st;
+    if ((st = inverse_batch(*TP, dc.leg, b, w.S, pout, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
     // wavelet scales, Eq. (4)
     int64_t off = 0;
     for (int j = J_min; j <= J; ++j) {
@@ -461,7 +508,7 @@ S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, in
       e = tile_prof(dc.leg, b, w.R, L, w.S, kj, W->kappa + (size_t)(j - J_min) * L, 0, s);
       if (e != hipSuccess) return S2LET_EHIP;
       double* wout = (double*)f_wav + ((size_t)start * wsz + off) * cmul;
-      if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s)) != S2LET_OK)
+      if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s, adjoint)) != S2LET_OK)
         return st;
       off += (int64_t)kj * (2 * kj - 1);
     }
@@ -469,9 +516,12 @@ S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, in
   return S2LET_OK;
 }
 
-S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L, int B,
-                                     int J_min, int multires, int reality, int precision, int nmaps,
-                                     void* ws, size_t ws_bytes, void* stream) {
+// Wavelet and scaling maps -> map at L.  adjoint = false: the synthesis, Eq. (8).  adjoint =
+// true: the adjoint of the analysis (inverse-transform adjoints at each scale, the kernels,
+// forward-transform adjoint at L).
+static int wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int L, int B, int J_min,
+                             int multires, int reality, int precision, int nmaps, void* ws, size_t ws_bytes,
+                             void* stream, bool adjoint) {
   if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
     return S2LET_EINVAL;
   int st = check_wavelet(L, B, J_min, multires);
@@ -504,7 +554,7 @@ S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_s
     const Workspace w = carve(ws, L, b.C, true);
     // scaling part
     const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
-    if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s)) != S2LET_OK) return st;
+    if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
     hipError_t e = tile_prof(dc.leg, b, w.R, kP, w.S, L, W->eta, 0, s);
     if (e != hipSuccess) return S2LET_EHIP;
     // wavelet scales, accumulated per Eq. (8)
@@ -512,15 +562,44 @@ S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_s
     for (int j = J_min; j <= J; ++j) {
       const int kj = bl_wav(j, L, B, multires);
       const double* win = (const double*)f_wav + ((size_t)start * wsz + off) * cmul;
-      if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s)) != S2LET_OK) return st;
+      if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s, adjoint)) != S2LET_OK)
+        return st;
       e = tile_prof(dc.leg, b, w.R, kj, w.S, L, W->kappa + (size_t)(j - J_min) * L, 1, s);
       if (e != hipSuccess) return S2LET_EHIP;
       off += (int64_t)kj * (2 * kj - 1);
     }
     double* fout = (double*)f + (size_t)start * msz * cmul;
-    if ((st = inverse_batch(*TL, dc.leg, b, w.S, fout, msz, w, precision, s)) != S2LET_OK) return st;
+    if ((st = inverse_batch(*TL, dc.leg, b, w.S, fout, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
   }
   return S2LET_OK;
+}
+
+S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                                    int multires, int reality, int precision, int nmaps, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  return wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, false);
+}
+
+S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L, int B,
+                                     int J_min, int multires, int reality, int precision, int nmaps,
+                                     void* ws, size_t ws_bytes, void* stream) {
+  return wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, false);
+}
+
+S2LET_API int s2let_axisym_analysis_adjoint(void* f, const void* f_wav, const void* f_scal, int L, int B,
+                                            int J_min, int multires, int reality, int precision, int nmaps,
+                                            void* ws, size_t ws_bytes, void* stream) {
+  return wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, true);
+}
+
+S2LET_API int s2let_axisym_synthesis_adjoint(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                                             int multires, int reality, int precision, int nmaps, void* ws,
+                                             size_t ws_bytes, void* stream) {
+  return wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, true);
 }
 
 S2LET_API int s2let_profile_enable(int on) {

@@ -58,6 +58,7 @@ struct ShtTables {
   double* st = nullptr;        // sin(theta_t), t < k
   double* ut = nullptr;        // |cos(theta_t)| - 1 = -2 sin^2(theta'/2), theta' = min(theta, pi - theta)
   double* sx = nullptr;        // sign of cos(theta_t) (+1 at the equator)
+  double* pole = nullptr;      // column t = k-1 of the odd-parity theta operator (see plan.cpp)
   double2* hphase = nullptr;   // exp(-i pi j / n) for j in [-(k-1), k-1], index j+k-1
 };
 
@@ -115,9 +116,12 @@ hipError_t launch_legendre_forward_bf16(const ShtTables& T, const LegTables& G, 
 hipError_t launch_legendre_inverse_bf16(const ShtTables& T, const LegTables& G, const Batch& b,
                                         const double* S, double* FT, unsigned long long* counter,
                                         hipStream_t s);
+// dst[b][a][c] = scale * src[a][b][c] over a k x k grid of C-column rows.
+hipError_t launch_transpose_rows(const Batch& b, int k, const double* src, double* dst, double scale,
+                                 hipStream_t s);
 // flm (user layout) -> S (k-packed rows, scaled by d_lm, -m columns by (-1)^m).
 hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm,
-                             double* S, hipStream_t s);
+                             double* S, hipStream_t s, bool herm = false);
 // R (k-packed raw forward sums, nparts partials) -> flm (user layout): f_lm = d_lm sum_g R_g
 // (and the symmetry for real maps).
 hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, int nparts,

@@ -116,6 +116,30 @@ struct SmallDft<16, INV> {
   }
 };
 
+// Sum of v over the T threads of one problem (T a power of two; problems occupy consecutive
+// threads of the workgroup), in a fixed order so that equal inputs give equal sums.  Every
+// thread of the workgroup must call it (it synchronises when T > 64); scratch holds one value per
+// wave of the workgroup (at most 8).
+__device__ __forceinline__ double2 problem_sum(double2 v, int T, double2* scratch) {
+  const int w = T < 64 ? T : 64;
+  for (int off = w >> 1; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
+  if (T <= 64) return v;
+  const int wave = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[wave] = v;
+  __syncthreads();
+  const int nw = T >> 6, first = (wave / nw) * nw;
+  double2 s = make_double2(0.0, 0.0);
+  for (int i = 0; i < nw; ++i) {
+    s.x += scratch[first + i].x;
+    s.y += scratch[first + i].y;
+  }
+  return s;
+}
+
 // W^p (sign chosen by INV) from a two-level table: W^p = lo[p mod 2^loglo] * hi[p >> loglo].
 template <bool INV>
 __device__ __forceinline__ double2 twiddle(int p, const double2* __restrict__ tlo,

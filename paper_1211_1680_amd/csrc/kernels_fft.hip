@@ -34,6 +34,7 @@ struct FftArgs {
   const double2* tw_hi;
   int loglo, logP;
   const double2* hphase;     // exp(-i pi j/n), j in [-(k-1), k-1]
+  const double* pole;        // pole column of the odd-parity theta operator
   int T, P, buf;             // threads per problem, problems per block, LDS values per problem
 };
 
@@ -143,11 +144,18 @@ __global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __
 //   I_j' = sum_j u_j w_e(j + j')               (w_e(p) = 2/(1-p^2) for even p, 0 for odd p)
 //   H_t  = sum_j' e^{-i pi j'/n} I_j' e^{-2 pi i j' t/n} / n^2
 // and the fold H'_E(t) = H_t + H_{n-1-t}, H'_O(t) = H_t - H_{n-1-t} (t < k-1).
+// The weight's odd p = +-1 terms, left out of the correlation, act on odd m only through the
+// south-pole sample: the odd pole value G_O(k-1) stays out of the packed transform and the
+// operator's pole row and column are applied directly (H'_O(t) += c_t G_O(k-1) for t < k-1,
+// H'_O(k-1) = sum_{t<k-1} c_t G_O(t) + c_{k-1} G_O(k-1), c = A.pole).  For band-limited maps
+// G_O(k-1) = 0 and lambda_lm(pi) = 0 for m != 0, so the correction matters for other inputs and
+// for the adjoint transform, which applies the same operator.
 // ------------------------------------------------------------------------------------------
 template <int VPT>
 __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restrict__ GT,
                                                double* __restrict__ HM, int C, int nprob) {
   extern __shared__ double2 smem[];
+  __shared__ double2 red_scratch[8];
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
   const int pl = threadIdx.x / A.T, lt = threadIdx.x % A.T;
   const int p = blk * A.P + pl;
@@ -160,7 +168,9 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
   const int mE = 2 * mu, mO = 2 * mu + 1;
   const bool hasO = mO < k;
 
-  // packed extension g_t = G_E(t) + G_O(t) (t < k);  G_E(n-1-t) - G_O(n-1-t) (t >= k)
+  // packed extension g_t = G_E(t) + G_O(t) (t < k);  G_E(n-1-t) - G_O(n-1-t) (t >= k), without
+  // the odd pole value; racc accumulates the pole row sum_{t<k-1} c_t G_O(t)
+  double2 racc = make_double2(0.0, 0.0);
   for (int t = lt; t < n; t += A.T) {
     double2 g = make_double2(0.0, 0.0);
     if (valid) {
@@ -169,14 +179,19 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
       const double* rE = GT + ((size_t)tt * k + mE) * C + 2 * s;
       g.x = rE[0];
       g.y = rE[1];
-      if (hasO) {
+      if (hasO && tt < k - 1) {
         const double* rO = GT + ((size_t)tt * k + mO) * C + 2 * s;
         g.x += sg * rO[0];
         g.y += sg * rO[1];
+        if (t < k - 1) {
+          racc.x = fma(A.pole[t], rO[0], racc.x);
+          racc.y = fma(A.pole[t], rO[1], racc.y);
+        }
       }
     }
     buf[t] = g;
   }
+  const double2 prow = problem_sum(racc, A.T, red_scratch);
   __syncthreads();
   dft_odd<false, VPT>(buf, A, lt);
 
@@ -234,15 +249,24 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
   __syncthreads();
   dft_odd<false, VPT>(buf, A, lt);
 
-  // fold onto t < k and separate the even and odd m
+  // fold onto t < k and separate the even and odd m; pole row and column of the odd operator
   if (valid) {
+    double2 pO = make_double2(0.0, 0.0);
+    if (hasO) {
+      const double* rO = GT + ((size_t)(k - 1) * k + mO) * C + 2 * s;
+      pO = make_double2(rO[0], rO[1]);
+    }
     for (int t = lt; t < k; t += A.T) {
       const double2 h1 = buf[t];
-      double2 he = h1, ho = make_double2(0.0, 0.0);
+      double2 he = h1, ho;
       if (t < k - 1) {
         const double2 h2 = buf[n - 1 - t];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
+        ho.x = fma(A.pole[t], pO.x, ho.x);
+        ho.y = fma(A.pole[t], pO.y, ho.y);
+      } else {
+        ho = make_double2(fma(A.pole[t], pO.x, prow.x), fma(A.pole[t], pO.y, prow.y));
       }
       double* wE = HM + ((size_t)mE * k + t) * C + 2 * s;
       wE[0] = he.x;
@@ -341,6 +365,7 @@ static FftArgs fft_args(const ShtTables& T, bool theta) {
   a.loglo = T.loglo;
   a.logP = T.logP;
   a.hphase = T.hphase;
+  a.pole = T.pole;
   int need = a.mixed ? a.n : a.M;          // LDS values of the odd-length DFT
   if (theta && a.Nc > need) need = a.Nc;
   const int vpt = need > 4096 ? 16 : 8;

@@ -25,6 +25,7 @@ struct K2048Args {
   const double2* khat0;
   const double2* khat1;
   const double2* hphase;
+  const double* pole;         // pole column of the odd-parity theta operator
 };
 
 __device__ __forceinline__ void stage_tables(const K2048Args& A, double2* w6lo, double2* w6hi, double2* w5lo,
@@ -101,6 +102,8 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
                                                       double* __restrict__ HM, int C, int nprob) {
   __shared__ double2 buf[NBUF];
   __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  __shared__ double2 red_scratch[8];
+  __shared__ double2 prow_s;   // pole row sum, kept in LDS through the transforms
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
@@ -110,17 +113,31 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
   const int s = valid ? p % ns : 0;
   const int mE = 2 * mu, mO = 2 * mu + 1;   // mO < K always (K even)
 
+  // packed extension without the odd pole value (applied by the pole correction, see k_theta)
+  double2 racc = make_double2(0.0, 0.0);
   for (int t = lt; t < N; t += TT) {
     double2 g = make_double2(0.0, 0.0);
     if (valid) {
       const int tt = (t < K) ? t : N - 1 - t;
       const double sg = (t < K) ? 1.0 : -1.0;
       const double* rE = GT + ((size_t)tt * K + mE) * C + 2 * s;
-      const double* rO = GT + ((size_t)tt * K + mO) * C + 2 * s;
-      g.x = rE[0] + sg * rO[0];
-      g.y = rE[1] + sg * rO[1];
+      g.x = rE[0];
+      g.y = rE[1];
+      if (tt < K - 1) {
+        const double* rO = GT + ((size_t)tt * K + mO) * C + 2 * s;
+        g.x += sg * rO[0];
+        g.y += sg * rO[1];
+        if (t < K - 1) {
+          racc.x = fma(A.pole[t], rO[0], racc.x);
+          racc.y = fma(A.pole[t], rO[1], racc.y);
+        }
+      }
     }
     buf[lds_pad(t)] = g;
+  }
+  {
+    const double2 prow = problem_sum(racc, TT, red_scratch);
+    if (lt == 0) prow_s = prow;
   }
   __syncthreads();
   dft4095<false, TT>(buf, lt, w5lo, w5hi);
@@ -182,13 +199,19 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
   dft4095<false, TT>(buf, lt, w5lo, w5hi);
 
   if (valid) {
+    const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
+    const double2 pO = make_double2(rP[0], rP[1]);
     for (int t = lt; t < K; t += TT) {
       const double2 h1 = buf[lds_pad(t)];
-      double2 he = h1, ho = make_double2(0.0, 0.0);
+      double2 he = h1, ho;
       if (t < K - 1) {
         const double2 h2 = buf[lds_pad(N - 1 - t)];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
+        ho.x = fma(A.pole[t], pO.x, ho.x);
+        ho.y = fma(A.pole[t], pO.y, ho.y);
+      } else {
+        ho = make_double2(fma(A.pole[t], pO.x, prow_s.x), fma(A.pole[t], pO.y, prow_s.y));
       }
       double* wE = HM + ((size_t)mE * K + t) * C + 2 * s;
       double* wO = HM + ((size_t)mO * K + t) * C + 2 * s;
@@ -268,6 +291,7 @@ static K2048Args k2048_args(const ShtTables& T) {
   a.khat0 = T.khat0;
   a.khat1 = T.khat1;
   a.hphase = T.hphase;
+  a.pole = T.pole;
   return a;
 }
 

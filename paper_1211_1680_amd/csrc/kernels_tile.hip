@@ -9,9 +9,10 @@
 namespace s2let {
 
 // blockIdx.y = m; threads over (l - m) * C + c.
+// herm (real maps only): use the Hermitian part (f_lm + (-1)^m conj f_{l,-m}) / 2 of the input.
 __global__ void k_unpack(const double2* __restrict__ flm, double* __restrict__ S,
                          const double* __restrict__ dfac, int k, int Lt, int C, int nb, int real,
-                         long long map_stride) {
+                         long long map_stride, int herm) {
   const int m = blockIdx.y;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int len = k - m;
@@ -25,6 +26,11 @@ __global__ void k_unpack(const double2* __restrict__ flm, double* __restrict__ S
     if (a < nb) {
       const double2 f = flm[(size_t)a * map_stride + (size_t)l * l + l + m];
       v = (c & 1) ? f.y : f.x;
+      if (herm) {
+        const double2 g = flm[(size_t)a * map_stride + (size_t)l * l + l - m];
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        v = 0.5 * (v + sg * ((c & 1) ? -g.y : g.x));
+      }
     }
   } else {
     const int a = c >> 2, part = c & 3;
@@ -104,11 +110,33 @@ __global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long 
     *o = v;
 }
 
+// dst = scale * src with the (theta, m) rows transposed: src[(a*k + b)*C + c] -> dst[(b*k + a)*C + c].
+// Used by the adjoint transforms, which skip the theta quadrature (inverse adjoint) or run it
+// between the Legendre step and the phi stage (forward adjoint).
+__global__ void k_transpose_rows(const double* __restrict__ src, double* __restrict__ dst, int k, int C,
+                                 double scale) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)k * k * C;
+  if (idx >= total) return;
+  const int c = (int)(idx % C);
+  const size_t row = idx / C;
+  const int a = (int)(row / k), b = (int)(row % k);
+  dst[((size_t)b * k + a) * C + c] = scale * src[idx];
+}
+
+hipError_t launch_transpose_rows(const Batch& b, int k, const double* src, double* dst, double scale,
+                                 hipStream_t s) {
+  const size_t total = (size_t)k * k * b.C;
+  const unsigned nblk = (unsigned)((total + 255) / 256);
+  k_transpose_rows<<<nblk, 256, 0, s>>>(src, dst, k, b.C, scale);
+  return hipGetLastError();
+}
+
 hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm, double* S,
-                             hipStream_t s) {
+                             hipStream_t s, bool herm) {
   dim3 grid((k * b.C + 255) / 256, k);
   k_unpack<<<grid, 256, 0, s>>>(flm, S, G.dfac, k, G.Lt, b.C, b.nb, b.reality == S2LET_REAL,
-                                (long long)k * k);
+                                (long long)k * k, herm ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -156,6 +156,42 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
   ut[k - 1] = 0.0;
   sx[k - 1] = -1.0;
 
+  // Pole column of the odd-parity theta operator.  For odd m the weight's p = +-1 terms, which
+  // the kernels leave out, cancel everywhere except in row and column t = k-1 (the south
+  // pole), where they are c_t = Q(t, k-1) = Q(k-1, t): the steps of the quadrature applied to
+  // the unit input at the pole, g = delta_{k-1} (Ghat_j = (-1)^j / n), with the full weight
+  //   I_j' = sum_j Ghat_j w(j + j'),  H(theta_t) = (1/n) sum_j' I_j' e^{-i j' theta_t},
+  //   c_t = H(t) - H(n-1-t) (t < k-1),  c_{k-1} = H(k-1)   (real up to rounding).
+  std::vector<double> pole(k);
+  {
+    std::vector<cLD> I(n);
+    for (int jp = -(k - 1); jp <= k - 1; ++jp) {
+      cLD acc(0, 0);
+      for (int j = -(k - 1); j <= k - 1; ++j) {
+        const int pp = j + jp;
+        cLD wv(0, 0);
+        if ((pp & 1) == 0) wv = cLD(2.0L / (1.0L - (LD)pp * (LD)pp), 0);
+        else if (pp == 1) wv = cLD(0, PI_L / 2);
+        else if (pp == -1) wv = cLD(0, -PI_L / 2);
+        acc += ((j & 1) ? -1.0L : 1.0L) * wv;
+      }
+      I[jp + k - 1] = acc / (LD)n;
+    }
+    // e^{-i j' theta_t} = e^{-i pi j' (2t+1) / n}: table over the residue of j'(2t+1) mod 2n
+    std::vector<cLD> ex(2 * n);
+    for (int q = 0; q < 2 * n; ++q) ex[q] = cLD(cosl(-PI_L * q / n), sinl(-PI_L * q / n));
+    auto H = [&](int t) {
+      cLD acc(0, 0);
+      for (int jp = -(k - 1); jp <= k - 1; ++jp) {
+        const long long q = (((long long)jp * (2 * t + 1)) % (2 * n) + 2 * n) % (2 * n);
+        acc += I[jp + k - 1] * ex[q];
+      }
+      return acc / (LD)n;
+    };
+    for (int t = 0; t < k - 1; ++t) pole[t] = (double)(H(t) - H(n - 1 - t)).real();
+    pole[k - 1] = (double)H(k - 1).real();
+  }
+
   std::vector<cLD> hph(2 * k - 1);
   for (int j = -(k - 1); j <= k - 1; ++j) {
     const LD ang = -PI_L * (LD)j / (LD)n;
@@ -167,6 +203,7 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
   if ((e = upload(&T->ut, ut)) != hipSuccess) return e;
   if ((e = upload(&T->sx, sx)) != hipSuccess) return e;
   if ((e = upload(&T->hphase, to_d2(hph))) != hipSuccess) return e;
+  if ((e = upload(&T->pole, pole)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -184,6 +221,7 @@ void free_sht_tables(ShtTables* T) {
   hipFree(T->ut);
   hipFree(T->sx);
   hipFree(T->hphase);
+  hipFree(T->pole);
   *T = ShtTables();
 }
 

@@ -93,3 +93,14 @@ def test_scales_on_oracle_rings(data):
     ref = oracle.inverse_sht(slm, kP, reality=True)
     print("scaling map k=%d" % kP, flush=True)
     assert _rel(data["f_scal"][:2].reshape(2, kP, 2 * kP - 1), ref, floor) < TOL
+
+
+def test_forward_arbitrary_samples_full_size(dev):
+    """Forward transform at L = 2048 of samples that are not band-limited (two real maps of
+    independent unit normals, so the south-pole ring is not constant), against the oracle."""
+    rng = np.random.default_rng(2048)
+    f = rng.standard_normal((2, L, 2 * L - 1))
+    print("full size: oracle forward of 2 arbitrary maps", flush=True)
+    ref = oracle.forward_sht(f, L)
+    got = s2.mw_forward(torch.from_numpy(f).to(dev), L, s2.REAL).cpu().numpy()
+    assert _rel(got, ref, 0.0) < TOL

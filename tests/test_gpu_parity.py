@@ -69,6 +69,21 @@ def test_forward_parity(dev, L, reality):
     assert _rel(got, flm) < TOL
 
 
+@pytest.mark.parametrize("reality", [s2.REAL, s2.COMPLEX])
+@pytest.mark.parametrize("L", [2, 3, 8, 13, 64])
+def test_forward_arbitrary_samples(dev, L, reality):
+    """The quadrature applied to samples that are not band-limited (a south-pole ring that is not
+    constant): the same linear map as the oracle's, including the pole terms of the weight."""
+    _log("forward of arbitrary samples", L, reality)
+    real = reality == s2.REAL
+    rng = np.random.default_rng(900 + L)
+    f = rng.standard_normal((3, L, 2 * L - 1))
+    if not real:
+        f = f + 1j * rng.standard_normal((3, L, 2 * L - 1))
+    got = s2.mw_forward(_to_dev(f, dev), L, reality).cpu().numpy()
+    assert _rel(got, oracle.forward_sht(f, L)) < TOL
+
+
 def test_forward_basis_vectors(dev):
     """Every basis vector e_lm at L = 12 comes back exactly (complex maps)."""
     L = 12

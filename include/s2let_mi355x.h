@@ -144,6 +144,50 @@ int s2let_axisym_synthesis_adjoint(void* f_wav, void* f_scal, const void* f, int
                                    int J_min, int multires, int reality, int precision, int nmaps,
                                    void* ws, size_t ws_bytes, void* stream);
 
+/* Batches of maps with uneven band-limits and wavelet parameters: axisymmetric wavelet
+ * analysis (Eqs. (4), (6)) and synthesis (Eq. (8)) of map i at band-limit L[i] with parameter
+ * B[i], common J_min, multiresolution flag, reality and precision.  Maps with equal (L, B) are
+ * processed together in the library's batched kernels; groups run concurrently on worker streams
+ * owned by the plan (default priority), forked from and joined back to the caller's stream.
+ *
+ * Layouts (device memory, caller-owned): maps concatenated in the given order (map i at sample
+ * offset map_off[i], [L[i]][2L[i]-1] doubles, or interleaved complex pairs); wavelet maps of map i
+ * concatenated as in s2let_axisym_analysis at wav_off[i]; scaling map at scal_off[i].
+ * s2let_batch_layout returns the totals {maps, wavelet maps, scaling maps} and the offsets (in
+ * doubles; any of the output pointers may be NULL).
+ *
+ * s2let_batch_create: host-side plan plus device resources owned by the plan (copy descriptors,
+ *   streams, events), released by s2let_batch_destroy.  EINVAL unless every L[i] >= 3,
+ *   B[i] >= 2 and 0 <= J_min < J(L[i], B[i]); EUNSUPPORTED for L[i] > S2LET_MAX_L.
+ * s2let_batch_workspace_size: bytes of caller-owned device workspace for every call below.
+ * s2let_batch_analysis: f -> (f_wav, f_scal).
+ * s2let_batch_run: analysis, then synthesis of its output: f -> (f_wav, f_scal) and rec.
+ * s2let_batch_autotune: times s2let_batch_run over the worker-stream counts {1, 2, 4, 8} and the
+ *   maps per batch {4, 8, 16} (real; {2, 4, 8} complex) on the given buffers (synchronising
+ *   the stream), keeps the fastest and returns it (pointers may be NULL).  Outputs hold a
+ *   complete run afterwards.
+ * s2let_batch_graph_capture: runs once eagerly, then captures s2let_batch_run on these buffers
+ *   into a HIP graph (stream must not be NULL); s2let_batch_graph_launch replays it on `stream`.
+ *   The graph stays bound to the buffers given at capture; changing the configuration
+ *   (autotune) discards it. */
+typedef struct s2let_batch s2let_batch;
+int s2let_batch_create(s2let_batch** plan, int nmaps, const int* L, const int* B, int J_min, int multires,
+                       int reality, int precision);
+int s2let_batch_destroy(s2let_batch* plan);
+int s2let_batch_layout(const s2let_batch* plan, int64_t* totals, int64_t* map_off, int64_t* wav_off,
+                       int64_t* scal_off);
+size_t s2let_batch_workspace_size(const s2let_batch* plan);
+int s2let_batch_analysis(s2let_batch* plan, void* f_wav, void* f_scal, const void* f, void* ws,
+                         size_t ws_bytes, void* stream);
+int s2let_batch_run(s2let_batch* plan, void* f_wav, void* f_scal, void* rec, const void* f, void* ws,
+                    size_t ws_bytes, void* stream);
+int s2let_batch_autotune(s2let_batch* plan, void* f_wav, void* f_scal, void* rec, const void* f, void* ws,
+                         size_t ws_bytes, void* stream, int* best_streams, int* best_maps_per_batch,
+                         float* best_ms);
+int s2let_batch_graph_capture(s2let_batch* plan, void* f_wav, void* f_scal, void* rec, const void* f,
+                              void* ws, size_t ws_bytes, void* stream);
+int s2let_batch_graph_launch(s2let_batch* plan, void* stream);
+
 /* Measurement support.  s2let_profile_enable(1) clears previous records and, until
  * s2let_profile_enable(0), brackets every kernel launch of the calls above with a pair of HIP
  * events recorded on the launch stream; the Legendre kernels also count the (l, theta) pairs they

@@ -18,7 +18,7 @@ __all__ = [
     "j_max", "bandlimit_wav", "bandlimit_scal", "mw_size", "wav_size", "tiling_axisym",
     "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
     "mw_forward_adjoint", "mw_inverse_adjoint", "analysis_adjoint", "synthesis_adjoint",
-    "profile_enable", "profile_query", "STAGES",
+    "BatchPlan", "profile_enable", "profile_query", "STAGES",
 ]
 
 REAL, COMPLEX = 0, 1
@@ -60,6 +60,16 @@ def _load():
         "mw_inverse_adjoint": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_analysis_adjoint": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_synthesis_adjoint": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
+        "s2let_batch_create": (i, [ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(i), i, i, i, i]),
+        "s2let_batch_destroy": (i, [vp]),
+        "s2let_batch_layout": (i, [vp] + [ctypes.POINTER(ctypes.c_int64)] * 4),
+        "s2let_batch_workspace_size": (sz, [vp]),
+        "s2let_batch_analysis": (i, [vp, vp, vp, vp, vp, sz, vp]),
+        "s2let_batch_run": (i, [vp, vp, vp, vp, vp, vp, sz, vp]),
+        "s2let_batch_autotune": (i, [vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(i), ctypes.POINTER(i),
+                                     ctypes.POINTER(ctypes.c_float)]),
+        "s2let_batch_graph_capture": (i, [vp, vp, vp, vp, vp, vp, sz, vp]),
+        "s2let_batch_graph_launch": (i, [vp, vp]),
         "s2let_sync": (i, [vp]),
         "s2let_profile_enable": (i, [i]),
         "s2let_profile_query": (i, [i, dp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp]),
@@ -340,6 +350,112 @@ def split_wav(f_wav, L: int, B: int, J_min: int, multires: bool = True):
         out.append(f_wav[:, off:off + n].reshape(nmaps, k, 2 * k - 1))
         off += n
     return out
+
+
+class BatchPlan:
+    """Wavelet analysis + synthesis of many maps with uneven (L, B) (s2let_batch_* in the C ABI).
+
+    Maps are concatenated in the given order in one flat tensor (float64 for REAL, complex128
+    for COMPLEX); wavelet and scaling maps likewise (offsets from ``map_off``, ``wav_off``,
+    ``scal_off``).  The plan owns worker streams and a few device tables; call ``close()``."""
+
+    def __init__(self, Ls, Bs, J_min: int, multires: bool = True, reality: int = REAL,
+                 precision: int = FP64, device=None):
+        torch = _torch()
+        self.Ls, self.Bs = [int(x) for x in Ls], [int(x) for x in Bs]
+        if len(self.Ls) != len(self.Bs) or not self.Ls:
+            raise ValueError("Ls and Bs must have the same nonzero length")
+        self.J_min, self.multires, self.reality, self.precision = J_min, multires, reality, precision
+        self.device = torch.device("cuda:0") if device is None else torch.device(device)
+        n = len(self.Ls)
+        arrL = (ctypes.c_int * n)(*self.Ls)
+        arrB = (ctypes.c_int * n)(*self.Bs)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.s2let_batch_create(ctypes.byref(h), n, arrL, arrB, J_min, int(multires), reality,
+                                           precision), "s2let_batch_create")
+        self._h = h
+        tot = (ctypes.c_int64 * 3)()
+        mo, wo, so = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+        _check(_lib.s2let_batch_layout(h, tot, mo, wo, so), "s2let_batch_layout")
+        cm = 1 if reality == REAL else 2
+        self.totals = [int(t) // cm for t in tot]          # in elements of the map dtype
+        self.map_off = [int(x) // cm for x in mo]
+        self.wav_off = [int(x) // cm for x in wo]
+        self.scal_off = [int(x) // cm for x in so]
+        self.ws = torch.empty(int(_lib.s2let_batch_workspace_size(h)), dtype=torch.uint8, device=self.device)
+
+    def _dtype(self):
+        return _map_dtype(self.reality)
+
+    def outputs(self):
+        torch = _torch()
+        dt = self._dtype()
+        return (torch.empty(self.totals[1], dtype=dt, device=self.device),
+                torch.empty(self.totals[2], dtype=dt, device=self.device),
+                torch.empty(self.totals[0], dtype=dt, device=self.device))
+
+    def _ws(self):
+        return self.ws.data_ptr(), self.ws.numel()
+
+    def analysis(self, f, out=None):
+        _need_cuda(f, "f", self._dtype())
+        f_wav, f_scal, _ = self.outputs() if out is None else (out[0], out[1], None)
+        _check(_lib.s2let_batch_analysis(self._h, f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), *self._ws(),
+                                         _stream(self.device)), "s2let_batch_analysis")
+        return f_wav, f_scal
+
+    def run(self, f, out=None):
+        """Analysis then synthesis: returns (f_wav, f_scal, reconstruction)."""
+        _need_cuda(f, "f", self._dtype())
+        f_wav, f_scal, rec = self.outputs() if out is None else out
+        _check(_lib.s2let_batch_run(self._h, f_wav.data_ptr(), f_scal.data_ptr(), rec.data_ptr(), f.data_ptr(),
+                                    *self._ws(), _stream(self.device)), "s2let_batch_run")
+        return f_wav, f_scal, rec
+
+    def autotune(self, f, out):
+        s_, c_, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+        f_wav, f_scal, rec = out
+        _check(_lib.s2let_batch_autotune(self._h, f_wav.data_ptr(), f_scal.data_ptr(), rec.data_ptr(),
+                                         f.data_ptr(), *self._ws(), _stream(self.device), ctypes.byref(s_),
+                                         ctypes.byref(c_), ctypes.byref(ms)), "s2let_batch_autotune")
+        return s_.value, c_.value, ms.value
+
+    def capture(self, f, out):
+        """Capture run(f, out) into a HIP graph on the current (non-default) stream."""
+        f_wav, f_scal, rec = out
+        _check(_lib.s2let_batch_graph_capture(self._h, f_wav.data_ptr(), f_scal.data_ptr(), rec.data_ptr(),
+                                              f.data_ptr(), *self._ws(), _stream(self.device)),
+               "s2let_batch_graph_capture")
+
+    def replay(self):
+        _check(_lib.s2let_batch_graph_launch(self._h, _stream(self.device)), "s2let_batch_graph_launch")
+
+    def map_view(self, flat, i, kind="map"):
+        """Map i of a flat buffer: kind 'map' -> [L, 2L-1]; 'wav' -> list of scale maps; 'scal'."""
+        L, B = self.Ls[i], self.Bs[i]
+        if kind == "map":
+            return flat[self.map_off[i]:self.map_off[i] + mw_size(L)].view(L, 2 * L - 1)
+        if kind == "scal":
+            k = bandlimit_scal(self.J_min, L, B, self.multires)
+            return flat[self.scal_off[i]:self.scal_off[i] + mw_size(k)].view(k, 2 * k - 1)
+        out, off = [], self.wav_off[i]
+        for j in range(self.J_min, j_max(L, B) + 1):
+            k = bandlimit_wav(j, L, B, self.multires)
+            out.append(flat[off:off + mw_size(k)].view(k, 2 * k - 1))
+            off += mw_size(k)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.s2let_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 STAGES = {"phi_forward": 0, "theta": 1, "legendre_analysis": 2, "legendre_synthesis": 3,

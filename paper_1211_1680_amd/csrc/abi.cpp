@@ -368,13 +368,13 @@ S2LET_API size_t s2let_workspace_size(int L, int B, int J_min, int multires, int
 }
 
 static int prologue(int L, int reality, int precision, int nmaps, void* ws, size_t ws_bytes,
-                    bool wavelet, int* dev) {
+                    bool wavelet, int* dev, int cap = 0) {
   int st = check_common(reality, precision, nmaps);
   if (st != S2LET_OK) return st;
   if (L < 1) return S2LET_EINVAL;
   if (L > S2LET_MAX_L) return S2LET_EUNSUPPORTED;
   if (!ws || !aligned16(ws)) return S2LET_EINVAL;
-  const Batch b = make_batch(reality, std::min(nmaps, batch_cap(reality)));
+  const Batch b = make_batch(reality, std::min(nmaps, cap > 0 ? cap : batch_cap(reality)));
   if (ws_bytes < ws_bytes_for(L, b.C, wavelet)) return S2LET_ENOMEM;
   return get_device(dev);
 }
@@ -461,15 +461,15 @@ S2LET_API int mw_forward_adjoint(void* f, const void* flm, int L, int reality, i
 // Map at L -> wavelet and scaling maps.  adjoint = false: the analysis, Eqs. (4) and (6).
 // adjoint = true: the adjoint of the synthesis of Eq. (8) (inverse-transform adjoint at L, the
 // real diagonal kernels and truncation, forward-transform adjoints at each scale).
-static int wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min, int multires,
+int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min, int multires,
                              int reality, int precision, int nmaps, void* ws, size_t ws_bytes, void* stream,
-                             bool adjoint) {
+                             bool adjoint, int cap) {
   if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
     return S2LET_EINVAL;
   int st = check_wavelet(L, B, J_min, multires);
   if (st != S2LET_OK) return st;
   int dev;
-  if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev)) != S2LET_OK) return st;
+  if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev, cap)) != S2LET_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
   DevCache& dc = g_cache[dev];
@@ -487,12 +487,12 @@ static int wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, in
     if ((st = ensure_sht(dc, bl_wav(j, L, B, multires), &t)) != S2LET_OK) return st;
     TJ.push_back(t);
   }
-  const int cap = batch_cap(reality);
+  const int bcap = cap > 0 ? std::min(cap, batch_cap(reality)) : batch_cap(reality);
   const int cmul = reality == S2LET_REAL ? 1 : 2;
   const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires),
                 psz = s2let_mw_size(kP);
-  for (int start = 0; start < nmaps; start += cap) {
-    const Batch b = make_batch(reality, std::min(cap, nmaps - start));
+  for (int start = 0; start < nmaps; start += bcap) {
+    const Batch b = make_batch(reality, std::min(bcap, nmaps - start));
     const Workspace w = carve(ws, L, b.C, true);
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
     if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
@@ -519,15 +519,15 @@ static int wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, in
 // Wavelet and scaling maps -> map at L.  adjoint = false: the synthesis, Eq. (8).  adjoint =
 // true: the adjoint of the analysis (inverse-transform adjoints at each scale, the kernels,
 // forward-transform adjoint at L).
-static int wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int L, int B, int J_min,
+int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int L, int B, int J_min,
                              int multires, int reality, int precision, int nmaps, void* ws, size_t ws_bytes,
-                             void* stream, bool adjoint) {
+                             void* stream, bool adjoint, int cap) {
   if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
     return S2LET_EINVAL;
   int st = check_wavelet(L, B, J_min, multires);
   if (st != S2LET_OK) return st;
   int dev;
-  if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev)) != S2LET_OK) return st;
+  if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev, cap)) != S2LET_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
   DevCache& dc = g_cache[dev];
@@ -545,12 +545,12 @@ static int wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int
     if ((st = ensure_sht(dc, bl_wav(j, L, B, multires), &t)) != S2LET_OK) return st;
     TJ.push_back(t);
   }
-  const int cap = batch_cap(reality);
+  const int bcap = cap > 0 ? std::min(cap, batch_cap(reality)) : batch_cap(reality);
   const int cmul = reality == S2LET_REAL ? 1 : 2;
   const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires),
                 psz = s2let_mw_size(kP);
-  for (int start = 0; start < nmaps; start += cap) {
-    const Batch b = make_batch(reality, std::min(cap, nmaps - start));
+  for (int start = 0; start < nmaps; start += bcap) {
+    const Batch b = make_batch(reality, std::min(bcap, nmaps - start));
     const Workspace w = carve(ws, L, b.C, true);
     // scaling part
     const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
@@ -577,29 +577,29 @@ static int wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int
 S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
                                     int multires, int reality, int precision, int nmaps, void* ws,
                                     size_t ws_bytes, void* stream) {
-  return wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, false);
+  return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, false, 0);
 }
 
 S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L, int B,
                                      int J_min, int multires, int reality, int precision, int nmaps,
                                      void* ws, size_t ws_bytes, void* stream) {
-  return wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, false);
+  return s2let_wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, false, 0);
 }
 
 S2LET_API int s2let_axisym_analysis_adjoint(void* f, const void* f_wav, const void* f_scal, int L, int B,
                                             int J_min, int multires, int reality, int precision, int nmaps,
                                             void* ws, size_t ws_bytes, void* stream) {
-  return wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, true);
+  return s2let_wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, true, 0);
 }
 
 S2LET_API int s2let_axisym_synthesis_adjoint(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
                                              int multires, int reality, int precision, int nmaps, void* ws,
                                              size_t ws_bytes, void* stream) {
-  return wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, true);
+  return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                           stream, true, 0);
 }
 
 S2LET_API int s2let_profile_enable(int on) {

@@ -52,6 +52,15 @@ enum { S2LET_FP64 = 0, S2LET_MIXED_FP32 = 1, S2LET_MIXED_BF16X3 = 2 };  /* preci
                                                                      Legendre contraction */
 #define S2LET_MAX_L 2048
 
+/* Generating functions of the axisymmetric wavelets (Sect. 2.2).  S2LET_KERNEL_SD: the
+ * scale-discretised functions of Eqs. (10)-(16) (the default of every call without a kernel
+ * argument).  S2LET_KERNEL_BSPLINE: the B-spline construction of the footnote to Sect. 2.2,
+ * k(t) = (3/2) B_3(2 t B^(J-1) / L), kappa_j^2 = k(l/B^(j+1)) - k(l/B^j) for j < J, with the top
+ * scale kappa_J^2 = 1 - k(l/B^J) so that the tiling sums to one below L; multiresolution
+ * band-limits k_j = min(ceil(L / B^(J-j-2)), L) (Sect. 3.1) and k_Phi = min(ceil(L / B^(J-J_min-1)), L).
+ * S2LET_KERNEL_NEEDLET is reserved (the paper does not define it): S2LET_EUNSUPPORTED. */
+enum { S2LET_KERNEL_SD = 0, S2LET_KERNEL_BSPLINE = 1, S2LET_KERNEL_NEEDLET = 2 };
+
 /* Scale range (Sect. 2.2, after Eq. (16)): J = ceil(log_B(L-1)), computed exactly in integers
  * as the smallest J with B^J >= L-1.  Returns J, or S2LET_EINVAL unless L >= 3 and B >= 2. */
 int s2let_j_max(int L, int B);
@@ -144,6 +153,30 @@ int s2let_axisym_synthesis_adjoint(void* f_wav, void* f_scal, const void* f, int
                                    int J_min, int multires, int reality, int precision, int nmaps,
                                    void* ws, size_t ws_bytes, void* stream);
 
+/* The band-limit, size, tiling, analysis and synthesis calls above with a choice of generating
+ * function (S2LET_KERNEL_*); identical to them for S2LET_KERNEL_SD. */
+int s2let_bandlimit_wav_kernel(int j, int L, int B, int multires, int kernel);
+int s2let_bandlimit_scal_kernel(int J_min, int L, int B, int multires, int kernel);
+int64_t s2let_wav_size_kernel(int L, int B, int J_min, int multires, int kernel);
+int s2let_tiling_axisym_kernel(double* kappa, double* eta, int L, int B, int J_min, int kernel);
+int s2let_axisym_analysis_kernel(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                                 int multires, int kernel, int reality, int precision, int nmaps, void* ws,
+                                 size_t ws_bytes, void* stream);
+int s2let_axisym_synthesis_kernel(void* f, const void* f_wav, const void* f_scal, int L, int B, int J_min,
+                                  int multires, int kernel, int reality, int precision, int nmaps, void* ws,
+                                  size_t ws_bytes, void* stream);
+
+/* Wavelet denoising by hard thresholding (Sect. 4.2).  For white noise with E|n_lm|^2 = sigma^2
+ * (Eq. (19)) the wavelet maps of scale j carry noise of standard deviation
+ *   sigma_j = sigma * sqrt( sum_l (2l+1)/(4 pi) kappa_j(l)^2 )           (Eq. (22)),
+ * written to sigma_wav[j - J_min] (host, J - J_min + 1 doubles).  s2let_hard_threshold sets to zero
+ * every sample of the wavelet maps (device, layout of s2let_axisym_analysis) of scale j whose
+ * magnitude is below thresholds[j - J_min] (host array; Eq. (23) with T_j = 3 sigma_j, read with
+ * the magnitude |Y^j|); the scaling maps are not thresholded.  Asynchronous on `stream`. */
+int s2let_noise_std_axisym(double* sigma_wav, int L, int B, int J_min, int kernel, double sigma);
+int s2let_hard_threshold(void* f_wav, const double* thresholds, int L, int B, int J_min, int multires,
+                         int kernel, int reality, int nmaps, void* stream);
+
 /* Batches of maps with uneven band-limits and wavelet parameters: axisymmetric wavelet
  * analysis (Eqs. (4), (6)) and synthesis (Eq. (8)) of map i at band-limit L[i] with parameter
  * B[i], common J_min, multiresolution flag, reality and precision.  Maps with equal (L, B) are
@@ -213,6 +246,11 @@ void s2let_finalize(void);
 
 /* Static description of a status code. */
 const char* s2let_strerror(int status);
+
+/* The HIP error code (hipError_t) behind the last S2LET_EHIP returned on the calling thread,
+ * and its name (static string); hipSuccess / "hipSuccess" if none. */
+int s2let_last_hip_error(void);
+const char* s2let_last_hip_error_name(void);
 
 /* Library version string. */
 const char* s2let_version(void);

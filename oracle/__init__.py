@@ -14,6 +14,10 @@ Functions and the passages they follow:
   quadrature_weight ....... the sin(theta) integral weights used by that quadrature
   tiling .................. Eqs. (10)-(16) and J = ceil(log_lambda(L-1)) (Sect. 2.2)
   analysis / synthesis .... Eqs. (4), (6), (8); multiresolution band-limits (Sect. 3.1)
+  *_adjoint ............... adjoints of the four transforms above (their steps transposed)
+  bspline_b3, k_bspline ... the B-spline generating function, Eqs. (17)-(18) (exact rationals)
+  noise_std ............... wavelet-space noise level of Sect. 4.3 (Eq. (19) and Eq. (15))
+  hard_threshold .......... Eq. (23); snr: Eqs. (20)-(21); denoise: Sect. 4.3
 
 Parity status: every function above is pinned by tests/test_oracle_pins.py except the
 absolute values of k_lambda (Eq. (12)), which the paper does not print: they are checked
@@ -24,6 +28,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+from fractions import Fraction
 import os
 import subprocess
 import threading
@@ -329,14 +334,35 @@ def j_max(L: int, B: int) -> int:
     return J
 
 
-def bandlimit_wav(j: int, L: int, B: int, multires: bool) -> int:
-    """Band-limit of wavelet scale j: min(B^{j+1}, L) with multiresolution, else L (Sect. 3.1)."""
-    return min(B ** (j + 1), L) if multires else L
+KERNELS = ("sd", "bspline")
 
 
-def bandlimit_scal(J_min: int, L: int, B: int, multires: bool) -> int:
-    """Band-limit of the scaling part: supp eta = [0, B^{J_min}), so min(B^{J_min}, L)."""
-    return min(B ** J_min, L) if multires else L
+def _ceil_frac(a: int, b: int) -> int:
+    return -(-a // b)
+
+
+def bandlimit_wav(j: int, L: int, B: int, multires: bool, kernel: str = "sd") -> int:
+    """Band-limit of wavelet scale j (Sect. 3.1): without multiresolution L; with it
+    min(B^{j+1}, L) for the scale-discretised kernels, and for the B-spline kernels the end of
+    their support [0, L/B^{J-j-2}] rounded up, capped at L (L itself when J-j-2 <= 0)."""
+    if not multires:
+        return L
+    if kernel == "bspline":
+        e = j_max(L, B) - j - 2
+        return L if e <= 0 else min(L, _ceil_frac(L, B ** e))
+    return min(B ** (j + 1), L)
+
+
+def bandlimit_scal(J_min: int, L: int, B: int, multires: bool, kernel: str = "sd") -> int:
+    """Band-limit of the scaling part: supp eta = [0, B^{J_min}) for the scale-discretised
+    kernels, so min(B^{J_min}, L); for the B-spline kernels eta^2 = k(l/B^{J_min}) vanishes from
+    l = L/B^{J-J_min-1} on, so that value rounded up (capped at L)."""
+    if not multires:
+        return L
+    if kernel == "bspline":
+        e = j_max(L, B) - J_min - 1
+        return L if e <= 0 else min(L, _ceil_frac(L, B ** e))
+    return min(B ** J_min, L)
 
 
 def schwartz(x: float) -> float:
@@ -406,11 +432,59 @@ def eta_lambda(t: float, lam: float) -> float:
     return math.sqrt(max(0.0, k_lambda(t, lam)))
 
 
-def tiling(L: int, B: int, J_min: int):
+# ----------------------------------------------------------------------------------------
+# B-spline generating function (footnote to Sect. 2.2, Eqs. (17)-(18)), in exact rationals
+# ----------------------------------------------------------------------------------------
+def bspline_b3(x) -> Fraction:
+    """B_3(x) = (|x-2|^3 - 4|x-1|^3 + 6|x|^3 - 4|x+1|^3 + |x+2|^3) / 12  (Eq. (18)), evaluated
+    exactly on rationals.  The combination is the fourth central difference of |x|^3/12, which
+    is zero for |x| >= 2 (it is then a fourth difference of a cubic); outside (-2, 2) the value
+    0 is returned directly."""
+    x = Fraction(x)
+    if abs(x) >= 2:
+        return Fraction(0)
+    c = lambda u: abs(u) ** 3
+    return (c(x - 2) - 4 * c(x - 1) + 6 * c(x) - 4 * c(x + 1) + c(x + 2)) / 12
+
+
+def k_bspline(t, lam: int, L: int, J: int) -> Fraction:
+    """k_lambda(t) = (3/2) B_3(2 t lambda^{J-1} / L)  (Eq. (17)); t rational."""
+    return Fraction(3, 2) * bspline_b3(2 * Fraction(t) * Fraction(lam) ** (J - 1) / L)
+
+
+def tiling_bspline_sq(L: int, B: int, J_min: int):
+    """Squared B-spline kernels as exact rationals: (kappa2 [scale][l], eta2 [l]) with
+    eta^2(l) = k(l/B^{J_min}), kappa_j^2(l) = k(l/B^{j+1}) - k(l/B^j) for j < J, and the top
+    scale kappa_J^2(l) = 1 - k(l/B^J), which makes eta^2 + sum_j kappa_j^2 = 1 (Eq. (9)) hold for
+    every l < L.  (For the scale-discretised kernels the same top-scale form coincides with
+    Eq. (13), since there k(l/B^{J+1}) = 1 for l < L.)"""
+    J = j_max(L, B)
+    if not (0 <= J_min < J):
+        raise ValueError("need 0 <= J_min < J")
+    eta2 = [k_bspline(Fraction(l, B ** J_min), B, L, J) for l in range(L)]
+    kap2 = []
+    for j in range(J_min, J + 1):
+        row = []
+        for l in range(L):
+            lo = k_bspline(Fraction(l, B ** j), B, L, J)
+            hi = k_bspline(Fraction(l, B ** (j + 1)), B, L, J) if j < J else Fraction(1)
+            row.append(hi - lo)
+        kap2.append(row)
+    return kap2, eta2
+
+
+def tiling(L: int, B: int, J_min: int, kernel: str = "sd"):
     """Harmonic kernels of Eqs. (15)-(16) without the sqrt((2l+1)/4pi) factor, which cancels
     against the sqrt(4pi/(2l+1)) of Eqs. (4), (6) and (8):
       kappa[j - J_min, l] = kappa_B(l / B^j),  j = J_min..J
-      eta[l]              = eta_B(l / B^J_min)."""
+      eta[l]              = eta_B(l / B^J_min).
+    kernel "sd": the scale-discretised functions of Eqs. (10)-(14); "bspline": Eqs. (17)-(18)."""
+    if kernel == "bspline":
+        kap2, eta2 = tiling_bspline_sq(L, B, J_min)
+        return (np.array([[math.sqrt(v) for v in row] for row in kap2]),
+                np.array([math.sqrt(v) for v in eta2]))
+    if kernel != "sd":
+        raise ValueError("kernel must be 'sd' or 'bspline'")
     J = j_max(L, B)
     if not (0 <= J_min < J):
         raise ValueError("need 0 <= J_min < J")
@@ -441,56 +515,58 @@ def _ell_of_index(L: int) -> np.ndarray:
     return np.repeat(np.arange(L), 2 * np.arange(L) + 1)
 
 
-def analysis_harmonic(flm: np.ndarray, L: int, B: int, J_min: int, multires: bool):
+def analysis_harmonic(flm: np.ndarray, L: int, B: int, J_min: int, multires: bool, kernel: str = "sd"):
     """Scaling and wavelet coefficients in harmonic space (Eqs. (4), (6)):
     W^Phi_lm = eta(l) f_lm for l < k_Phi;  W^j_lm = kappa_j(l) f_lm for l < k_j."""
     flm = _as_maps(flm, L)
-    kappa, eta = tiling(L, B, J_min)
+    kappa, eta = tiling(L, B, J_min, kernel)
     ell = _ell_of_index(L)
     J = j_max(L, B)
-    kP = bandlimit_scal(J_min, L, B, multires)
+    kP = bandlimit_scal(J_min, L, B, multires, kernel)
     scal = _truncate(flm * eta[ell][None, :], L, kP)
     wav = []
     for j in range(J_min, J + 1):
-        kj = bandlimit_wav(j, L, B, multires)
+        kj = bandlimit_wav(j, L, B, multires, kernel)
         wav.append(_truncate(flm * kappa[j - J_min][ell][None, :], L, kj))
     return wav, scal
 
 
-def analysis(f: np.ndarray, L: int, B: int, J_min: int, multires: bool, reality: bool):
+def analysis(f: np.ndarray, L: int, B: int, J_min: int, multires: bool, reality: bool, kernel: str = "sd"):
     """Wavelet analysis of maps f [nmaps, L, 2L-1]: forward SHT at L, Eqs. (4)/(6), then an
     inverse SHT per scale at its band-limit.  Returns (list of wavelet maps per j, scaling map)."""
     flm = forward_sht(f, L)
-    wav_lm, scal_lm = analysis_harmonic(flm, L, B, J_min, multires)
+    wav_lm, scal_lm = analysis_harmonic(flm, L, B, J_min, multires, kernel)
     J = j_max(L, B)
-    kP = bandlimit_scal(J_min, L, B, multires)
+    kP = bandlimit_scal(J_min, L, B, multires, kernel)
     scal = inverse_sht(scal_lm, kP, reality)
-    wav = [inverse_sht(w, bandlimit_wav(j, L, B, multires), reality)
+    wav = [inverse_sht(w, bandlimit_wav(j, L, B, multires, kernel), reality)
            for j, w in zip(range(J_min, J + 1), wav_lm)]
     return wav, scal
 
 
-def synthesis_harmonic(wav_lm, scal_lm, L: int, B: int, J_min: int, multires: bool) -> np.ndarray:
+def synthesis_harmonic(wav_lm, scal_lm, L: int, B: int, J_min: int, multires: bool,
+                       kernel: str = "sd") -> np.ndarray:
     """Eq. (8): f_lm = eta(l) W^Phi_lm + sum_j kappa_j(l) W^j_lm (scales zero-extended to L)."""
-    kappa, eta = tiling(L, B, J_min)
+    kappa, eta = tiling(L, B, J_min, kernel)
     ell = _ell_of_index(L)
     J = j_max(L, B)
-    kP = bandlimit_scal(J_min, L, B, multires)
+    kP = bandlimit_scal(J_min, L, B, multires, kernel)
     out = _extend(_as_maps(scal_lm, kP), kP, L) * eta[ell][None, :]
     for j, w in zip(range(J_min, J + 1), wav_lm):
-        kj = bandlimit_wav(j, L, B, multires)
+        kj = bandlimit_wav(j, L, B, multires, kernel)
         out = out + _extend(_as_maps(w, kj), kj, L) * kappa[j - J_min][ell][None, :]
     return out
 
 
-def synthesis(wav, scal, L: int, B: int, J_min: int, multires: bool, reality: bool) -> np.ndarray:
+def synthesis(wav, scal, L: int, B: int, J_min: int, multires: bool, reality: bool,
+              kernel: str = "sd") -> np.ndarray:
     """Wavelet synthesis: forward SHT of each scale at its band-limit, Eq. (8), inverse SHT at L."""
     J = j_max(L, B)
-    kP = bandlimit_scal(J_min, L, B, multires)
+    kP = bandlimit_scal(J_min, L, B, multires, kernel)
     scal_lm = forward_sht(scal, kP)
-    wav_lm = [forward_sht(w, bandlimit_wav(j, L, B, multires))
+    wav_lm = [forward_sht(w, bandlimit_wav(j, L, B, multires, kernel))
               for j, w in zip(range(J_min, J + 1), wav)]
-    flm = synthesis_harmonic(wav_lm, scal_lm, L, B, J_min, multires)
+    flm = synthesis_harmonic(wav_lm, scal_lm, L, B, J_min, multires, kernel)
     return inverse_sht(flm, L, reality)
 
 
@@ -520,6 +596,46 @@ def synthesis_adjoint(f: np.ndarray, L: int, B: int, J_min: int, multires: bool,
         kj = bandlimit_wav(j, L, B, multires)
         wav.append(forward_sht_adjoint(_truncate(g * kappa[j - J_min][ell][None, :], L, kj), kj, reality))
     return wav, scal
+
+
+# ----------------------------------------------------------------------------------------
+# Denoising by hard thresholding (Sect. 4.3, Eqs. (19)-(23))
+# ----------------------------------------------------------------------------------------
+def noise_std(L: int, B: int, J_min: int, sigma: float, kernel: str = "sd") -> np.ndarray:
+    """sigma_j (j = J_min..J) for white noise with E|n_lm|^2 = sigma^2 (Eq. (19)):
+    (sigma_j)^2 = sigma^2 sum_l |Psi^j_l0|^2 with Psi^j_l0 = sqrt((2l+1)/4pi) kappa_j(l)
+    (Eq. (15))."""
+    kappa, _ = tiling(L, B, J_min, kernel)
+    ell = np.arange(L)
+    psi2 = (2.0 * ell + 1.0) / (4.0 * math.pi) * kappa ** 2
+    return sigma * np.sqrt(np.sum(psi2, axis=1))
+
+
+def hard_threshold(wav, thresholds):
+    """Eq. (23), read with the magnitude: D^j = 0 where |Y^j| < T^j, Y^j elsewhere.  wav: list
+    over scales of arrays; thresholds: one value per scale.  Returns new arrays."""
+    out = []
+    for w, t in zip(wav, thresholds):
+        d = np.array(w, copy=True)
+        d[np.abs(d) < t] = 0
+        out.append(d)
+    return out
+
+
+def snr(s_lm, y_lm) -> float:
+    """SNR(y) = 10 log10(||s||^2 / ||y - s||^2) (Eq. (20)) with the energies summed over
+    harmonic coefficients (Eq. (21))."""
+    s_lm, y_lm = np.asarray(s_lm), np.asarray(y_lm)
+    return 10.0 * math.log10(float(np.sum(np.abs(s_lm) ** 2)) / float(np.sum(np.abs(y_lm - s_lm) ** 2)))
+
+
+def denoise(y, L: int, B: int, J_min: int, sigma: float, multires: bool, reality: bool,
+            kernel: str = "sd", nsigma: float = 3.0):
+    """Wavelet analysis of y, hard thresholding of every wavelet scale at T_j = nsigma sigma_j,
+    and synthesis from the thresholded scales and the untouched scaling part (Sect. 4.3)."""
+    wav, scal = analysis(y, L, B, J_min, multires, reality, kernel)
+    wav = hard_threshold(wav, nsigma * noise_std(L, B, J_min, sigma, kernel))
+    return synthesis(wav, scal, L, B, J_min, multires, reality, kernel)
 
 
 # ----------------------------------------------------------------------------------------

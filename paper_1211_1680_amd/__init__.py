@@ -19,10 +19,12 @@ __all__ = [
     "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
     "mw_forward_adjoint", "mw_inverse_adjoint", "analysis_adjoint", "synthesis_adjoint",
     "BatchPlan", "profile_enable", "profile_query", "STAGES",
+    "KERNEL_SD", "KERNEL_BSPLINE", "KERNEL_NEEDLET", "noise_std", "hard_threshold", "denoise", "snr",
 ]
 
 REAL, COMPLEX = 0, 1
 FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
+KERNEL_SD, KERNEL_BSPLINE, KERNEL_NEEDLET = 0, 1, 2
 MAX_L = 2048
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 
@@ -33,11 +35,18 @@ LIB_PATH = os.path.join(_HERE, "libs2let_mi355x.so")
 class S2letError(RuntimeError):
     def __init__(self, status: int, where: str):
         msg = _lib.s2let_strerror(status).decode() if _lib is not None else str(status)
+        if status == EHIP and _lib is not None:
+            msg += ": %s" % _lib.s2let_last_hip_error_name().decode()
         super().__init__("%s failed: %s (status %d)" % (where, msg, status))
         self.status = status
 
 
 def _load():
+    # torch ships its own HIP and HSA runtimes under the same sonames as /opt/rocm's.  Loaded
+    # first, they satisfy this library's dependencies and the process holds one runtime; loaded
+    # after this library, torch would map a second pair, and the second HSA runtime to open the
+    # device reports that there is none.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libs2let_mi355x.so is not built (run __graft_entry__.build() or "
                           "python paper_1211_1680_amd/build.py)")
@@ -70,11 +79,21 @@ def _load():
                                      ctypes.POINTER(ctypes.c_float)]),
         "s2let_batch_graph_capture": (i, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "s2let_batch_graph_launch": (i, [vp, vp]),
+        "s2let_bandlimit_wav_kernel": (i, [i, i, i, i, i]),
+        "s2let_bandlimit_scal_kernel": (i, [i, i, i, i, i]),
+        "s2let_wav_size_kernel": (i64, [i, i, i, i, i]),
+        "s2let_tiling_axisym_kernel": (i, [dp, dp, i, i, i, i]),
+        "s2let_axisym_analysis_kernel": (i, [vp, vp, vp, i, i, i, i, i, i, i, i, vp, sz, vp]),
+        "s2let_axisym_synthesis_kernel": (i, [vp, vp, vp, i, i, i, i, i, i, i, i, vp, sz, vp]),
+        "s2let_noise_std_axisym": (i, [dp, i, i, i, i, ctypes.c_double]),
+        "s2let_hard_threshold": (i, [vp, dp, i, i, i, i, i, i, i, vp]),
         "s2let_sync": (i, [vp]),
         "s2let_profile_enable": (i, [i]),
         "s2let_profile_query": (i, [i, dp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp]),
         "s2let_finalize": (None, []),
         "s2let_strerror": (ctypes.c_char_p, [i]),
+        "s2let_last_hip_error": (i, []),
+        "s2let_last_hip_error_name": (ctypes.c_char_p, []),
         "s2let_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -100,15 +119,15 @@ def j_max(L: int, B: int) -> int:
     return r
 
 
-def bandlimit_wav(j: int, L: int, B: int, multires: bool) -> int:
-    r = _lib.s2let_bandlimit_wav(j, L, B, int(multires))
-    _check(min(r, 0), "s2let_bandlimit_wav")
+def bandlimit_wav(j: int, L: int, B: int, multires: bool, kernel: int = KERNEL_SD) -> int:
+    r = _lib.s2let_bandlimit_wav_kernel(j, L, B, int(multires), kernel)
+    _check(min(r, 0), "s2let_bandlimit_wav_kernel")
     return r
 
 
-def bandlimit_scal(J_min: int, L: int, B: int, multires: bool) -> int:
-    r = _lib.s2let_bandlimit_scal(J_min, L, B, int(multires))
-    _check(min(r, 0), "s2let_bandlimit_scal")
+def bandlimit_scal(J_min: int, L: int, B: int, multires: bool, kernel: int = KERNEL_SD) -> int:
+    r = _lib.s2let_bandlimit_scal_kernel(J_min, L, B, int(multires), kernel)
+    _check(min(r, 0), "s2let_bandlimit_scal_kernel")
     return r
 
 
@@ -119,22 +138,31 @@ def mw_size(k: int) -> int:
     return r
 
 
-def wav_size(L: int, B: int, J_min: int, multires: bool) -> int:
-    r = _lib.s2let_wav_size(L, B, J_min, int(multires))
+def wav_size(L: int, B: int, J_min: int, multires: bool, kernel: int = KERNEL_SD) -> int:
+    r = _lib.s2let_wav_size_kernel(L, B, J_min, int(multires), kernel)
     if r < 0:
-        raise S2letError(EINVAL, "s2let_wav_size")
+        raise S2letError(EINVAL, "s2let_wav_size_kernel")
     return r
 
 
-def tiling_axisym(L: int, B: int, J_min: int):
+def tiling_axisym(L: int, B: int, J_min: int, kernel: int = KERNEL_SD):
     """(kappa [J-J_min+1, L], eta [L]) as numpy arrays (host computation in the library)."""
     J = j_max(L, B)
     kappa = np.zeros((J - J_min + 1, L))
     eta = np.zeros(L)
     dp = ctypes.POINTER(ctypes.c_double)
-    _check(_lib.s2let_tiling_axisym(kappa.ctypes.data_as(dp), eta.ctypes.data_as(dp), L, B, J_min),
-           "s2let_tiling_axisym")
+    _check(_lib.s2let_tiling_axisym_kernel(kappa.ctypes.data_as(dp), eta.ctypes.data_as(dp), L, B, J_min,
+                                           kernel), "s2let_tiling_axisym_kernel")
     return kappa, eta
+
+
+def noise_std(L: int, B: int, J_min: int, sigma: float, kernel: int = KERNEL_SD):
+    """sigma_j, j = J_min..J: standard deviation of white harmonic noise of variance sigma^2
+    seen through wavelet scale j (host computation in the library)."""
+    out = np.zeros(j_max(L, B) - J_min + 1)
+    _check(_lib.s2let_noise_std_axisym(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), L, B, J_min,
+                                       kernel, float(sigma)), "s2let_noise_std_axisym")
+    return out
 
 
 def workspace_size(L, B=2, J_min=0, multires=False, reality=REAL, precision=FP64, nmaps=1,
@@ -214,7 +242,7 @@ def mw_inverse(flm, L: int, reality: int = REAL, precision: int = FP64, workspac
 
 
 def analysis(f, L: int, B: int, J_min: int, multires: bool = True, reality: int = REAL,
-             precision: int = FP64, workspace=None, out=None):
+             precision: int = FP64, workspace=None, out=None, kernel: int = KERNEL_SD):
     """Wavelet analysis.  Returns (f_wav [nmaps, wav_size], f_scal [nmaps, mw_size(k_Phi)])."""
     torch = _torch()
     dt = _map_dtype(reality)
@@ -222,41 +250,78 @@ def analysis(f, L: int, B: int, J_min: int, multires: bool = True, reality: int 
     nmaps = f.shape[0] if f.dim() == 3 else 1
     if f.numel() != nmaps * mw_size(L):
         raise ValueError("f must hold nmaps * L * (2L-1) samples")
-    kP = bandlimit_scal(J_min, L, B, multires)
+    kP = bandlimit_scal(J_min, L, B, multires, kernel)
     if out is None:
-        f_wav = torch.empty((nmaps, wav_size(L, B, J_min, multires)), dtype=dt, device=f.device)
+        f_wav = torch.empty((nmaps, wav_size(L, B, J_min, multires, kernel)), dtype=dt, device=f.device)
         f_scal = torch.empty((nmaps, mw_size(kP)), dtype=dt, device=f.device)
     else:
         f_wav, f_scal = out
     ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
                     f.device, workspace)
-    _check(_lib.s2let_axisym_analysis(f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), L, B, J_min,
-                                      int(multires), reality, precision, nmaps, ws.data_ptr(),
-                                      ws.numel() * ws.element_size(), _stream(f.device)),
-           "s2let_axisym_analysis")
+    _check(_lib.s2let_axisym_analysis_kernel(f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), L, B, J_min,
+                                             int(multires), kernel, reality, precision, nmaps, ws.data_ptr(),
+                                             ws.numel() * ws.element_size(), _stream(f.device)),
+           "s2let_axisym_analysis_kernel")
     return f_wav, f_scal
 
 
 def synthesis(f_wav, f_scal, L: int, B: int, J_min: int, multires: bool = True,
-              reality: int = REAL, precision: int = FP64, workspace=None, out=None):
+              reality: int = REAL, precision: int = FP64, workspace=None, out=None, kernel: int = KERNEL_SD):
     """Wavelet synthesis (Eq. (8)).  Returns f [nmaps, L, 2L-1]."""
     torch = _torch()
     dt = _map_dtype(reality)
     _need_cuda(f_wav, "f_wav", dt)
     _need_cuda(f_scal, "f_scal", dt)
     nmaps = f_wav.shape[0] if f_wav.dim() == 2 else 1
-    if f_wav.numel() != nmaps * wav_size(L, B, J_min, multires):
+    if f_wav.numel() != nmaps * wav_size(L, B, J_min, multires, kernel):
         raise ValueError("f_wav has the wrong size")
-    if f_scal.numel() != nmaps * mw_size(bandlimit_scal(J_min, L, B, multires)):
+    if f_scal.numel() != nmaps * mw_size(bandlimit_scal(J_min, L, B, multires, kernel)):
         raise ValueError("f_scal has the wrong size")
     f = out if out is not None else torch.empty((nmaps, L, 2 * L - 1), dtype=dt, device=f_wav.device)
     ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
                     f_wav.device, workspace)
-    _check(_lib.s2let_axisym_synthesis(f.data_ptr(), f_wav.data_ptr(), f_scal.data_ptr(), L, B, J_min,
-                                       int(multires), reality, precision, nmaps, ws.data_ptr(),
-                                       ws.numel() * ws.element_size(), _stream(f_wav.device)),
-           "s2let_axisym_synthesis")
+    _check(_lib.s2let_axisym_synthesis_kernel(f.data_ptr(), f_wav.data_ptr(), f_scal.data_ptr(), L, B, J_min,
+                                              int(multires), kernel, reality, precision, nmaps, ws.data_ptr(),
+                                              ws.numel() * ws.element_size(), _stream(f_wav.device)),
+           "s2let_axisym_synthesis_kernel")
     return f
+
+
+def hard_threshold(f_wav, thresholds, L: int, B: int, J_min: int, multires: bool = True,
+                   reality: int = REAL, kernel: int = KERNEL_SD):
+    """In place on the device: wavelet samples of scale j with magnitude below thresholds[j - J_min]
+    are set to zero (Eq. (23)).  Returns f_wav."""
+    dt = _map_dtype(reality)
+    _need_cuda(f_wav, "f_wav", dt)
+    nmaps = f_wav.shape[0] if f_wav.dim() == 2 else 1
+    if f_wav.numel() != nmaps * wav_size(L, B, J_min, multires, kernel):
+        raise ValueError("f_wav has the wrong size")
+    thr = np.ascontiguousarray(thresholds, dtype=np.float64)
+    if thr.shape != (j_max(L, B) - J_min + 1,):
+        raise ValueError("one threshold per wavelet scale is needed")
+    _check(_lib.s2let_hard_threshold(f_wav.data_ptr(), thr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), L, B,
+                                     J_min, int(multires), kernel, reality, nmaps, _stream(f_wav.device)),
+           "s2let_hard_threshold")
+    return f_wav
+
+
+def denoise(y, L: int, B: int, J_min: int, sigma: float, multires: bool = True, reality: int = REAL,
+            kernel: int = KERNEL_SD, nsigma: float = 3.0, precision: int = FP64):
+    """Wavelet hard-threshold denoising of maps y: analysis, thresholds T_j = nsigma * sigma_j on
+    the wavelet scales (the scaling part is kept), synthesis.  sigma is the standard deviation of
+    the white noise's harmonic coefficients.  Returns the denoised maps."""
+    f_wav, f_scal = analysis(y, L, B, J_min, multires, reality, precision, kernel=kernel)
+    hard_threshold(f_wav, nsigma * noise_std(L, B, J_min, sigma, kernel), L, B, J_min, multires, reality, kernel)
+    return synthesis(f_wav, f_scal, L, B, J_min, multires, reality, precision, kernel=kernel)
+
+
+def snr(s_lm, y_lm):
+    """SNR(y) = 10 log10(||s||^2 / ||y - s||^2) in dB, energies summed over harmonic coefficients
+    (Eqs. (20)-(21)); device or host tensors of f_lm."""
+    torch = _torch()
+    num = torch.sum(torch.abs(s_lm) ** 2)
+    den = torch.sum(torch.abs(y_lm - s_lm) ** 2)
+    return float(10.0 * torch.log10(num / den))
 
 
 def mw_inverse_adjoint(f, L: int, reality: int = REAL, precision: int = FP64, workspace=None):
@@ -340,12 +405,12 @@ def synthesis_adjoint(f, L: int, B: int, J_min: int, multires: bool = True, real
     return f_wav, f_scal
 
 
-def split_wav(f_wav, L: int, B: int, J_min: int, multires: bool = True):
+def split_wav(f_wav, L: int, B: int, J_min: int, multires: bool = True, kernel: int = KERNEL_SD):
     """Views of the concatenated wavelet maps: list over j = J_min..J of [nmaps, k_j, 2k_j-1]."""
     out, off = [], 0
     nmaps = f_wav.shape[0]
     for j in range(J_min, j_max(L, B) + 1):
-        k = bandlimit_wav(j, L, B, multires)
+        k = bandlimit_wav(j, L, B, multires, kernel)
         n = mw_size(k)
         out.append(f_wav[:, off:off + n].reshape(nmaps, k, 2 * k - 1))
         off += n

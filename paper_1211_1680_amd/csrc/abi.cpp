@@ -14,6 +14,17 @@
 #define S2LET_API extern "C" __attribute__((visibility("default")))
 
 namespace s2let {
+
+// The HIP error behind the last S2LET_EHIP returned on this thread.
+thread_local hipError_t g_last_hip = hipSuccess;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = e;
+  return S2LET_EHIP;
+}
+
+int to_status(hipError_t e) { return e == hipSuccess ? S2LET_OK : hip_fail(e); }
+
 namespace {
 
 struct WavTables {
@@ -25,7 +36,7 @@ struct WavTables {
 struct DevCache {
   std::map<int, ShtTables> sht;
   LegTables leg;
-  std::map<std::tuple<int, int, int>, WavTables> wav;
+  std::map<std::tuple<int, int, int, int>, WavTables> wav;   // (L, B, J_min, kernel)
 };
 
 std::mutex g_mu;
@@ -112,8 +123,32 @@ long long ipow_cap(int B, int e, long long cap) {
   return p;
 }
 
-int bl_wav(int j, int L, int B, int multires) { return multires ? (int)ipow_cap(B, j + 1, L) : L; }
-int bl_scal(int J_min, int L, int B, int multires) { return multires ? (int)ipow_cap(B, J_min, L) : L; }
+// ceil(L / B^e), e >= 0
+int ceil_div_pow(int L, int B, int e) {
+  long long p = 1;
+  for (int i = 0; i < e; ++i) {
+    p *= B;
+    if (p >= L) return 1;
+  }
+  return (int)((L + p - 1) / p);
+}
+
+int bl_wav(int j, int L, int B, int multires, int kernel = S2LET_KERNEL_SD) {
+  if (!multires) return L;
+  if (kernel == S2LET_KERNEL_BSPLINE) {
+    const int e = jmax_int(L, B) - j - 2;
+    return e <= 0 ? L : std::min(L, ceil_div_pow(L, B, e));
+  }
+  return (int)ipow_cap(B, j + 1, L);
+}
+int bl_scal(int J_min, int L, int B, int multires, int kernel = S2LET_KERNEL_SD) {
+  if (!multires) return L;
+  if (kernel == S2LET_KERNEL_BSPLINE) {
+    const int e = jmax_int(L, B) - J_min - 1;
+    return e <= 0 ? L : std::min(L, ceil_div_pow(L, B, e));
+  }
+  return (int)ipow_cap(B, J_min, L);
+}
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -151,17 +186,15 @@ Workspace carve(void* ws, int L, int C, bool wavelet) {
 int nparts_of(int k) { return legendre_forward_groups(k); }
 long long pstride_of(int k, const Batch& b) { return (long long)tri_rows(k) * b.C; }
 
-int to_status(hipError_t e) { return e == hipSuccess ? S2LET_OK : S2LET_EHIP; }
-
 // ---- plan cache (lock held by caller) ----
-int get_device(int* dev) { return hipGetDevice(dev) == hipSuccess ? S2LET_OK : S2LET_EHIP; }
+int get_device(int* dev) { return to_status(hipGetDevice(dev)); }
 
 int ensure_leg(DevCache& dc) {
   if (dc.leg.Lt == 0) {
     hipError_t e = build_leg_tables(S2LET_MAX_L, &dc.leg);
     if (e != hipSuccess) {
       free_leg_tables(&dc.leg);
-      return e == hipErrorOutOfMemory ? S2LET_ENOMEM : S2LET_EHIP;
+      return e == hipErrorOutOfMemory ? S2LET_ENOMEM : hip_fail(e);
     }
   }
   return S2LET_OK;
@@ -174,7 +207,7 @@ int ensure_sht(DevCache& dc, int k, ShtTables** out) {
     hipError_t e = build_sht_tables(k, &T);
     if (e != hipSuccess) {
       free_sht_tables(&T);
-      return e == hipErrorOutOfMemory ? S2LET_ENOMEM : S2LET_EHIP;
+      return e == hipErrorOutOfMemory ? S2LET_ENOMEM : hip_fail(e);
     }
     it = dc.sht.emplace(k, T).first;
   }
@@ -182,25 +215,26 @@ int ensure_sht(DevCache& dc, int k, ShtTables** out) {
   return S2LET_OK;
 }
 
-int ensure_wav(DevCache& dc, int L, int B, int J_min, WavTables** out) {
-  auto key = std::make_tuple(L, B, J_min);
+int ensure_wav(DevCache& dc, int L, int B, int J_min, int kernel, WavTables** out) {
+  auto key = std::make_tuple(L, B, J_min, kernel);
   auto it = dc.wav.find(key);
   if (it == dc.wav.end()) {
     WavTables W;
     W.J = jmax_int(L, B);
     const int ns = W.J - J_min + 1;
     std::vector<double> kappa((size_t)ns * L), eta(L);
-    tiling_host(L, B, J_min, W.J, kappa.data(), eta.data());
+    tiling_host_kernel(L, B, J_min, W.J, kernel, kappa.data(), eta.data());
     if (hipMalloc((void**)&W.kappa, sizeof(double) * kappa.size()) != hipSuccess) return S2LET_ENOMEM;
     if (hipMalloc((void**)&W.eta, sizeof(double) * eta.size()) != hipSuccess) {
       hipFree(W.kappa);
       return S2LET_ENOMEM;
     }
-    if (hipMemcpy(W.kappa, kappa.data(), sizeof(double) * kappa.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(W.eta, eta.data(), sizeof(double) * eta.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    hipError_t e = hipMemcpy(W.kappa, kappa.data(), sizeof(double) * kappa.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(W.eta, eta.data(), sizeof(double) * eta.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
       hipFree(W.kappa);
       hipFree(W.eta);
-      return S2LET_EHIP;
+      return hip_fail(e);
     }
     it = dc.wav.emplace(key, W).first;
   }
@@ -313,11 +347,11 @@ int check_wavelet(int L, int B, int J_min, int multires) {
   return S2LET_OK;
 }
 
-int64_t wav_size_int(int L, int B, int J_min, int multires) {
+int64_t wav_size_int(int L, int B, int J_min, int multires, int kernel = S2LET_KERNEL_SD) {
   const int J = jmax_int(L, B);
   int64_t tot = 0;
   for (int j = J_min; j <= J; ++j) {
-    const int64_t k = bl_wav(j, L, B, multires);
+    const int64_t k = bl_wav(j, L, B, multires, kernel);
     tot += k * (2 * k - 1);
   }
   return tot;
@@ -403,7 +437,7 @@ static int sht_maps_to_coefs(void* flm, const void* f, int L, int reality, int p
     if ((st = forward_batch(*T, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
     double2* out = (double2*)flm + (size_t)start * L * L;
     hipError_t e = launch_pack_flm(dc.leg, b, L, w.R, nparts_of(L), pstride_of(L, b), out, s);
-    if (e != hipSuccess) return S2LET_EHIP;
+    if (e != hipSuccess) return hip_fail(e);
   }
   return S2LET_OK;
 }
@@ -431,7 +465,7 @@ static int sht_coefs_to_maps(void* f, const void* flm, int L, int reality, int p
     const Workspace w = carve(ws, L, b.C, false);
     const double2* in = (const double2*)flm + (size_t)start * L * L;
     hipError_t e = launch_unpack_flm(dc.leg, b, L, in, w.S, s, adjoint);
-    if (e != hipSuccess) return S2LET_EHIP;
+    if (e != hipSuccess) return hip_fail(e);
     double* fout = (double*)f + (size_t)start * msz * cmul;
     if ((st = inverse_batch(*T, dc.leg, b, w.S, fout, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
   }
@@ -463,11 +497,13 @@ S2LET_API int mw_forward_adjoint(void* f, const void* flm, int L, int reality, i
 // real diagonal kernels and truncation, forward-transform adjoints at each scale).
 int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min, int multires,
                              int reality, int precision, int nmaps, void* ws, size_t ws_bytes, void* stream,
-                             bool adjoint, int cap) {
+                             bool adjoint, int cap, int kernel) {
   if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
     return S2LET_EINVAL;
   int st = check_wavelet(L, B, J_min, multires);
   if (st != S2LET_OK) return st;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE)
+    return kernel == S2LET_KERNEL_NEEDLET ? S2LET_EUNSUPPORTED : S2LET_EINVAL;
   int dev;
   if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev, cap)) != S2LET_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -475,21 +511,21 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
   DevCache& dc = g_cache[dev];
   if ((st = ensure_leg(dc)) != S2LET_OK) return st;
   WavTables* W;
-  if ((st = ensure_wav(dc, L, B, J_min, &W)) != S2LET_OK) return st;
+  if ((st = ensure_wav(dc, L, B, J_min, kernel, &W)) != S2LET_OK) return st;
   const int J = W->J;
-  const int kP = bl_scal(J_min, L, B, multires);
+  const int kP = bl_scal(J_min, L, B, multires, kernel);
   ShtTables *TL, *TP;
   if ((st = ensure_sht(dc, L, &TL)) != S2LET_OK) return st;
   if ((st = ensure_sht(dc, kP, &TP)) != S2LET_OK) return st;
   std::vector<ShtTables*> TJ;
   for (int j = J_min; j <= J; ++j) {
     ShtTables* t;
-    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires), &t)) != S2LET_OK) return st;
+    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires, kernel), &t)) != S2LET_OK) return st;
     TJ.push_back(t);
   }
   const int bcap = cap > 0 ? std::min(cap, batch_cap(reality)) : batch_cap(reality);
   const int cmul = reality == S2LET_REAL ? 1 : 2;
-  const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires),
+  const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires, kernel),
                 psz = s2let_mw_size(kP);
   for (int start = 0; start < nmaps; start += bcap) {
     const Batch b = make_batch(reality, std::min(bcap, nmaps - start));
@@ -498,15 +534,15 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
     if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
     // scaling part, Eq. (6)
     hipError_t e = tile_prof(dc.leg, b, w.R, L, w.S, kP, W->eta, 0, s);
-    if (e != hipSuccess) return S2LET_EHIP;
+    if (e != hipSuccess) return hip_fail(e);
     double* pout = (double*)f_scal + (size_t)start * psz * cmul;
     if ((st = inverse_batch(*TP, dc.leg, b, w.S, pout, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
     // wavelet scales, Eq. (4)
     int64_t off = 0;
     for (int j = J_min; j <= J; ++j) {
-      const int kj = bl_wav(j, L, B, multires);
+      const int kj = bl_wav(j, L, B, multires, kernel);
       e = tile_prof(dc.leg, b, w.R, L, w.S, kj, W->kappa + (size_t)(j - J_min) * L, 0, s);
-      if (e != hipSuccess) return S2LET_EHIP;
+      if (e != hipSuccess) return hip_fail(e);
       double* wout = (double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s, adjoint)) != S2LET_OK)
         return st;
@@ -521,11 +557,13 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
 // forward-transform adjoint at L).
 int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int L, int B, int J_min,
                              int multires, int reality, int precision, int nmaps, void* ws, size_t ws_bytes,
-                             void* stream, bool adjoint, int cap) {
+                             void* stream, bool adjoint, int cap, int kernel) {
   if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
     return S2LET_EINVAL;
   int st = check_wavelet(L, B, J_min, multires);
   if (st != S2LET_OK) return st;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE)
+    return kernel == S2LET_KERNEL_NEEDLET ? S2LET_EUNSUPPORTED : S2LET_EINVAL;
   int dev;
   if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev, cap)) != S2LET_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -533,21 +571,21 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
   DevCache& dc = g_cache[dev];
   if ((st = ensure_leg(dc)) != S2LET_OK) return st;
   WavTables* W;
-  if ((st = ensure_wav(dc, L, B, J_min, &W)) != S2LET_OK) return st;
+  if ((st = ensure_wav(dc, L, B, J_min, kernel, &W)) != S2LET_OK) return st;
   const int J = W->J;
-  const int kP = bl_scal(J_min, L, B, multires);
+  const int kP = bl_scal(J_min, L, B, multires, kernel);
   ShtTables *TL, *TP;
   if ((st = ensure_sht(dc, L, &TL)) != S2LET_OK) return st;
   if ((st = ensure_sht(dc, kP, &TP)) != S2LET_OK) return st;
   std::vector<ShtTables*> TJ;
   for (int j = J_min; j <= J; ++j) {
     ShtTables* t;
-    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires), &t)) != S2LET_OK) return st;
+    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires, kernel), &t)) != S2LET_OK) return st;
     TJ.push_back(t);
   }
   const int bcap = cap > 0 ? std::min(cap, batch_cap(reality)) : batch_cap(reality);
   const int cmul = reality == S2LET_REAL ? 1 : 2;
-  const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires),
+  const int64_t msz = s2let_mw_size(L), wsz = wav_size_int(L, B, J_min, multires, kernel),
                 psz = s2let_mw_size(kP);
   for (int start = 0; start < nmaps; start += bcap) {
     const Batch b = make_batch(reality, std::min(bcap, nmaps - start));
@@ -556,16 +594,16 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
     const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
     if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
     hipError_t e = tile_prof(dc.leg, b, w.R, kP, w.S, L, W->eta, 0, s);
-    if (e != hipSuccess) return S2LET_EHIP;
+    if (e != hipSuccess) return hip_fail(e);
     // wavelet scales, accumulated per Eq. (8)
     int64_t off = 0;
     for (int j = J_min; j <= J; ++j) {
-      const int kj = bl_wav(j, L, B, multires);
+      const int kj = bl_wav(j, L, B, multires, kernel);
       const double* win = (const double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s, adjoint)) != S2LET_OK)
         return st;
       e = tile_prof(dc.leg, b, w.R, kj, w.S, L, W->kappa + (size_t)(j - J_min) * L, 1, s);
-      if (e != hipSuccess) return S2LET_EHIP;
+      if (e != hipSuccess) return hip_fail(e);
       off += (int64_t)kj * (2 * kj - 1);
     }
     double* fout = (double*)f + (size_t)start * msz * cmul;
@@ -578,28 +616,113 @@ S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, in
                                     int multires, int reality, int precision, int nmaps, void* ws,
                                     size_t ws_bytes, void* stream) {
   return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, false, 0);
+                           stream, false, 0, S2LET_KERNEL_SD);
 }
 
 S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L, int B,
                                      int J_min, int multires, int reality, int precision, int nmaps,
                                      void* ws, size_t ws_bytes, void* stream) {
   return s2let_wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, false, 0);
+                           stream, false, 0, S2LET_KERNEL_SD);
 }
 
 S2LET_API int s2let_axisym_analysis_adjoint(void* f, const void* f_wav, const void* f_scal, int L, int B,
                                             int J_min, int multires, int reality, int precision, int nmaps,
                                             void* ws, size_t ws_bytes, void* stream) {
   return s2let_wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, true, 0);
+                           stream, true, 0, S2LET_KERNEL_SD);
 }
 
 S2LET_API int s2let_axisym_synthesis_adjoint(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
                                              int multires, int reality, int precision, int nmaps, void* ws,
                                              size_t ws_bytes, void* stream) {
   return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, true, 0);
+                           stream, true, 0, S2LET_KERNEL_SD);
+}
+
+S2LET_API int s2let_bandlimit_wav_kernel(int j, int L, int B, int multires, int kernel) {
+  if (j < 0 || L < 1 || B < 2) return S2LET_EINVAL;
+  if (kernel == S2LET_KERNEL_BSPLINE && L < 3) return S2LET_EINVAL;
+  if (kernel == S2LET_KERNEL_NEEDLET) return S2LET_EUNSUPPORTED;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE) return S2LET_EINVAL;
+  return bl_wav(j, L, B, multires, kernel);
+}
+
+S2LET_API int s2let_bandlimit_scal_kernel(int J_min, int L, int B, int multires, int kernel) {
+  if (J_min < 0 || L < 1 || B < 2) return S2LET_EINVAL;
+  if (kernel == S2LET_KERNEL_BSPLINE && L < 3) return S2LET_EINVAL;
+  if (kernel == S2LET_KERNEL_NEEDLET) return S2LET_EUNSUPPORTED;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE) return S2LET_EINVAL;
+  return bl_scal(J_min, L, B, multires, kernel);
+}
+
+S2LET_API int64_t s2let_wav_size_kernel(int L, int B, int J_min, int multires, int kernel) {
+  if (check_wavelet(L, B, J_min, multires) != S2LET_OK) return -1;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE) return -1;
+  return wav_size_int(L, B, J_min, multires, kernel);
+}
+
+S2LET_API int s2let_tiling_axisym_kernel(double* kappa, double* eta, int L, int B, int J_min, int kernel) {
+  if (!kappa || !eta) return S2LET_EINVAL;
+  if (check_wavelet(L, B, J_min, 0) != S2LET_OK) return S2LET_EINVAL;
+  if (kernel == S2LET_KERNEL_NEEDLET) return S2LET_EUNSUPPORTED;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE) return S2LET_EINVAL;
+  tiling_host_kernel(L, B, J_min, jmax_int(L, B), kernel, kappa, eta);
+  return S2LET_OK;
+}
+
+S2LET_API int s2let_axisym_analysis_kernel(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                                           int multires, int kernel, int reality, int precision, int nmaps,
+                                           void* ws, size_t ws_bytes, void* stream) {
+  return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                                 stream, false, 0, kernel);
+}
+
+S2LET_API int s2let_axisym_synthesis_kernel(void* f, const void* f_wav, const void* f_scal, int L, int B,
+                                            int J_min, int multires, int kernel, int reality, int precision,
+                                            int nmaps, void* ws, size_t ws_bytes, void* stream) {
+  return s2let_wav_scales_to_map(f, f_wav, f_scal, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
+                                 stream, false, 0, kernel);
+}
+
+S2LET_API int s2let_noise_std_axisym(double* sigma_wav, int L, int B, int J_min, int kernel, double sigma) {
+  if (!sigma_wav || !(sigma >= 0.0)) return S2LET_EINVAL;
+  if (check_wavelet(L, B, J_min, 0) != S2LET_OK) return S2LET_EINVAL;
+  if (kernel == S2LET_KERNEL_NEEDLET) return S2LET_EUNSUPPORTED;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE) return S2LET_EINVAL;
+  const int J = jmax_int(L, B), ns = J - J_min + 1;
+  std::vector<double> kappa((size_t)ns * L), eta(L);
+  tiling_host_kernel(L, B, J_min, J, kernel, kappa.data(), eta.data());
+  for (int j = 0; j < ns; ++j) {
+    long double acc = 0.0L;
+    for (int l = 0; l < L; ++l) {
+      const long double kv = kappa[(size_t)j * L + l];
+      acc += (2.0L * l + 1.0L) / (4.0L * 3.141592653589793238462643383279502884L) * kv * kv;
+    }
+    sigma_wav[j] = (double)(sigma * sqrtl(acc));
+  }
+  return S2LET_OK;
+}
+
+S2LET_API int s2let_hard_threshold(void* f_wav, const double* thresholds, int L, int B, int J_min, int multires,
+                                   int kernel, int reality, int nmaps, void* stream) {
+  if (!f_wav || !thresholds || !aligned16(f_wav) || nmaps < 1) return S2LET_EINVAL;
+  if (reality != S2LET_REAL && reality != S2LET_COMPLEX) return S2LET_EINVAL;
+  if (check_wavelet(L, B, J_min, multires) != S2LET_OK) return S2LET_EINVAL;
+  if (kernel == S2LET_KERNEL_NEEDLET) return S2LET_EUNSUPPORTED;
+  if (kernel != S2LET_KERNEL_SD && kernel != S2LET_KERNEL_BSPLINE) return S2LET_EINVAL;
+  const int J = jmax_int(L, B);
+  const int64_t wsz = wav_size_int(L, B, J_min, multires, kernel);
+  int64_t off = 0;
+  for (int j = J_min; j <= J; ++j) {
+    const int64_t k = bl_wav(j, L, B, multires, kernel);
+    const int64_t n = k * (2 * k - 1);
+    hipError_t e = launch_hard_threshold((double*)f_wav, off, n, wsz, nmaps, reality == S2LET_COMPLEX,
+                                         thresholds[j - J_min], (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    off += n;
+  }
+  return S2LET_OK;
 }
 
 S2LET_API int s2let_profile_enable(int on) {
@@ -661,7 +784,7 @@ S2LET_API int s2let_profile_query(int stage, double* ms, int64_t* launches, doub
 
 S2LET_API int s2let_sync(void* stream) {
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-  if (e != hipSuccess) return S2LET_EHIP;
+  if (e != hipSuccess) return hip_fail(e);
   e = hipGetLastError();
   return e == hipSuccess ? S2LET_OK : S2LET_EHIP;
 }
@@ -693,5 +816,9 @@ S2LET_API const char* s2let_strerror(int status) {
   }
   return "unknown status";
 }
+
+S2LET_API int s2let_last_hip_error(void) { return (int)g_last_hip; }
+
+S2LET_API const char* s2let_last_hip_error_name(void) { return hipGetErrorName(g_last_hip); }
 
 S2LET_API const char* s2let_version(void) { return "s2let_mi355x 0.1 (gfx950)"; }

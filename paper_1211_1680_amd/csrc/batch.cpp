@@ -22,10 +22,10 @@
 // capped wavelet drivers of abi.cpp
 int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min, int multires,
                             int reality, int precision, int nmaps, void* ws, size_t ws_bytes, void* stream,
-                            bool adjoint, int cap);
+                            bool adjoint, int cap, int kernel);
 int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int L, int B, int J_min,
                             int multires, int reality, int precision, int nmaps, void* ws, size_t ws_bytes,
-                            void* stream, bool adjoint, int cap);
+                            void* stream, bool adjoint, int cap, int kernel);
 
 namespace {
 
@@ -99,7 +99,7 @@ int copy_segments(const s2let_batch* b, const double* src, double* dst, int firs
   for (int i = first; i < first + count; ++i) maxlen = std::max(maxlen, b->segs[i].len);
   const unsigned gx = (unsigned)std::min<long long>((maxlen + 255) / 256, 1024);
   k_seg_copy<<<dim3(gx > 0 ? gx : 1, count), 256, 0, s>>>(src, dst, b->segs_dev + first);
-  return hipGetLastError() == hipSuccess ? S2LET_OK : S2LET_EHIP;
+  return s2let::to_status(hipGetLastError());
 }
 
 // analysis (f -> f_wav, f_scal), then optionally synthesis of the analysis output (-> rec), of
@@ -123,13 +123,13 @@ int run(s2let_batch* b, void* f_wav, void* f_scal, void* rec, const void* f, voi
     double* rc = stage + g.st_rec;
     if ((st = copy_segments(b, (const double*)f, in, g.seg_first[0], n, s)) != S2LET_OK) return st;
     if ((st = s2let_wav_map_to_scales(wv, sc, in, g.L, g.B, b->J_min, b->multires, b->reality, b->precision, n,
-                                      wsg, b->ws_stream, s, false, b->cap)) != S2LET_OK)
+                                      wsg, b->ws_stream, s, false, b->cap, S2LET_KERNEL_SD)) != S2LET_OK)
       return st;
     if ((st = copy_segments(b, wv, (double*)f_wav, g.seg_first[1], n, s)) != S2LET_OK) return st;
     if ((st = copy_segments(b, sc, (double*)f_scal, g.seg_first[2], n, s)) != S2LET_OK) return st;
     if (do_synthesis) {
       if ((st = s2let_wav_scales_to_map(rc, wv, sc, g.L, g.B, b->J_min, b->multires, b->reality, b->precision, n,
-                                        wsg, b->ws_stream, s, false, b->cap)) != S2LET_OK)
+                                        wsg, b->ws_stream, s, false, b->cap, S2LET_KERNEL_SD)) != S2LET_OK)
         return st;
       if ((st = copy_segments(b, rc, (double*)rec, g.seg_first[3], n, s)) != S2LET_OK) return st;
     }

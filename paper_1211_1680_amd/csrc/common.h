@@ -116,6 +116,11 @@ hipError_t launch_legendre_forward_bf16(const ShtTables& T, const LegTables& G, 
 hipError_t launch_legendre_inverse_bf16(const ShtTables& T, const LegTables& G, const Batch& b,
                                         const double* S, double* FT, unsigned long long* counter,
                                         hipStream_t s);
+// Records e as the HIP error behind the status and returns S2LET_EHIP (defined with the C ABI).
+int hip_fail(hipError_t e);
+int to_status(hipError_t e);
+hipError_t launch_hard_threshold(double* w, long long off, long long n, long long stride, int nmaps, bool cplx,
+                                 double thr, hipStream_t s);
 // dst[b][a][c] = scale * src[a][b][c] over a k x k grid of C-column rows.
 hipError_t launch_transpose_rows(const Batch& b, int k, const double* src, double* dst, double scale,
                                  hipStream_t s);

@@ -132,6 +132,37 @@ hipError_t launch_transpose_rows(const Batch& b, int k, const double* src, doubl
   return hipGetLastError();
 }
 
+// Hard thresholding (Eq. (23)): samples [off, off + n) of every map (map stride `stride`
+// samples) with magnitude below thr are set to zero; complex samples are (re, im) pairs.
+__global__ void k_hard_threshold(double* __restrict__ w, long long off, long long n, long long stride, int nmaps,
+                                 int cplx, double thr) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= n || a >= nmaps) return;
+  if (cplx) {
+    double2* p = reinterpret_cast<double2*>(w) + (size_t)a * stride + off + i;
+    const double2 v = *p;
+    if (hypot(v.x, v.y) < thr) *p = make_double2(0.0, 0.0);
+  } else {
+    double* p = w + (size_t)a * stride + off + i;
+    if (fabs(*p) < thr) *p = 0.0;
+  }
+}
+
+hipError_t launch_hard_threshold(double* w, long long off, long long n, long long stride, int nmaps, bool cplx,
+                                 double thr, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t esz = cplx ? 2 : 1;
+  for (int a0 = 0; a0 < nmaps; a0 += 65535) {   // grid.y stays within its limit
+    const int na = std::min(65535, nmaps - a0);
+    dim3 grid((unsigned)((n + 255) / 256), na);
+    k_hard_threshold<<<grid, 256, 0, s>>>(w + (size_t)a0 * stride * esz, off, n, stride, na, cplx ? 1 : 0, thr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const double2* flm, double* S,
                              hipStream_t s, bool herm) {
   dim3 grid((k * b.C + 255) / 256, k);

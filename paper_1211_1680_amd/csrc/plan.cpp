@@ -8,6 +8,7 @@
 #include <map>
 #include <vector>
 
+#include "../../include/s2let_mi355x.h"
 #include "common.h"
 #include "plan.h"
 
@@ -362,6 +363,48 @@ double k_lambda_host(double t, double lam) {
   const LD den = integrate(1.0L / L, 1.0L, L, panels);
   const LD num = integrate((LD)t, 1.0L, L, panels);
   return (double)(num / den);
+}
+
+// B-spline generating function (footnote to Sect. 2.2): k(t) = (3/2) B_3(2 t lambda^(J-1) / L) with
+// the cubic B-spline B_3(x) = (|x-2|^3 - 4|x-1|^3 + 6|x|^3 - 4|x+1|^3 + |x+2|^3) / 12.  eta(l) =
+// sqrt k(l / lambda^J_min), kappa_j(l) = sqrt(k(l / lambda^(j+1)) - k(l / lambda^j)) for j < J and,
+// so that the tiling sums to one below L, kappa_J(l) = sqrt(1 - k(l / lambda^J)).
+static void tiling_bspline(int L, int B, int J_min, int J, double* kappa, double* eta) {
+  const LD lam = (LD)B;
+  // Cubic B-spline of Eq. (18) in its piecewise-polynomial form (the five-term sum of cubes is
+  // the same function but cancels badly near the end of the support, where kappa_j is small).
+  auto b3 = [](LD x) {
+    x = x < 0 ? -x : x;
+    if (x >= 2.0L) return 0.0L;
+    if (x >= 1.0L) {
+      const LD r = 2.0L - x;
+      return r * r * r / 6.0L;
+    }
+    return 2.0L / 3.0L - x * x + x * x * x / 2.0L;
+  };
+  LD pJ1 = 1.0L;
+  for (int i = 0; i < J - 1; ++i) pJ1 *= lam;
+  auto k = [&](LD t) {
+    const LD x = 2.0L * t * pJ1 / (LD)L;
+    return x >= 2.0L ? 0.0L : 1.5L * b3(x);
+  };
+  std::vector<LD> pw(J + 2);
+  pw[0] = 1.0L;
+  for (int j = 1; j < J + 2; ++j) pw[j] = pw[j - 1] * lam;
+  for (int l = 0; l < L; ++l) {
+    eta[l] = (double)sqrtl(std::max(0.0L, k((LD)l / pw[J_min])));
+    for (int j = J_min; j <= J; ++j) {
+      const LD k2 = j < J ? k((LD)l / pw[j + 1]) - k((LD)l / pw[j]) : 1.0L - k((LD)l / pw[J]);
+      kappa[(size_t)(j - J_min) * L + l] = (double)sqrtl(std::max(0.0L, k2));
+    }
+  }
+}
+
+void tiling_host_kernel(int L, int B, int J_min, int J, int kernel, double* kappa, double* eta) {
+  if (kernel == S2LET_KERNEL_BSPLINE)
+    tiling_bspline(L, B, J_min, J, kappa, eta);
+  else
+    tiling_host(L, B, J_min, J, kappa, eta);
 }
 
 void tiling_host(int L, int B, int J_min, int J, double* kappa, double* eta) {

@@ -13,4 +13,5 @@ void leg_factors_host(int Lt, std::vector<double>* alpha, std::vector<double>* b
                       std::vector<double>* dfac, std::vector<double>* cm);
 double k_lambda_host(double t, double lam);
 void tiling_host(int L, int B, int J_min, int J, double* kappa, double* eta);
+void tiling_host_kernel(int L, int B, int J_min, int J, int kernel, double* kappa, double* eta);
 }  // namespace s2let

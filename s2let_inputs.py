@@ -97,3 +97,16 @@ def random_unit_flm_basis(L: int, ell: int, m: int) -> np.ndarray:
     out = np.zeros((1, L * L), dtype=np.complex128)
     out[0, ell * ell + ell + m] = 1.0
     return out
+
+
+def denoise_workload(L: int, nmaps: int = 1, seed: int = 9, snr_db: float = 11.78, alpha: float = 3.0):
+    """Signal-plus-white-noise maps for the hard-thresholding denoising example of Sect. 4.3:
+    s with spectrum C_l = (l + 1)^(-alpha) (most power on large scales), and real white noise
+    n with E|n_lm|^2 = sigma^2 for every (l, m), sigma chosen so that the expected noise energy
+    sigma^2 L^2 sets SNR(y) to snr_db against the mean energy of the drawn signals (11.78 dB is
+    the noisy map of that example).  Returns (s_lm, n_lm, sigma), both [nmaps, L*L]."""
+    s = random_flm(L, nmaps, reality=True, seed=seed, cl=spectrum_power(L, alpha))
+    energy = float(np.mean(np.sum(np.abs(s) ** 2, axis=1)))
+    sigma = float(np.sqrt(energy / (L * L * 10.0 ** (snr_db / 10.0))))
+    n = random_flm(L, nmaps, reality=True, seed=seed + 5000, cl=np.full(L, sigma * sigma))
+    return s, n, sigma

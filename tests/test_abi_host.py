@@ -109,3 +109,78 @@ def test_workspace_size_monotone():
     c = s2.workspace_size(128, nmaps=16)
     assert 0 < a < b < c
     assert s2.workspace_size(2048, 2, 3, True, s2.REAL, s2.FP64, 16, True) < 8 * 2 ** 30
+
+
+# ---------------------------------------------------------------- generating functions, noise model
+@pytest.mark.parametrize("L,B,J_min", [(16, 2, 0), (50, 3, 2), (128, 2, 0), (128, 3, 2), (300, 3, 1), (2048, 2, 3)])
+def test_bspline_tiling_and_bandlimits_match_oracle(L, B, J_min):
+    """Host B-spline tiling (long double) against the oracle's exact rationals; band-limits and
+    sizes for both kernels."""
+    kappa, eta = s2.tiling_axisym(L, B, J_min, s2.KERNEL_BSPLINE)
+    ok, oe = oracle.tiling(L, B, J_min, "bspline")
+    assert np.max(np.abs(kappa - ok)) < 1e-15 and np.max(np.abs(eta - oe)) < 1e-15
+    for kernel, name in ((s2.KERNEL_SD, "sd"), (s2.KERNEL_BSPLINE, "bspline")):
+        for mr in (False, True):
+            tot = 0
+            for j in range(J_min, oracle.j_max(L, B) + 1):
+                k = oracle.bandlimit_wav(j, L, B, mr, name)
+                assert s2.bandlimit_wav(j, L, B, mr, kernel) == k
+                tot += k * (2 * k - 1)
+            assert s2.wav_size(L, B, J_min, mr, kernel) == tot
+            assert s2.bandlimit_scal(J_min, L, B, mr, kernel) == oracle.bandlimit_scal(J_min, L, B, mr, name)
+
+
+def test_sd_kernel_calls_equal_default_calls():
+    k1, e1 = s2.tiling_axisym(128, 3, 2)
+    k2, e2 = s2.tiling_axisym(128, 3, 2, s2.KERNEL_SD)
+    assert np.array_equal(k1, k2) and np.array_equal(e1, e2)
+    assert s2.lib.s2let_wav_size(512, 2, 2, 1) == s2.lib.s2let_wav_size_kernel(512, 2, 2, 1, s2.KERNEL_SD)
+
+
+@pytest.mark.parametrize("kernel,name", [(0, "sd"), (1, "bspline")])
+def test_noise_std_matches_oracle(kernel, name):
+    for (L, B, J_min, sigma) in [(64, 2, 0, 1.0), (128, 2, 0, 0.05), (300, 3, 1, 2.5)]:
+        got = s2.noise_std(L, B, J_min, sigma, kernel)
+        ref = oracle.noise_std(L, B, J_min, sigma, name)
+        assert np.max(np.abs(got - ref) / ref) < 1e-14
+
+
+def test_kernel_arguments_rejected_without_device():
+    lib = s2.lib
+    ws, buf = ctypes.c_void_p(4096), ctypes.c_void_p(4096)
+    dp = ctypes.POINTER(ctypes.c_double)
+    k = np.zeros(64 * 8)
+    e = np.zeros(64)
+    assert lib.s2let_tiling_axisym_kernel(k.ctypes.data_as(dp), e.ctypes.data_as(dp), 64, 2, 0, 2) == s2.EUNSUPPORTED
+    assert lib.s2let_tiling_axisym_kernel(k.ctypes.data_as(dp), e.ctypes.data_as(dp), 64, 2, 0, 7) == s2.EINVAL
+    assert lib.s2let_bandlimit_wav_kernel(3, 64, 2, 1, 2) == s2.EUNSUPPORTED
+    assert lib.s2let_bandlimit_scal_kernel(1, 64, 2, 1, 9) == s2.EINVAL
+    assert lib.s2let_wav_size_kernel(64, 2, 0, 1, 5) == -1
+    a = lib.s2let_axisym_analysis_kernel
+    assert a(buf, buf, buf, 64, 2, 0, 1, 2, 0, 0, 1, ws, 1 << 40, None) == s2.EUNSUPPORTED
+    assert a(buf, buf, buf, 64, 2, 0, 1, -1, 0, 0, 1, ws, 1 << 40, None) == s2.EINVAL
+    sy = lib.s2let_axisym_synthesis_kernel
+    assert sy(buf, buf, buf, 64, 2, 0, 1, 2, 0, 0, 1, ws, 1 << 40, None) == s2.EUNSUPPORTED
+    sig = np.zeros(8)
+    assert lib.s2let_noise_std_axisym(sig.ctypes.data_as(dp), 64, 2, 0, 0, -1.0) == s2.EINVAL
+    assert lib.s2let_noise_std_axisym(sig.ctypes.data_as(dp), 64, 2, 0, 2, 1.0) == s2.EUNSUPPORTED
+    thr = np.ones(8)
+    h = lib.s2let_hard_threshold
+    assert h(None, thr.ctypes.data_as(dp), 64, 2, 0, 1, 0, 0, 1, None) == s2.EINVAL
+    assert h(buf, None, 64, 2, 0, 1, 0, 0, 1, None) == s2.EINVAL
+    assert h(buf, thr.ctypes.data_as(dp), 64, 2, 0, 1, 0, 3, 1, None) == s2.EINVAL
+    assert h(buf, thr.ctypes.data_as(dp), 64, 2, 0, 1, 2, 0, 1, None) == s2.EUNSUPPORTED
+    assert h(buf, thr.ctypes.data_as(dp), 64, 2, 0, 1, 0, 0, 0, None) == s2.EINVAL
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must not map a second HIP/HSA runtime into the process
+    (two HSA runtimes cannot both open the device)."""
+    import subprocess
+    import sys
+    code = ("import paper_1211_1680_amd, torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l or 'libhsa-runtime64' in l}\n"
+            "print(len([x for x in libs if 'amdhip64' in x]), len([x for x in libs if 'hsa-runtime64' in x]))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"], out.stdout

@@ -34,17 +34,25 @@ PEAK_HBM_GBS = 8000.0
 # scaled by known bytes / counter reading on a plain 1 GiB copy kernel (factors 2.0 and 1.0).
 # Valid only for the kernel source they were taken on (sha256 below); otherwise reported as null.
 MEASURED_TRAFFIC = {
-    "source": "paper_1211_1680_amd/csrc/kernels_legendre.hip",
-    "sha256": "53a1d006120e3da2b6e87d13d3aa60126b2b6bfa8ac25ef6a56a6ecc11d3760c",
-    "bytes_per_launch": {"legendre_analysis": 9.798e8, "legendre_synthesis": 2.3766e9},
+    # the Legendre kernels' sources; the counters are reported only while these files are unchanged
+    "sources": ["paper_1211_1680_amd/csrc/kernels_legendre.hip", "paper_1211_1680_amd/csrc/legendre_rec.h"],
+    "sha256": None,
+    "bytes_per_launch": {},
 }
 
 
-def measured_traffic(stage):
+def sources_sha256(paths):
     import hashlib
-    path = os.path.join(ROOT, MEASURED_TRAFFIC["source"])
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage):
     try:
-        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
+        sha = sources_sha256(MEASURED_TRAFFIC["sources"])
     except OSError:
         return None
     if sha != MEASURED_TRAFFIC["sha256"]:

@@ -183,7 +183,14 @@ Workspace carve(void* ws, int L, int C, bool wavelet) {
 }
 
 // partial-sum layout of the forward Legendre step at band-limit k
-int nparts_of(int k) { return legendre_forward_groups(k); }
+// The FP64 forward and inverse transforms at the band-limit with compiled transforms run their
+// Legendre steps on the symmetric grid (see launch_theta_2048 / launch_resample_2048).
+bool sym_path(int k, const Batch& b, int precision, bool adjoint) {
+  return k == 2048 && precision == S2LET_FP64 && !adjoint && b.C >= 16;
+}
+int nparts_of(int k, const Batch& b, int precision, bool adjoint) {
+  return sym_path(k, b, precision, adjoint) ? legendre_forward_groups_sym(k) : legendre_forward_groups(k);
+}
 long long pstride_of(int k, const Batch& b) { return (long long)tri_rows(k) * b.C; }
 
 // ---- plan cache (lock held by caller) ----
@@ -259,25 +266,30 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   if (r) r->bytes = mapb + colb;
   if ((e = launch_phi_forward(T, b, f, map_stride, w.GT, s)) != hipSuccess) return to_status(e);
   prof_end(r, s);
+  const bool sym = sym_path(T.k, b, precision, adjoint);
   r = prof_begin(ST_THETA, s);
   if (r) r->bytes = 2.0 * colb;
   if (adjoint)
     e = launch_transpose_rows(b, T.k, w.GT, w.HM, n / (2.0 * M_PI), s);
+  else if (sym)
+    e = launch_theta_2048(T, b, w.GT, w.HM, s, true);
   else
     e = launch_theta(T, b, w.GT, w.HM, s);
   if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
   r = prof_begin(ST_LEG_FWD, s);
   if (r) {
-    r->triples = triples_of(T.k);
+    r->triples = sym ? triples_of(T.k) / 2.0 : triples_of(T.k);
     r->rec_flops = 3.0;
     r->col_flops = 2.0 * b.used;
     r->flops_full = r->triples * (r->rec_flops + r->col_flops);
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
-  if ((e = launch_legendre_forward(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r),
-                                   s)) != hipSuccess)
-    return to_status(e);
+  if (sym)
+    e = launch_legendre_forward_sym(T, G, b, w.HM, w.R, pstride_of(T.k, b), prof_counter(r), s);
+  else
+    e = launch_legendre_forward(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r), s);
+  if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
   return S2LET_OK;
 }
@@ -292,17 +304,28 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   const double k = T.k, n = T.n;
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
   const double colb = 8.0 * b.used * k * k;
+  const bool sym = sym_path(T.k, b, precision, adjoint);
   ProfRec* r = prof_begin(ST_LEG_INV, s);
   if (r) {
-    r->triples = triples_of(T.k);
+    r->triples = sym ? triples_of(T.k) / 2.0 : triples_of(T.k);
     r->rec_flops = 3.0;
     r->col_flops = 2.0 * b.used;
     r->flops_full = r->triples * (r->rec_flops + r->col_flops);
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
-  if ((e = launch_legendre_inverse(T, G, b, S, w.GT, precision, prof_counter(r), s)) != hipSuccess)
-    return to_status(e);
+  if (sym)
+    e = launch_legendre_inverse_sym(T, G, b, S, w.HM, prof_counter(r), s);
+  else
+    e = launch_legendre_inverse(T, G, b, S, w.GT, precision, prof_counter(r), s);
+  if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
+  if (sym) {
+    // symmetric grid -> MW nodes (counted with the theta-type stages)
+    r = prof_begin(ST_THETA, s);
+    if (r) r->bytes = 2.0 * colb;
+    if ((e = launch_resample_2048(T, b, w.HM, w.GT, s)) != hipSuccess) return to_status(e);
+    prof_end(r, s);
+  }
   if (adjoint) {
     r = prof_begin(ST_THETA, s);
     if (r) r->bytes = 4.0 * colb;
@@ -317,7 +340,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   return S2LET_OK;
 }
 
-hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int ks, double* dst, int kd,
+hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int ks, int nparts, double* dst, int kd,
                      const double* kern, int accumulate, hipStream_t s) {
   ProfRec* r = prof_begin(ST_TILE, s);
   if (r) {
@@ -326,7 +349,7 @@ hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int 
     const double tk = kk * (kk + 1) / 2.0;
     r->bytes = 8.0 * b.used * (accumulate ? 3.0 * tk : tk + (double)tri_rows(kd));
   }
-  hipError_t e = launch_tile(G, b, src, ks, nparts_of(ks), pstride_of(ks, b), dst, kd, kern, accumulate, s);
+  hipError_t e = launch_tile(G, b, src, ks, nparts, pstride_of(ks, b), dst, kd, kern, accumulate, s);
   prof_end(r, s);
   return e;
 }
@@ -436,7 +459,7 @@ static int sht_maps_to_coefs(void* flm, const void* f, int L, int reality, int p
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
     if ((st = forward_batch(*T, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
     double2* out = (double2*)flm + (size_t)start * L * L;
-    hipError_t e = launch_pack_flm(dc.leg, b, L, w.R, nparts_of(L), pstride_of(L, b), out, s);
+    hipError_t e = launch_pack_flm(dc.leg, b, L, w.R, nparts_of(L, b, precision, adjoint), pstride_of(L, b), out, s);
     if (e != hipSuccess) return hip_fail(e);
   }
   return S2LET_OK;
@@ -533,7 +556,7 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
     if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
     // scaling part, Eq. (6)
-    hipError_t e = tile_prof(dc.leg, b, w.R, L, w.S, kP, W->eta, 0, s);
+    hipError_t e = tile_prof(dc.leg, b, w.R, L, nparts_of(L, b, precision, adjoint), w.S, kP, W->eta, 0, s);
     if (e != hipSuccess) return hip_fail(e);
     double* pout = (double*)f_scal + (size_t)start * psz * cmul;
     if ((st = inverse_batch(*TP, dc.leg, b, w.S, pout, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
@@ -541,7 +564,8 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
     int64_t off = 0;
     for (int j = J_min; j <= J; ++j) {
       const int kj = bl_wav(j, L, B, multires, kernel);
-      e = tile_prof(dc.leg, b, w.R, L, w.S, kj, W->kappa + (size_t)(j - J_min) * L, 0, s);
+      e = tile_prof(dc.leg, b, w.R, L, nparts_of(L, b, precision, adjoint), w.S, kj,
+                    W->kappa + (size_t)(j - J_min) * L, 0, s);
       if (e != hipSuccess) return hip_fail(e);
       double* wout = (double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s, adjoint)) != S2LET_OK)
@@ -593,7 +617,7 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
     // scaling part
     const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
     if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
-    hipError_t e = tile_prof(dc.leg, b, w.R, kP, w.S, L, W->eta, 0, s);
+    hipError_t e = tile_prof(dc.leg, b, w.R, kP, nparts_of(kP, b, precision, adjoint), w.S, L, W->eta, 0, s);
     if (e != hipSuccess) return hip_fail(e);
     // wavelet scales, accumulated per Eq. (8)
     int64_t off = 0;
@@ -602,7 +626,8 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
       const double* win = (const double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s, adjoint)) != S2LET_OK)
         return st;
-      e = tile_prof(dc.leg, b, w.R, kj, w.S, L, W->kappa + (size_t)(j - J_min) * L, 1, s);
+      e = tile_prof(dc.leg, b, w.R, kj, nparts_of(kj, b, precision, adjoint), w.S, L,
+                    W->kappa + (size_t)(j - J_min) * L, 1, s);
       if (e != hipSuccess) return hip_fail(e);
       off += (int64_t)kj * (2 * kj - 1);
     }

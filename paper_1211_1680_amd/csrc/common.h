@@ -60,6 +60,16 @@ struct ShtTables {
   double* sx = nullptr;        // sign of cos(theta_t) (+1 at the equator)
   double* pole = nullptr;      // column t = k-1 of the odd-parity theta operator (see plan.cpp)
   double2* hphase = nullptr;   // exp(-i pi j / n) for j in [-(k-1), k-1], index j+k-1
+  // Symmetric auxiliary grid psi_s = pi (2s+1) / (2k), s < 2k on the circle (built for the band-limits
+  // that have the compiled transforms): the theta stage evaluates its output there, and the
+  // Legendre steps run on the northern half s < k/2, where lambda_lm(pi - psi) = (-1)^(l+m) lambda_lm(psi).
+  int sym = 0;
+  double* ut_s = nullptr;      // |cos psi_s| - 1 = -2 sin^2(psi_s / 2), s < k/2
+  double* st_s = nullptr;      // sin psi_s, s < k/2
+  double* sx_s = nullptr;      // +1 (northern nodes)
+  double2* psph = nullptr;     // (n / 2k) exp(-i pi j / 2k), j in [-(k-1), k-1]: theta-stage output phase
+  double* pole_s = nullptr;    // psi-grid column of the odd-parity theta operator for the pole input, s < k
+  double2* rsph = nullptr;     // exp(-i pi j / 2k) exp(i pi j / n) / (4k), j in [-(k-1), k-1]: resampling
 };
 
 // Tables indexed by (l, m) up to a maximum band-limit Lt (shared by every k <= Lt).
@@ -96,7 +106,18 @@ hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* 
 bool fft_k2048_applies(const ShtTables& T);
 hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
                                    double* GT, hipStream_t s);
-hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
+hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s,
+                             bool sym = false);
+// Symmetric-grid variants (T.sym; FP64, C in {16, 32}): theta stage onto the psi grid (HM holds
+// the north/south sums in rows s < k/2 and differences in rows k/2 + s), the Legendre steps on
+// the northern nodes (the synthesis writes FS[m][s][c], s < k), and the resampling FS -> FT[t][m][c].
+hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
+int legendre_forward_groups_sym(int k);
+hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
+                                       double* R, long long part_stride, unsigned long long* counter,
+                                       hipStream_t s);
+hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* S,
+                                       double* FS, unsigned long long* counter, hipStream_t s);
 hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
                                    int64_t map_stride, hipStream_t s);
 // Legendre contraction, forward: HM[m][t][c] -> R[tri_off(k,m)+l-m][c] = sum_t z_lm(theta_t) H',

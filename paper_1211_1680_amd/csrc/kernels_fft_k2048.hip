@@ -26,6 +26,9 @@ struct K2048Args {
   const double2* khat1;
   const double2* hphase;
   const double* pole;         // pole column of the odd-parity theta operator
+  const double2* psph;        // symmetric grid: theta-stage output phase
+  const double* pole_s;       // symmetric grid: pole column
+  const double2* rsph;        // symmetric grid: resampling phase
 };
 
 __device__ __forceinline__ void stage_tables(const K2048Args& A, double2* w6lo, double2* w6hi, double2* w5lo,
@@ -98,6 +101,12 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const d
 }
 
 // theta stage (see k_theta): GT[(t*k + m)*C + c] -> HM[(m*k + t)*C + c].
+// SYM: the output transform evaluates on the symmetric grid psi_s = pi (2s+1) / (2k) instead of
+// the MW nodes (a 4096-point FFT in place of the 4095-point DFT; the weight's p = +-1 terms still
+// act only through the odd-m pole sample, now through the psi-grid pole column), folds s and
+// 2k-1-s, and writes the north/south sums and differences for the Legendre analysis on s < k/2:
+// HM[(m*k + s)*C + c] = H(s) + H(k-1-s), HM[(m*k + k/2 + s)*C + c] = H(s) - H(k-1-s).
+template <bool SYM>
 __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double* __restrict__ GT,
                                                       double* __restrict__ HM, int C, int nprob) {
   __shared__ double2 buf[NBUF];
@@ -127,7 +136,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
         const double* rO = GT + ((size_t)tt * K + mO) * C + 2 * s;
         g.x += sg * rO[0];
         g.y += sg * rO[1];
-        if (t < K - 1) {
+        if (!SYM && t < K - 1) {
           racc.x = fma(A.pole[t], rO[0], racc.x);
           racc.y = fma(A.pole[t], rO[1], racc.y);
         }
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
     }
     buf[lds_pad(t)] = g;
   }
-  {
+  if (!SYM) {
     const double2 prow = problem_sum(racc, TT, red_scratch);
     if (lt == 0) prow_s = prow;
   }
@@ -182,9 +191,42 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       const int idx = lt + i * TT;
       if (idx < NJ) {
         const int jp = idx - (K - 1);
-        if (((jp - P) & 1) == 0) keep[i] = cmul(A.hphase[idx], buf[lds_pad((-(jp - P) / 2) & (NC - 1))]);
+        if (((jp - P) & 1) == 0)
+          keep[i] = cmul(SYM ? A.psph[idx] : A.hphase[idx], buf[lds_pad((-(jp - P) / 2) & (NC - 1))]);
       }
     }
+  }
+  __syncthreads();
+  if constexpr (SYM) {
+    // I(j') at j' mod 4096 (slot 2048 stays empty), FFT onto the psi grid
+    if (lt == 0) buf[lds_pad(K)] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * TT;
+      if (idx < NJ) buf[lds_pad((idx - (K - 1)) & (NC - 1))] = keep[i];
+    }
+    __syncthreads();
+    fft4096<false, TT>(buf, lt, w6lo, w6hi);
+    if (valid) {
+      const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
+      const double2 pO = make_double2(rP[0], rP[1]);
+      for (int q = lt; q < K / 2; q += TT) {
+        const int qs = K - 1 - q;   // the southern mirror of node q
+        const double2 a1 = buf[lds_pad(q)], a2 = buf[lds_pad(NC - 1 - q)];
+        const double2 b1 = buf[lds_pad(qs)], b2 = buf[lds_pad(NC - 1 - qs)];
+        const double2 hea = cadd(a1, a2), heb = cadd(b1, b2);
+        double2 hoa = csub(a1, a2), hob = csub(b1, b2);
+        hoa.x = fma(A.pole_s[q], pO.x, hoa.x);
+        hoa.y = fma(A.pole_s[q], pO.y, hoa.y);
+        hob.x = fma(A.pole_s[qs], pO.x, hob.x);
+        hob.y = fma(A.pole_s[qs], pO.y, hob.y);
+        *reinterpret_cast<double2*>(HM + ((size_t)mE * K + q) * C + 2 * s) = cadd(hea, heb);
+        *reinterpret_cast<double2*>(HM + ((size_t)mE * K + K / 2 + q) * C + 2 * s) = csub(hea, heb);
+        *reinterpret_cast<double2*>(HM + ((size_t)mO * K + q) * C + 2 * s) = cadd(hoa, hob);
+        *reinterpret_cast<double2*>(HM + ((size_t)mO * K + K / 2 + q) * C + 2 * s) = csub(hoa, hob);
+      }
+    }
+    return;
   }
   __syncthreads();
 #pragma unroll
@@ -219,6 +261,82 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       wE[1] = he.y;
       wO[0] = ho.x;
       wO[1] = ho.y;
+    }
+  }
+}
+
+
+// Resampling from the symmetric grid to the MW nodes (inverse transforms on the symmetric grid):
+// FS[(m*k + s)*C + c] holds F_m(psi_s) for s < k (band-limited in theta); an even and an odd m
+// share one complex sequence on the 2k-point circle (F(2 pi - psi) = (-1)^m F(psi)), a 4096-point
+// FFT gives the Fourier coefficients |j| <= k-1, and the 4095-point inverse DFT evaluates them at
+// theta_t = pi (2t+1) / n; the parities separate by the reflection t -> n-1-t.
+// Output FT[(t*k + m)*C + c], t < k.
+__global__ __launch_bounds__(TT, 4) void k_resample_2048(K2048Args A, const double* __restrict__ FS,
+                                                         double* __restrict__ FT, int C, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  stage_tables(A, w6lo, w6hi, w5lo, w5hi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int ns = C / 2;
+  const int mu = valid ? p / ns : 0;
+  const int s = valid ? p % ns : 0;
+  const int mE = 2 * mu, mO = 2 * mu + 1;
+  constexpr int NL = K / TT;   // 4
+  double2 fe[NL], fo[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int q = lt + i * TT;
+    fe[i] = make_double2(0.0, 0.0);
+    fo[i] = make_double2(0.0, 0.0);
+    if (valid) {
+      fe[i] = *reinterpret_cast<const double2*>(FS + ((size_t)mE * K + q) * C + 2 * s);
+      fo[i] = *reinterpret_cast<const double2*>(FS + ((size_t)mO * K + q) * C + 2 * s);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int q = lt + i * TT;
+    buf[lds_pad(q)] = cadd(fe[i], fo[i]);
+    buf[lds_pad(NC - 1 - q)] = csub(fe[i], fo[i]);
+  }
+  __syncthreads();
+  fft4096<false, TT>(buf, lt, w6lo, w6hi);
+  constexpr int MAXV = NC / TT;
+  constexpr int NJ = 2 * K - 1;
+  double2 keep[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) keep[i] = cmul(A.rsph[idx], buf[lds_pad((idx - (K - 1)) & (NC - 1))]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) {
+      const int j = idx - (K - 1);
+      buf[lds_pad(j < 0 ? j + N : j)] = keep[i];
+    }
+  }
+  __syncthreads();
+  dft4095<true, TT>(buf, lt, w5lo, w5hi);
+  if (valid) {
+    for (int t = lt; t < K; t += TT) {
+      const double2 h1 = buf[lds_pad(t)];
+      double2 he, ho;
+      if (t < K - 1) {
+        const double2 h2 = buf[lds_pad(N - 1 - t)];
+        he = cadd(h1, h2);
+        ho = csub(h1, h2);
+      } else {
+        he = cadd(h1, h1);
+        ho = make_double2(0.0, 0.0);
+      }
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mE) * C + 2 * s) = he;
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mO) * C + 2 * s) = ho;
     }
   }
 }
@@ -292,6 +410,9 @@ static K2048Args k2048_args(const ShtTables& T) {
   a.khat1 = T.khat1;
   a.hphase = T.hphase;
   a.pole = T.pole;
+  a.psph = T.psph;
+  a.pole_s = T.pole_s;
+  a.rsph = T.rsph;
   return a;
 }
 
@@ -309,9 +430,22 @@ hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const voi
   return hipGetLastError();
 }
 
-hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s) {
+hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s,
+                             bool sym) {
   const int nprob = (K / 2) * (b.C / 2);
-  k_theta_2048<<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
+  if (sym) {
+    if (!T.sym) return hipErrorInvalidValue;
+    k_theta_2048<true><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
+  } else {
+    k_theta_2048<false><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
+  if (!T.sym || !k2048_ok(T)) return hipErrorInvalidValue;
+  const int nprob = (K / 2) * (b.C / 2);
+  k_resample_2048<<<nprob, TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
   return hipGetLastError();
 }
 

@@ -416,6 +416,275 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
 }
 
 // ------------------------------------------------------------------------------------------
+// The two contractions on the northern half of the symmetric grid psi_s = pi (2s+1) / (2k),
+// s < k/2 (FP64, C >= 16).  With lambda_lm(pi - psi) = (-1)^(l+m) lambda_lm(psi), a degree of
+// even l+m meets the sum H(s) + H(k-1-s) of the theta stage's output and one of odd l+m the
+// difference, so every (l, m) runs the recursion and the contraction over k/2 nodes instead of
+// k.  A chunk starts at l0 = m + 32 i (16 i), so l+m has the parity of the step j within it;
+// the z tile keeps even steps in its first half and odd steps in its second.
+// ------------------------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restrict__ HM, double* __restrict__ R,
+                                                          long long part_stride,
+                                                          const double* __restrict__ alpha,
+                                                          const double* __restrict__ beta,
+                                                          const double* __restrict__ cm,
+                                                          const double* __restrict__ ut,
+                                                          const double* __restrict__ sx,
+                                                          const double* __restrict__ st, int k, int Lt, int ng,
+                                                          unsigned long long* __restrict__ counter) {
+  constexpr int CT = C / 16;
+  constexpr int RS = 2 * ((C / 2) | 1);
+  constexpr int ZBYTES = FWD_NW * FWD_LC * FWD_ZS * (int)sizeof(double);
+  constexpr int RBYTES = FWD_NW * FWD_LC * RS * (int)sizeof(double);
+  __shared__ __align__(16) char smem[ZBYTES > RBYTES ? ZBYTES : RBYTES];
+  double (*Z)[FWD_LC][FWD_ZS] = reinterpret_cast<double (*)[FWD_LC][FWD_ZS]>(smem);
+  double* red = reinterpret_cast<double*>(smem);
+  unsigned long long retained = 0;
+  const int kh = k / 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int pair = blockIdx.x / ng;
+  const int grp = blockIdx.x % ng;
+  const int tile = grp * FWD_NW + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < kh;
+  const bool tile_live = tile * 64 < kh;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = 1.0;   // every node (and every idle lane) is northern
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  double* __restrict__ Rg = R + (size_t)grp * part_stride;
+
+  for (int im = 0; im < nm; ++im) {
+    const int m = im == 0 ? pair : k - 1 - pair;
+    const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
+    const double* __restrict__ Hm = HM + (size_t)m * k * C;
+    // operands: ap = H(s) + H(k-1-s) (even l+m), an = H(s) - H(k-1-s) (odd l+m)
+    double ap[16][CT], an[16][CT];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int tg = tile * 64 + 4 * kk + lq;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = ct * 16 + li;
+        ap[kk][ct] = tg < kh ? Hm[(size_t)tg * C + c] : 0.0;
+        an[kk][ct] = tg < kh ? Hm[(size_t)(kh + tg) * C + c] : 0.0;
+      }
+    }
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cf_next = chunk_coef<FWD_LC>(am, bm, 0, k - m, lane);
+
+    for (int l0 = m; l0 < k; l0 += FWD_LC) {
+      v4d acc[2][CT];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<double>::zero();
+      const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
+      const double cf = cf_next;
+      cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
+      recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e,
+                          [&](int j, double v) { Z[w][(j & 1) * (FWD_LC / 2) + (j >> 1)][lane] = v; });
+      if (!skip) {
+        wave_lds_sync();
+        const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
+        const int nt = (kh - tile * 64) < 64 ? (kh - tile * 64) : 64;
+        retained += (unsigned long long)nl * (unsigned long long)nt;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          const int tl = 4 * kk + lq;
+          const double b0 = Z[w][li][tl], b1 = Z[w][16 + li][tl];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            acc[0][ct] = Mma<double>::mma(ap[kk][ct], b0, acc[0][ct]);
+            acc[1][ct] = Mma<double>::mma(an[kk][ct], b1, acc[1][ct]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int lt2 = 0; lt2 < 2; ++lt2)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = ct * 16 + Mma<double>::row(lq, v);
+            red[((size_t)w * FWD_LC + lt2 * 16 + li) * RS + c] = acc[lt2][ct][v];
+          }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < FWD_LC * C; idx += FWD_NW * 64) {
+        const int lloc = idx / C, c = idx % C;
+        const int l = l0 + 2 * (lloc & 15) + (lloc >> 4);
+        if (l < k) {
+          double sum = 0.0;
+#pragma unroll
+          for (int ww = 0; ww < FWD_NW; ++ww) sum += red[(ww * FWD_LC + lloc) * RS + c];
+          Rg[(tri_off(k, m) + (l - m)) * C + c] = sum;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (counter != nullptr && lane == 0 && retained > 0) atomicAdd(counter, retained);
+}
+
+// Synthesis: E(s) = sum over even l+m, O(s) = sum over odd l+m of z_l(psi_s) S[l][c] on the
+// northern nodes; F(psi_s) = E + O and F(psi_{k-1-s}) = E - O, written to FS[(m*k + s)*C + c],
+// s < k (m-major, read by the resampling to the MW nodes).
+template <int C>
+__global__ __launch_bounds__(256) void k_legendre_inv_sym(const double* __restrict__ S, double* __restrict__ FS,
+                                                          const double* __restrict__ alpha,
+                                                          const double* __restrict__ beta,
+                                                          const double* __restrict__ cm,
+                                                          const double* __restrict__ ut,
+                                                          const double* __restrict__ sx,
+                                                          const double* __restrict__ st, int k, int Lt, int ntb,
+                                                          unsigned long long* __restrict__ counter) {
+  constexpr int CT = C / 16;
+  __shared__ double Z[4][INVM_LC][INVM_ZS];
+  const int kh = k / 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int pair = blk / ntb;
+  const int tile = (blk % ntb) * 4 + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < kh;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = 1.0;
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  unsigned long long retained = 0;
+
+  for (int im = 0; im < nm; ++im) {
+    const int m = im == 0 ? pair : k - 1 - pair;
+    const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
+    const double* __restrict__ Sm = S + tri_off(k, m) * C;
+    v4d accE[4][CT], accO[4][CT];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        accE[g][ct] = Mma<double>::zero();
+        accO[g][ct] = Mma<double>::zero();
+      }
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cf_next = chunk_coef<INVM_LC>(am, bm, 0, k - m, lane);
+    // k-step sl covers the steps jd = (sl >> 1) + 8 (sl & 1) + 2 lq: sl = 0, 1 even, sl = 2, 3 odd
+    double bn[INVM_LC / 4][CT];
+#pragma unroll
+    for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+      const int l = m + (sl >> 1) + 8 * (sl & 1) + 2 * lq;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+    }
+    for (int l0 = m; l0 < k; l0 += INVM_LC) {
+      const bool skip = __all(!valid || negligible(z1, z2, e));
+      double b[INVM_LC / 4][CT];
+#pragma unroll
+      for (int sl = 0; sl < INVM_LC / 4; ++sl)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) b[sl][ct] = bn[sl][ct];
+      if (l0 + INVM_LC < k) {
+#pragma unroll
+        for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+          const int l = l0 + INVM_LC + (sl >> 1) + 8 * (sl & 1) + 2 * lq;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+        }
+      }
+      const double cf = cf_next;
+      cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
+      recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e,
+                           [&](int j, double v) { Z[w][(j & 1) * (INVM_LC / 2) + (j >> 1)][lane] = v; });
+      if (!skip) {
+        wave_lds_sync();
+        const int nl = (k - l0) < INVM_LC ? (k - l0) : INVM_LC;
+        retained += (unsigned long long)nl * (unsigned long long)(valid ? 1 : 0);
+#pragma unroll
+        for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const double av = Z[w][4 * sl + lq][16 * g + li];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              if (sl < 2)
+                accE[g][ct] = Mma<double>::mma(av, b[sl][ct], accE[g][ct]);
+              else
+                accO[g][ct] = Mma<double>::mma(av, b[sl][ct], accO[g][ct]);
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int tt = tile * 64 + 16 * g + Mma<double>::row(lq, v);
+        if (tt < kh) {
+          double* north = FS + ((size_t)m * k + tt) * C;
+          double* south = FS + ((size_t)m * k + (k - 1 - tt)) * C;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            north[ct * 16 + li] = accE[g][ct][v] + accO[g][ct][v];
+            south[ct * 16 + li] = accE[g][ct][v] - accO[g][ct][v];
+          }
+        }
+      }
+  }
+  if (counter != nullptr) {
+    for (int off = 32; off > 0; off >>= 1) retained += __shfl_down(retained, off);
+    if (lane == 0 && retained > 0) atomicAdd(counter, retained);
+  }
+}
+
+int legendre_forward_groups_sym(int k) { return (k / 2 + FWD_TB - 1) / FWD_TB; }
+
+hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
+                                       double* R, long long part_stride, unsigned long long* counter,
+                                       hipStream_t s) {
+  const int k = T.k;
+  if (!T.sym || (k & 1)) return hipErrorInvalidValue;
+  const int ng = legendre_forward_groups_sym(k);
+  const int npairs = (k + 1) / 2;
+  if (b.C == 32)
+    k_legendre_fwd_sym<32><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s,
+                                                               T.sx_s, T.st_s, k, G.Lt, ng, counter);
+  else if (b.C == 16)
+    k_legendre_fwd_sym<16><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s,
+                                                               T.sx_s, T.st_s, k, G.Lt, ng, counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* S,
+                                       double* FS, unsigned long long* counter, hipStream_t s) {
+  const int k = T.k;
+  if (!T.sym || (k & 1)) return hipErrorInvalidValue;
+  const int ntb = (k / 2 + 255) / 256;
+  const int npairs = (k + 1) / 2;
+  if (b.C == 32)
+    k_legendre_inv_sym<32><<<npairs * ntb, 256, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
+                                                        G.Lt, ntb, counter);
+  else if (b.C == 16)
+    k_legendre_inv_sym<16><<<npairs * ntb, 256, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
+                                                        G.Lt, ntb, counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 // Batches below 16 columns run the FP64 VALU kernel in every precision mode.
 template <int C>
 static hipError_t inv_c(const ShtTables& T, const LegTables& G, const double* S, double* FT, int precision,

@@ -163,7 +163,7 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
   // the unit input at the pole, g = delta_{k-1} (Ghat_j = (-1)^j / n), with the full weight
   //   I_j' = sum_j Ghat_j w(j + j'),  H(theta_t) = (1/n) sum_j' I_j' e^{-i j' theta_t},
   //   c_t = H(t) - H(n-1-t) (t < k-1),  c_{k-1} = H(k-1)   (real up to rounding).
-  std::vector<double> pole(k);
+  std::vector<double> pole(k), pole_s;
   {
     std::vector<cLD> I(n);
     for (int jp = -(k - 1); jp <= k - 1; ++jp) {
@@ -191,6 +191,23 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
     };
     for (int t = 0; t < k - 1; ++t) pole[t] = (double)(H(t) - H(n - 1 - t)).real();
     pole[k - 1] = (double)H(k - 1).real();
+    if (k == 2048) {
+      // the same operator evaluated on the psi grid (N = 2k points psi_s = pi (2s+1) / N):
+      //   H(psi_s) = (1/N) sum_j' I_j' e^{-i j' psi_s},  c_s = H(s) - H(N-1-s)  (odd fold), s < k
+      const int N = 2 * k;
+      std::vector<cLD> exN(2 * N);
+      for (int q = 0; q < 2 * N; ++q) exN[q] = cLD(cosl(-PI_L * q / N), sinl(-PI_L * q / N));
+      auto Hs = [&](int t) {
+        cLD acc(0, 0);
+        for (int jp = -(k - 1); jp <= k - 1; ++jp) {
+          const long long q = (((long long)jp * (2 * t + 1)) % (2 * N) + 2 * N) % (2 * N);
+          acc += I[jp + k - 1] * exN[q];
+        }
+        return acc / (LD)N;
+      };
+      pole_s.resize(k);
+      for (int t = 0; t < k; ++t) pole_s[t] = (double)(Hs(t) - Hs(N - 1 - t)).real();
+    }
   }
 
   std::vector<cLD> hph(2 * k - 1);
@@ -205,6 +222,31 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
   if ((e = upload(&T->sx, sx)) != hipSuccess) return e;
   if ((e = upload(&T->hphase, to_d2(hph))) != hipSuccess) return e;
   if ((e = upload(&T->pole, pole)) != hipSuccess) return e;
+
+  if (k == 2048) {
+    const int N = 2 * k, kh = k / 2;
+    std::vector<double> us(kh), ss(kh), xs(kh, 1.0);
+    for (int t = 0; t < kh; ++t) {
+      const LD ps = PI_L * (LD)(2 * t + 1) / (LD)N;
+      const LD h = sinl(0.5L * ps);
+      us[t] = (double)(-2.0L * h * h);
+      ss[t] = (double)sinl(ps);
+    }
+    std::vector<cLD> pph(2 * k - 1), rph(2 * k - 1);
+    for (int j = -(k - 1); j <= k - 1; ++j) {
+      const LD a = -PI_L * (LD)j / (LD)N;
+      pph[j + k - 1] = cLD(cosl(a), sinl(a)) * ((LD)n / (LD)N);
+      const LD b = a + PI_L * (LD)j / (LD)n;
+      rph[j + k - 1] = cLD(cosl(b), sinl(b)) / (LD)(2 * N);
+    }
+    if ((e = upload(&T->ut_s, us)) != hipSuccess) return e;
+    if ((e = upload(&T->st_s, ss)) != hipSuccess) return e;
+    if ((e = upload(&T->sx_s, xs)) != hipSuccess) return e;
+    if ((e = upload(&T->psph, to_d2(pph))) != hipSuccess) return e;
+    if ((e = upload(&T->rsph, to_d2(rph))) != hipSuccess) return e;
+    if ((e = upload(&T->pole_s, pole_s)) != hipSuccess) return e;
+    T->sym = 1;
+  }
   return hipSuccess;
 }
 
@@ -223,6 +265,12 @@ void free_sht_tables(ShtTables* T) {
   hipFree(T->sx);
   hipFree(T->hphase);
   hipFree(T->pole);
+  hipFree(T->ut_s);
+  hipFree(T->st_s);
+  hipFree(T->sx_s);
+  hipFree(T->psph);
+  hipFree(T->pole_s);
+  hipFree(T->rsph);
   *T = ShtTables();
 }
 

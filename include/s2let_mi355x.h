@@ -230,13 +230,18 @@ int s2let_batch_graph_launch(s2let_batch* plan, void* stream);
  * (l, m, theta) triple: 3 recursion flops plus 2 flops per data column), the flops of the work
  * actually done (retained pairs), and the algorithmic HBM bytes (inputs read once, outputs
  * written once).  Stages: 0 phi forward, 1 theta quadrature, 2 Legendre analysis,
- * 3 Legendre synthesis, 4 phi inverse, 5 harmonic tiling.  Host-side, not thread-safe with
+ * 3 Legendre synthesis, 4 phi inverse, 5 harmonic tiling, 6 resampling from the symmetric grid
+ * to the MW nodes (the inverse transforms that run their Legendre step on that grid).
+ * s2let_profile_query_k() counts only the launches at band-limit k (every launch for k <= 0;
+ * the tiling is counted at its destination band-limit).  Host-side, not thread-safe with
  * concurrent transform calls on other threads.  S2LET_EINVAL for a bad stage or null pointer. */
 enum { S2LET_STAGE_PHI_FWD = 0, S2LET_STAGE_THETA = 1, S2LET_STAGE_LEG_FWD = 2,
-       S2LET_STAGE_LEG_INV = 3, S2LET_STAGE_PHI_INV = 4, S2LET_STAGE_TILE = 5 };
+       S2LET_STAGE_LEG_INV = 3, S2LET_STAGE_PHI_INV = 4, S2LET_STAGE_TILE = 5, S2LET_STAGE_RESAMPLE = 6 };
 int s2let_profile_enable(int on);
 int s2let_profile_query(int stage, double* ms, int64_t* launches, double* flops_full,
                         double* flops_retained, double* bytes);
+int s2let_profile_query_k(int stage, int k, double* ms, int64_t* launches, double* flops_full,
+                          double* flops_retained, double* bytes);
 
 /* Waits for the stream and reports a pending asynchronous device error as S2LET_EHIP. */
 int s2let_sync(void* stream);

@@ -90,6 +90,7 @@ def _load():
         "s2let_sync": (i, [vp]),
         "s2let_profile_enable": (i, [i]),
         "s2let_profile_query": (i, [i, dp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp]),
+        "s2let_profile_query_k": (i, [i, i, dp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp]),
         "s2let_finalize": (None, []),
         "s2let_strerror": (ctypes.c_char_p, [i]),
         "s2let_last_hip_error": (i, []),
@@ -524,7 +525,7 @@ class BatchPlan:
 
 
 STAGES = {"phi_forward": 0, "theta": 1, "legendre_analysis": 2, "legendre_synthesis": 3,
-          "phi_inverse": 4, "tiling": 5}
+          "phi_inverse": 4, "tiling": 5, "resample": 6}
 
 
 def profile_enable(on: bool = True):
@@ -532,12 +533,13 @@ def profile_enable(on: bool = True):
     _check(_lib.s2let_profile_enable(int(on)), "s2let_profile_enable")
 
 
-def profile_query(stage: str) -> dict:
-    """Summed kernel time and algorithmic work of one stage since profile_enable(True)."""
+def profile_query(stage: str, k: int = 0) -> dict:
+    """Summed kernel time and algorithmic work of one stage since profile_enable(True), over the
+    launches at band-limit k (all launches for k <= 0)."""
     ms, fl, fr, by = (ctypes.c_double() for _ in range(4))
     n = ctypes.c_int64()
-    _check(_lib.s2let_profile_query(STAGES[stage], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
-                                    ctypes.byref(fr), ctypes.byref(by)), "s2let_profile_query")
+    _check(_lib.s2let_profile_query_k(STAGES[stage], int(k), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                      ctypes.byref(fr), ctypes.byref(by)), "s2let_profile_query_k")
     return {"ms": ms.value, "launches": n.value, "flops_full": fl.value, "flops_retained": fr.value,
             "bytes": by.value}
 

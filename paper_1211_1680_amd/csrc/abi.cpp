@@ -45,6 +45,7 @@ std::map<int, DevCache> g_cache;
 // ---- optional per-stage timing (HIP events on the launch stream) ----
 struct ProfRec {
   int stage;
+  int k;                // band-limit of the launch
   hipEvent_t a, b;
   double flops_full;    // algorithmic flops of the launch (Legendre stages)
   double bytes;         // algorithmic HBM bytes of the launch
@@ -63,10 +64,11 @@ struct Prof {
 constexpr int kProfSlots = 8192;
 Prof g_prof;
 
-ProfRec* prof_begin(int stage, hipStream_t s) {
+ProfRec* prof_begin(int stage, hipStream_t s, int k) {
   if (!g_prof.on) return nullptr;
   ProfRec r{};
   r.stage = stage;
+  r.k = k;
   r.slot = -1;
   if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return nullptr;
   hipEventRecord(r.a, s);
@@ -262,12 +264,12 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   const double k = T.k, n = T.n;
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
   const double colb = 8.0 * b.used * k * k;
-  ProfRec* r = prof_begin(ST_PHI_FWD, s);
+  ProfRec* r = prof_begin(ST_PHI_FWD, s, T.k);
   if (r) r->bytes = mapb + colb;
   if ((e = launch_phi_forward(T, b, f, map_stride, w.GT, s)) != hipSuccess) return to_status(e);
   prof_end(r, s);
   const bool sym = sym_path(T.k, b, precision, adjoint);
-  r = prof_begin(ST_THETA, s);
+  r = prof_begin(ST_THETA, s, T.k);
   if (r) r->bytes = 2.0 * colb;
   if (adjoint)
     e = launch_transpose_rows(b, T.k, w.GT, w.HM, n / (2.0 * M_PI), s);
@@ -277,7 +279,7 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     e = launch_theta(T, b, w.GT, w.HM, s);
   if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
-  r = prof_begin(ST_LEG_FWD, s);
+  r = prof_begin(ST_LEG_FWD, s, T.k);
   if (r) {
     r->triples = sym ? triples_of(T.k) / 2.0 : triples_of(T.k);
     r->rec_flops = 3.0;
@@ -305,7 +307,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
   const double colb = 8.0 * b.used * k * k;
   const bool sym = sym_path(T.k, b, precision, adjoint);
-  ProfRec* r = prof_begin(ST_LEG_INV, s);
+  ProfRec* r = prof_begin(ST_LEG_INV, s, T.k);
   if (r) {
     r->triples = sym ? triples_of(T.k) / 2.0 : triples_of(T.k);
     r->rec_flops = 3.0;
@@ -320,20 +322,20 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
   if (sym) {
-    // symmetric grid -> MW nodes (counted with the theta-type stages)
-    r = prof_begin(ST_THETA, s);
+    // symmetric grid -> MW nodes
+    r = prof_begin(ST_RESAMPLE, s, T.k);
     if (r) r->bytes = 2.0 * colb;
     if ((e = launch_resample_2048(T, b, w.HM, w.GT, s)) != hipSuccess) return to_status(e);
     prof_end(r, s);
   }
   if (adjoint) {
-    r = prof_begin(ST_THETA, s);
+    r = prof_begin(ST_THETA, s, T.k);
     if (r) r->bytes = 4.0 * colb;
     if ((e = launch_theta(T, b, w.GT, w.HM, s)) != hipSuccess) return to_status(e);
     if ((e = launch_transpose_rows(b, T.k, w.HM, w.GT, 2.0 * M_PI / n, s)) != hipSuccess) return to_status(e);
     prof_end(r, s);
   }
-  r = prof_begin(ST_PHI_INV, s);
+  r = prof_begin(ST_PHI_INV, s, T.k);
   if (r) r->bytes = mapb + colb;
   if ((e = launch_phi_inverse(T, b, w.GT, f, map_stride, s)) != hipSuccess) return to_status(e);
   prof_end(r, s);
@@ -342,7 +344,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
 
 hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int ks, int nparts, double* dst, int kd,
                      const double* kern, int accumulate, hipStream_t s) {
-  ProfRec* r = prof_begin(ST_TILE, s);
+  ProfRec* r = prof_begin(ST_TILE, s, kd);
   if (r) {
     // coefficients read once, destination written (and read when accumulating, rows < ks only)
     const double kk = std::min(ks, kd);
@@ -776,8 +778,8 @@ S2LET_API int s2let_profile_enable(int on) {
   return S2LET_OK;
 }
 
-S2LET_API int s2let_profile_query(int stage, double* ms, int64_t* launches, double* flops_full,
-                                  double* flops_retained, double* bytes) {
+S2LET_API int s2let_profile_query_k(int stage, int k, double* ms, int64_t* launches, double* flops_full,
+                                    double* flops_retained, double* bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (stage < 0 || stage >= ST_N || !ms || !launches || !flops_full || !flops_retained || !bytes)
     return S2LET_EINVAL;
@@ -794,7 +796,7 @@ S2LET_API int s2let_profile_query(int stage, double* ms, int64_t* launches, doub
   *flops_retained = 0.0;
   *bytes = 0.0;
   for (auto& r : g_prof.recs) {
-    if (r.stage != stage) continue;
+    if (r.stage != stage || (k > 0 && r.k != k)) continue;
     if (hipEventSynchronize(r.b) != hipSuccess) return S2LET_EHIP;
     float t = 0.f;
     if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return S2LET_EHIP;
@@ -805,6 +807,11 @@ S2LET_API int s2let_profile_query(int stage, double* ms, int64_t* launches, doub
     if (r.slot >= 0) *flops_retained += r.triples * r.rec_flops + (double)cnt[r.slot] * r.col_flops;
   }
   return S2LET_OK;
+}
+
+S2LET_API int s2let_profile_query(int stage, double* ms, int64_t* launches, double* flops_full,
+                                  double* flops_retained, double* bytes) {
+  return s2let_profile_query_k(stage, 0, ms, launches, flops_full, flops_retained, bytes);
 }
 
 S2LET_API int s2let_sync(void* stream) {

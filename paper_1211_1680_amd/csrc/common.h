@@ -82,7 +82,9 @@ struct LegTables {
 };
 
 // Kernel stages, for the optional per-stage timing.
-enum Stage { ST_PHI_FWD = 0, ST_THETA = 1, ST_LEG_FWD = 2, ST_LEG_INV = 3, ST_PHI_INV = 4, ST_TILE = 5, ST_N = 6 };
+enum Stage {
+  ST_PHI_FWD = 0, ST_THETA = 1, ST_LEG_FWD = 2, ST_LEG_INV = 3, ST_PHI_INV = 4, ST_TILE = 5, ST_RESAMPLE = 6, ST_N = 7
+};
 
 // Column layout of a batch: C columns of doubles per (row) entry.  Real maps: 2 columns per
 // map (re, im of m >= 0).  Complex maps: 4 per map (re, im of +m, then re, im of -m).

@@ -104,8 +104,9 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const d
 // SYM: the output transform evaluates on the symmetric grid psi_s = pi (2s+1) / (2k) instead of
 // the MW nodes (a 4096-point FFT in place of the 4095-point DFT; the weight's p = +-1 terms still
 // act only through the odd-m pole sample, now through the psi-grid pole column), folds s and
-// 2k-1-s, and writes the north/south sums and differences for the Legendre analysis on s < k/2:
-// HM[(m*k + s)*C + c] = H(s) + H(k-1-s), HM[(m*k + k/2 + s)*C + c] = H(s) - H(k-1-s).
+// 2k-1-s, and writes the north/south sums and differences for the Legendre analysis on s < k/2,
+// column-pair major: row (m*(C/2) + cp)*k of double2, entry s = H(s) + H(k-1-s) and entry
+// k/2 + s = H(s) - H(k-1-s).
 template <bool SYM>
 __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double* __restrict__ GT,
                                                       double* __restrict__ HM, int C, int nprob) {
@@ -220,10 +221,12 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
         hoa.y = fma(A.pole_s[q], pO.y, hoa.y);
         hob.x = fma(A.pole_s[qs], pO.x, hob.x);
         hob.y = fma(A.pole_s[qs], pO.y, hob.y);
-        *reinterpret_cast<double2*>(HM + ((size_t)mE * K + q) * C + 2 * s) = cadd(hea, heb);
-        *reinterpret_cast<double2*>(HM + ((size_t)mE * K + K / 2 + q) * C + 2 * s) = csub(hea, heb);
-        *reinterpret_cast<double2*>(HM + ((size_t)mO * K + q) * C + 2 * s) = cadd(hoa, hob);
-        *reinterpret_cast<double2*>(HM + ((size_t)mO * K + K / 2 + q) * C + 2 * s) = csub(hoa, hob);
+        double2* colE = reinterpret_cast<double2*>(HM) + ((size_t)mE * ns + s) * K;
+        double2* colO = reinterpret_cast<double2*>(HM) + ((size_t)mO * ns + s) * K;
+        colE[q] = cadd(hea, heb);
+        colE[K / 2 + q] = csub(hea, heb);
+        colO[q] = cadd(hoa, hob);
+        colO[K / 2 + q] = csub(hoa, hob);
       }
     }
     return;
@@ -267,7 +270,8 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
 
 
 // Resampling from the symmetric grid to the MW nodes (inverse transforms on the symmetric grid):
-// FS[(m*k + s)*C + c] holds F_m(psi_s) for s < k (band-limited in theta); an even and an odd m
+// FS holds F_m(psi_s), s < k, column-pair major (row (m*(C/2) + cp)*k of double2; band-limited
+// in theta); an even and an odd m
 // share one complex sequence on the 2k-point circle (F(2 pi - psi) = (-1)^m F(psi)), a 4096-point
 // FFT gives the Fourier coefficients |j| <= k-1, and the 4095-point inverse DFT evaluates them at
 // theta_t = pi (2t+1) / n; the parities separate by the reflection t -> n-1-t.
@@ -292,8 +296,8 @@ __global__ __launch_bounds__(TT, 4) void k_resample_2048(K2048Args A, const doub
     fe[i] = make_double2(0.0, 0.0);
     fo[i] = make_double2(0.0, 0.0);
     if (valid) {
-      fe[i] = *reinterpret_cast<const double2*>(FS + ((size_t)mE * K + q) * C + 2 * s);
-      fo[i] = *reinterpret_cast<const double2*>(FS + ((size_t)mO * K + q) * C + 2 * s);
+      fe[i] = reinterpret_cast<const double2*>(FS)[((size_t)mE * ns + s) * K + q];
+      fo[i] = reinterpret_cast<const double2*>(FS)[((size_t)mO * ns + s) * K + q];
     }
   }
 #pragma unroll

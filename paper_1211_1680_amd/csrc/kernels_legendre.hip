@@ -461,7 +461,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
     const double* __restrict__ am = alpha + tri_off(Lt, m);
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Hm = HM + (size_t)m * k * C;
-    // operands: ap = H(s) + H(k-1-s) (even l+m), an = H(s) - H(k-1-s) (odd l+m)
+    // operands: ap = H(s) + H(k-1-s) (even l+m), an = H(s) - H(k-1-s) (odd l+m); the layout is
+    // column-pair major, Hm[(cp*k + node)*2 + re/im]
     double ap[16][CT], an[16][CT];
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
@@ -469,8 +470,9 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int c = ct * 16 + li;
-        ap[kk][ct] = tg < kh ? Hm[(size_t)tg * C + c] : 0.0;
-        an[kk][ct] = tg < kh ? Hm[(size_t)(kh + tg) * C + c] : 0.0;
+        const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1);
+        ap[kk][ct] = tg < kh ? col[(size_t)tg * 2] : 0.0;
+        an[kk][ct] = tg < kh ? col[(size_t)(kh + tg) * 2] : 0.0;
       }
     }
     int e;
@@ -533,10 +535,10 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
 }
 
 // Synthesis: E(s) = sum over even l+m, O(s) = sum over odd l+m of z_l(psi_s) S[l][c] on the
-// northern nodes; F(psi_s) = E + O and F(psi_{k-1-s}) = E - O, written to FS[(m*k + s)*C + c],
-// s < k (m-major, read by the resampling to the MW nodes).
+// northern nodes; F(psi_s) = E + O and F(psi_{k-1-s}) = E - O, written column-pair major,
+// FS[((m*(C/2) + c/2)*k + s)*2 + c%2], s < k (read by the resampling to the MW nodes).
 template <int C>
-__global__ __launch_bounds__(256) void k_legendre_inv_sym(const double* __restrict__ S, double* __restrict__ FS,
+__global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __restrict__ S, double* __restrict__ FS,
                                                           const double* __restrict__ alpha,
                                                           const double* __restrict__ beta,
                                                           const double* __restrict__ cm,
@@ -587,19 +589,6 @@ __global__ __launch_bounds__(256) void k_legendre_inv_sym(const double* __restri
     }
     for (int l0 = m; l0 < k; l0 += INVM_LC) {
       const bool skip = __all(!valid || negligible(z1, z2, e));
-      double b[INVM_LC / 4][CT];
-#pragma unroll
-      for (int sl = 0; sl < INVM_LC / 4; ++sl)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) b[sl][ct] = bn[sl][ct];
-      if (l0 + INVM_LC < k) {
-#pragma unroll
-        for (int sl = 0; sl < INVM_LC / 4; ++sl) {
-          const int l = l0 + INVM_LC + (sl >> 1) + 8 * (sl & 1) + 2 * lq;
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
-        }
-      }
       const double cf = cf_next;
       cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
       recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e,
@@ -616,13 +605,22 @@ __global__ __launch_bounds__(256) void k_legendre_inv_sym(const double* __restri
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
               if (sl < 2)
-                accE[g][ct] = Mma<double>::mma(av, b[sl][ct], accE[g][ct]);
+                accE[g][ct] = Mma<double>::mma(av, bn[sl][ct], accE[g][ct]);
               else
-                accO[g][ct] = Mma<double>::mma(av, b[sl][ct], accO[g][ct]);
+                accO[g][ct] = Mma<double>::mma(av, bn[sl][ct], accO[g][ct]);
             }
           }
         }
         wave_lds_sync();
+      }
+      // the next chunk's coefficient rows are in flight during its recursion
+      if (l0 + INVM_LC < k) {
+#pragma unroll
+        for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+          const int l = l0 + INVM_LC + (sl >> 1) + 8 * (sl & 1) + 2 * lq;
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+        }
       }
     }
 #pragma unroll
@@ -631,12 +629,12 @@ __global__ __launch_bounds__(256) void k_legendre_inv_sym(const double* __restri
       for (int v = 0; v < 4; ++v) {
         const int tt = tile * 64 + 16 * g + Mma<double>::row(lq, v);
         if (tt < kh) {
-          double* north = FS + ((size_t)m * k + tt) * C;
-          double* south = FS + ((size_t)m * k + (k - 1 - tt)) * C;
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
-            north[ct * 16 + li] = accE[g][ct][v] + accO[g][ct][v];
-            south[ct * 16 + li] = accE[g][ct][v] - accO[g][ct][v];
+            const int c = ct * 16 + li;
+            double* col = FS + ((size_t)m * C + (c & ~1)) * k + (c & 1);
+            col[(size_t)tt * 2] = accE[g][ct][v] + accO[g][ct][v];
+            col[(size_t)(k - 1 - tt) * 2] = accE[g][ct][v] - accO[g][ct][v];
           }
         }
       }

@@ -188,7 +188,7 @@ Workspace carve(void* ws, int L, int C, bool wavelet) {
 // The FP64 forward and inverse transforms at the band-limit with compiled transforms run their
 // Legendre steps on the symmetric grid (see launch_theta_2048 / launch_resample_2048).
 bool sym_path(int k, const Batch& b, int precision, bool adjoint) {
-  return k == 2048 && precision == S2LET_FP64 && !adjoint && b.C >= 16;
+  return k == 2048 && !adjoint && b.C >= 16;
 }
 int nparts_of(int k, const Batch& b, int precision, bool adjoint) {
   return sym_path(k, b, precision, adjoint) ? legendre_forward_groups_sym(k) : legendre_forward_groups(k);
@@ -288,7 +288,7 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
   if (sym)
-    e = launch_legendre_forward_sym(T, G, b, w.HM, w.R, pstride_of(T.k, b), prof_counter(r), s);
+    e = launch_legendre_forward_sym(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r), s);
   else
     e = launch_legendre_forward(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r), s);
   if (e != hipSuccess) return to_status(e);
@@ -316,7 +316,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
   if (sym)
-    e = launch_legendre_inverse_sym(T, G, b, S, w.HM, prof_counter(r), s);
+    e = launch_legendre_inverse_sym(T, G, b, S, w.HM, precision, prof_counter(r), s);
   else
     e = launch_legendre_inverse(T, G, b, S, w.GT, precision, prof_counter(r), s);
   if (e != hipSuccess) return to_status(e);

@@ -116,10 +116,16 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
 hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
 int legendre_forward_groups_sym(int k);
 hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
-                                       double* R, long long part_stride, unsigned long long* counter,
-                                       hipStream_t s);
+                                       double* R, long long part_stride, int precision,
+                                       unsigned long long* counter, hipStream_t s);
 hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* S,
-                                       double* FS, unsigned long long* counter, hipStream_t s);
+                                       double* FS, int precision, unsigned long long* counter, hipStream_t s);
+hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
+                                            const double* HM, double* R, long long part_stride,
+                                            unsigned long long* counter, hipStream_t s);
+hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
+                                            const double* S, double* FS, unsigned long long* counter,
+                                            hipStream_t s);
 hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
                                    int64_t map_stride, hipStream_t s);
 // Legendre contraction, forward: HM[m][t][c] -> R[tri_off(k,m)+l-m][c] = sum_t z_lm(theta_t) H',

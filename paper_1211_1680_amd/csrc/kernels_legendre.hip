@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
 // k.  A chunk starts at l0 = m + 32 i (16 i), so l+m has the parity of the step j within it;
 // the z tile keeps even steps in its first half and odd steps in its second.
 // ------------------------------------------------------------------------------------------
-template <int C>
+template <int C, typename T>
 __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restrict__ HM, double* __restrict__ R,
                                                           long long part_stride,
                                                           const double* __restrict__ alpha,
@@ -435,10 +435,10 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
                                                           unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
   constexpr int RS = 2 * ((C / 2) | 1);
-  constexpr int ZBYTES = FWD_NW * FWD_LC * FWD_ZS * (int)sizeof(double);
+  constexpr int ZBYTES = FWD_NW * FWD_LC * FWD_ZS * (int)sizeof(T);
   constexpr int RBYTES = FWD_NW * FWD_LC * RS * (int)sizeof(double);
   __shared__ __align__(16) char smem[ZBYTES > RBYTES ? ZBYTES : RBYTES];
-  double (*Z)[FWD_LC][FWD_ZS] = reinterpret_cast<double (*)[FWD_LC][FWD_ZS]>(smem);
+  T (*Z)[FWD_LC][FWD_ZS] = reinterpret_cast<T (*)[FWD_LC][FWD_ZS]>(smem);
   double* red = reinterpret_cast<double*>(smem);
   unsigned long long retained = 0;
   const int kh = k / 2;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
     const double* __restrict__ Hm = HM + (size_t)m * k * C;
     // operands: ap = H(s) + H(k-1-s) (even l+m), an = H(s) - H(k-1-s) (odd l+m); the layout is
     // column-pair major, Hm[(cp*k + node)*2 + re/im]
-    double ap[16][CT], an[16][CT];
+    T ap[16][CT], an[16][CT];
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int tg = tile * 64 + 4 * kk + lq;
@@ -471,8 +471,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
       for (int ct = 0; ct < CT; ++ct) {
         const int c = ct * 16 + li;
         const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1);
-        ap[kk][ct] = tg < kh ? col[(size_t)tg * 2] : 0.0;
-        an[kk][ct] = tg < kh ? col[(size_t)(kh + tg) * 2] : 0.0;
+        ap[kk][ct] = (T)(tg < kh ? col[(size_t)tg * 2] : 0.0);
+        an[kk][ct] = (T)(tg < kh ? col[(size_t)(kh + tg) * 2] : 0.0);
       }
     }
     int e;
@@ -481,16 +481,16 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
     double cf_next = chunk_coef<FWD_LC>(am, bm, 0, k - m, lane);
 
     for (int l0 = m; l0 < k; l0 += FWD_LC) {
-      v4d acc[2][CT];
+      typename Mma<T>::acc_t acc[2][CT];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<double>::zero();
+        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<T>::zero();
       const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
       const double cf = cf_next;
       cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
       recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e,
-                          [&](int j, double v) { Z[w][(j & 1) * (FWD_LC / 2) + (j >> 1)][lane] = v; });
+                          [&](int j, double v) { Z[w][(j & 1) * (FWD_LC / 2) + (j >> 1)][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
@@ -499,11 +499,11 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
           const int tl = 4 * kk + lq;
-          const double b0 = Z[w][li][tl], b1 = Z[w][16 + li][tl];
+          const T b0 = Z[w][li][tl], b1 = Z[w][16 + li][tl];
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
-            acc[0][ct] = Mma<double>::mma(ap[kk][ct], b0, acc[0][ct]);
-            acc[1][ct] = Mma<double>::mma(an[kk][ct], b1, acc[1][ct]);
+            acc[0][ct] = Mma<T>::mma(ap[kk][ct], b0, acc[0][ct]);
+            acc[1][ct] = Mma<T>::mma(an[kk][ct], b1, acc[1][ct]);
           }
         }
       }
@@ -514,8 +514,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int c = ct * 16 + Mma<double>::row(lq, v);
-            red[((size_t)w * FWD_LC + lt2 * 16 + li) * RS + c] = acc[lt2][ct][v];
+            const int c = ct * 16 + Mma<T>::row(lq, v);
+            red[((size_t)w * FWD_LC + lt2 * 16 + li) * RS + c] = (double)acc[lt2][ct][v];
           }
       __syncthreads();
       for (int idx = threadIdx.x; idx < FWD_LC * C; idx += FWD_NW * 64) {
@@ -537,8 +537,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
 // Synthesis: E(s) = sum over even l+m, O(s) = sum over odd l+m of z_l(psi_s) S[l][c] on the
 // northern nodes; F(psi_s) = E + O and F(psi_{k-1-s}) = E - O, written column-pair major,
 // FS[((m*(C/2) + c/2)*k + s)*2 + c%2], s < k (read by the resampling to the MW nodes).
-template <int C>
-__global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __restrict__ S, double* __restrict__ FS,
+template <int C, typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sym(const double* __restrict__ S, double* __restrict__ FS,
                                                           const double* __restrict__ alpha,
                                                           const double* __restrict__ beta,
                                                           const double* __restrict__ cm,
@@ -547,7 +547,8 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __res
                                                           const double* __restrict__ st, int k, int Lt, int ntb,
                                                           unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
-  __shared__ double Z[4][INVM_LC][INVM_ZS];
+  constexpr bool F64 = sizeof(T) == sizeof(double);
+  __shared__ T Z[4][INVM_LC][INVM_ZS];
   const int kh = k / 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
@@ -567,14 +568,25 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __res
     const double* __restrict__ am = alpha + tri_off(Lt, m);
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Sm = S + tri_off(k, m) * C;
-    v4d accE[4][CT], accO[4][CT];
+    typename Mma<T>::acc_t accE[4][CT], accO[4][CT];
+    // FP32 path: north (E + O) and south (E - O) sums in FP64, fed every INVM_FLUSH chunks
+    double accN[F64 ? 1 : 4][F64 ? 1 : CT][4], accS[F64 ? 1 : 4][F64 ? 1 : CT][4];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
-        accE[g][ct] = Mma<double>::zero();
-        accO[g][ct] = Mma<double>::zero();
+        accE[g][ct] = Mma<T>::zero();
+        accO[g][ct] = Mma<T>::zero();
       }
+    if constexpr (!F64) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) accN[g][ct][v] = accS[g][ct][v] = 0.0;
+    }
+    int since_flush = 0;
     int e;
     double z1, z2;
     recur_start(cm[m], s, sg, m, z1, z2, e);
@@ -592,7 +604,7 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __res
       const double cf = cf_next;
       cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
       recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e,
-                           [&](int j, double v) { Z[w][(j & 1) * (INVM_LC / 2) + (j >> 1)][lane] = v; });
+                           [&](int j, double v) { Z[w][(j & 1) * (INVM_LC / 2) + (j >> 1)][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < INVM_LC ? (k - l0) : INVM_LC;
@@ -601,17 +613,35 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __res
         for (int sl = 0; sl < INVM_LC / 4; ++sl) {
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
-            const double av = Z[w][4 * sl + lq][16 * g + li];
+            const T av = Z[w][4 * sl + lq][16 * g + li];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
               if (sl < 2)
-                accE[g][ct] = Mma<double>::mma(av, bn[sl][ct], accE[g][ct]);
+                accE[g][ct] = Mma<T>::mma(av, (T)bn[sl][ct], accE[g][ct]);
               else
-                accO[g][ct] = Mma<double>::mma(av, bn[sl][ct], accO[g][ct]);
+                accO[g][ct] = Mma<T>::mma(av, (T)bn[sl][ct], accO[g][ct]);
             }
           }
         }
         wave_lds_sync();
+        if constexpr (!F64) {
+          if (++since_flush == INVM_FLUSH) {
+            since_flush = 0;
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  const double E = (double)accE[g][ct][v], O = (double)accO[g][ct][v];
+                  accN[g][ct][v] += E + O;
+                  accS[g][ct][v] += E - O;
+                }
+                accE[g][ct] = Mma<T>::zero();
+                accO[g][ct] = Mma<T>::zero();
+              }
+          }
+        }
       }
       // the next chunk's coefficient rows are in flight during its recursion
       if (l0 + INVM_LC < k) {
@@ -627,14 +657,20 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __res
     for (int g = 0; g < 4; ++g)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int tt = tile * 64 + 16 * g + Mma<double>::row(lq, v);
+        const int tt = tile * 64 + 16 * g + Mma<T>::row(lq, v);
         if (tt < kh) {
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             const int c = ct * 16 + li;
             double* col = FS + ((size_t)m * C + (c & ~1)) * k + (c & 1);
-            col[(size_t)tt * 2] = accE[g][ct][v] + accO[g][ct][v];
-            col[(size_t)(k - 1 - tt) * 2] = accE[g][ct][v] - accO[g][ct][v];
+            const double E = (double)accE[g][ct][v], O = (double)accO[g][ct][v];
+            if constexpr (F64) {
+              col[(size_t)tt * 2] = E + O;
+              col[(size_t)(k - 1 - tt) * 2] = E - O;
+            } else {
+              col[(size_t)tt * 2] = accN[g][ct][v] + (E + O);
+              col[(size_t)(k - 1 - tt) * 2] = accS[g][ct][v] + (E - O);
+            }
           }
         }
       }
@@ -648,35 +684,51 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_sym(const double* __res
 int legendre_forward_groups_sym(int k) { return (k / 2 + FWD_TB - 1) / FWD_TB; }
 
 hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
-                                       double* R, long long part_stride, unsigned long long* counter,
-                                       hipStream_t s) {
+                                       double* R, long long part_stride, int precision,
+                                       unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   if (!T.sym || (k & 1)) return hipErrorInvalidValue;
+  if (precision == S2LET_MIXED_BF16X3) return launch_legendre_forward_bf16_sym(T, G, b, HM, R, part_stride, counter, s);
   const int ng = legendre_forward_groups_sym(k);
-  const int npairs = (k + 1) / 2;
-  if (b.C == 32)
-    k_legendre_fwd_sym<32><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s,
-                                                               T.sx_s, T.st_s, k, G.Lt, ng, counter);
+  const dim3 grid(((k + 1) / 2) * ng), block(FWD_NW * 64);
+  const bool f32 = precision == S2LET_MIXED_FP32;
+  if (b.C == 32 && f32)
+    k_legendre_fwd_sym<32, float><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
+                                                         T.st_s, k, G.Lt, ng, counter);
+  else if (b.C == 32)
+    k_legendre_fwd_sym<32, double><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
+                                                          T.st_s, k, G.Lt, ng, counter);
+  else if (b.C == 16 && f32)
+    k_legendre_fwd_sym<16, float><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
+                                                         T.st_s, k, G.Lt, ng, counter);
   else if (b.C == 16)
-    k_legendre_fwd_sym<16><<<npairs * ng, FWD_NW * 64, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s,
-                                                               T.sx_s, T.st_s, k, G.Lt, ng, counter);
+    k_legendre_fwd_sym<16, double><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
+                                                          T.st_s, k, G.Lt, ng, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* S,
-                                       double* FS, unsigned long long* counter, hipStream_t s) {
+                                       double* FS, int precision, unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   if (!T.sym || (k & 1)) return hipErrorInvalidValue;
+  if (precision == S2LET_MIXED_BF16X3) return launch_legendre_inverse_bf16_sym(T, G, b, S, FS, counter, s);
   const int ntb = (k / 2 + 255) / 256;
-  const int npairs = (k + 1) / 2;
-  if (b.C == 32)
-    k_legendre_inv_sym<32><<<npairs * ntb, 256, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
-                                                        G.Lt, ntb, counter);
+  const dim3 grid(((k + 1) / 2) * ntb), block(256);
+  const bool f32 = precision == S2LET_MIXED_FP32;
+  if (b.C == 32 && f32)
+    k_legendre_inv_sym<32, float><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
+                                                         G.Lt, ntb, counter);
+  else if (b.C == 32)
+    k_legendre_inv_sym<32, double><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
+                                                          G.Lt, ntb, counter);
+  else if (b.C == 16 && f32)
+    k_legendre_inv_sym<16, float><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
+                                                         G.Lt, ntb, counter);
   else if (b.C == 16)
-    k_legendre_inv_sym<16><<<npairs * ntb, 256, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
-                                                        G.Lt, ntb, counter);
+    k_legendre_inv_sym<16, double><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
+                                                          G.Lt, ntb, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

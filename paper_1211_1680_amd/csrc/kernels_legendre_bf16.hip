@@ -305,6 +305,352 @@ __global__ __launch_bounds__(256) void k_legendre_inv_bf16(const double* __restr
 }
 
 // ------------------------------------------------------------------------------------------
+// The same two contractions on the northern half of the symmetric grid (see the FP64 kernels
+// k_legendre_fwd_sym / k_legendre_inv_sym): even l+m meets the north/south sums of the theta
+// stage, odd l+m the differences.
+// Analysis: as k_legendre_fwd_bf16 with two operand sets; z tile rows 0..15 hold the even steps
+// of the 32-degree chunk, rows 16..31 the odd steps.
+// ------------------------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __restrict__ HM,
+                                                               double* __restrict__ R, long long part_stride,
+                                                               const double* __restrict__ alpha,
+                                                               const double* __restrict__ beta,
+                                                               const double* __restrict__ cm,
+                                                               const double* __restrict__ ut,
+                                                               const double* __restrict__ st, int k, int Lt, int ng,
+                                                               unsigned long long* __restrict__ counter) {
+  constexpr int CT = C / 16;
+  constexpr int RS = 2 * ((C / 2) | 1);
+  constexpr int ZBYTES = FB_NW * 2 * FB_LC * FB_ZR * 2;
+  constexpr int RBYTES = FB_NW * FB_LC * RS * (int)sizeof(double);
+  __shared__ __align__(16) char smem[ZBYTES > RBYTES ? ZBYTES : RBYTES];
+  __bf16 (*Zt)[2][FB_LC][FB_ZR] = reinterpret_cast<__bf16 (*)[2][FB_LC][FB_ZR]>(smem);
+  double* red = reinterpret_cast<double*>(smem);
+  unsigned long long retained = 0;
+  const int kh = k / 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int pair = blockIdx.x / ng;
+  const int grp = blockIdx.x % ng;
+  const int tile = grp * FB_NW + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < kh;
+  const bool tile_live = tile * 64 < kh;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = 1.0;
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  double* __restrict__ Rg = R + (size_t)grp * part_stride;
+
+  for (int im = 0; im < nm; ++im) {
+    const int m = im == 0 ? pair : k - 1 - pair;
+    const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
+    const double* __restrict__ Hm = HM + (size_t)m * k * C;
+    // element e of a*[kb][ct]: node tile*64 + 32 kb + 8 lq + e, column ct*16 + li (column-pair major)
+    bf16x8 aph[2][CT], apl[2][CT], anh[2][CT], anl[2][CT];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int tg = tile * 64 + 32 * kb + 8 * lq + e;
+          const int c = ct * 16 + li;
+          const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1);
+          const double hp = tg < kh ? col[(size_t)tg * 2] : 0.0;
+          const double hn = tg < kh ? col[(size_t)(kh + tg) * 2] : 0.0;
+          __bf16 hi, lo;
+          split_bf16(hp, hi, lo);
+          aph[kb][ct][e] = hi;
+          apl[kb][ct][e] = lo;
+          split_bf16(hn, hi, lo);
+          anh[kb][ct][e] = hi;
+          anl[kb][ct][e] = lo;
+        }
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cf_next = chunk_coef<FB_LC>(am, bm, 0, k - m, lane);
+
+    for (int l0 = m; l0 < k; l0 += FB_LC) {
+      v4f acc[2][CT];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+      const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
+      const double cf = cf_next;
+      cf_next = chunk_coef<FB_LC>(am, bm, l0 + FB_LC - m, k - m, lane);
+      recur_chunk<FB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
+        __bf16 hi, lo;
+        split_bf16(v, hi, lo);
+        const int row = (j & 1) * (FB_LC / 2) + (j >> 1);
+        Zt[w][0][row][lane] = hi;
+        Zt[w][1][row][lane] = lo;
+      });
+      if (!skip) {
+        wave_lds_sync();
+        const int nl = (k - l0) < FB_LC ? (k - l0) : FB_LC;
+        const int nt = (kh - tile * 64) < 64 ? (kh - tile * 64) : 64;
+        retained += (unsigned long long)nl * (unsigned long long)nt;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          const bf16x8 b0h = *reinterpret_cast<const bf16x8*>(&Zt[w][0][li][32 * kb + 8 * lq]);
+          const bf16x8 b0l = *reinterpret_cast<const bf16x8*>(&Zt[w][1][li][32 * kb + 8 * lq]);
+          const bf16x8 b1h = *reinterpret_cast<const bf16x8*>(&Zt[w][0][16 + li][32 * kb + 8 * lq]);
+          const bf16x8 b1l = *reinterpret_cast<const bf16x8*>(&Zt[w][1][16 + li][32 * kb + 8 * lq]);
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            acc[0][ct] = mma3(aph[kb][ct], apl[kb][ct], b0h, b0l, acc[0][ct]);
+            acc[1][ct] = mma3(anh[kb][ct], anl[kb][ct], b1h, b1l, acc[1][ct]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int lt = 0; lt < 2; ++lt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = ct * 16 + 4 * lq + v;
+            red[((size_t)w * FB_LC + lt * 16 + li) * RS + c] = (double)acc[lt][ct][v];
+          }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < FB_LC * C; idx += FB_NW * 64) {
+        const int lloc = idx / C, c = idx % C;
+        const int l = l0 + 2 * (lloc & 15) + (lloc >> 4);
+        if (l < k) {
+          double sum = 0.0;
+#pragma unroll
+          for (int ww = 0; ww < FB_NW; ++ww) sum += red[(ww * FB_LC + lloc) * RS + c];
+          Rg[(tri_off(k, m) + (l - m)) * C + c] = sum;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (counter != nullptr && lane == 0 && retained > 0) atomicAdd(counter, retained);
+}
+
+// Synthesis: 64-degree chunks, so that one v_mfma_f32_16x16x32_bf16 contracts the 32 even or the
+// 32 odd degrees; z tile row per node [even hi 32 | odd hi 32 | even lo 32 | odd lo 32 | 8 pad];
+// FP32 partial sums (32 terms per chunk and parity) carried into the FP64 north and south sums
+// every IBS_FLUSH chunks.
+constexpr int IBS_LC = 64;
+constexpr int IBS_ZR = 136;
+constexpr int IBS_FLUSH = 2;
+
+template <int C>
+__global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* __restrict__ S,
+                                                                  double* __restrict__ FS,
+                                                                  const double* __restrict__ alpha,
+                                                                  const double* __restrict__ beta,
+                                                                  const double* __restrict__ cm,
+                                                                  const double* __restrict__ ut,
+                                                                  const double* __restrict__ st, int k, int Lt,
+                                                                  int ntb, unsigned long long* __restrict__ counter) {
+  constexpr int CT = C / 16;
+  __shared__ __align__(16) __bf16 Z[4][64][IBS_ZR];
+  const int kh = k / 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int pair = blk / ntb;
+  const int tile = (blk % ntb) * 4 + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < kh;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = 1.0;
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  unsigned long long retained = 0;
+
+  for (int im = 0; im < nm; ++im) {
+    const int m = im == 0 ? pair : k - 1 - pair;
+    const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
+    const double* __restrict__ Sm = S + tri_off(k, m) * C;
+    v4f accE[4][CT], accO[4][CT];
+    double accN[4][CT][4], accS[4][CT][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        accE[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+        accO[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accN[g][ct][v] = accS[g][ct][v] = 0.0;
+      }
+    int since_flush = 0;
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cfa_next = chunk_coef<32>(am, bm, 0, k - m, lane);
+    double cfb_next = chunk_coef<32>(am, bm, 32, k - m, lane);
+    // coefficient rows of the chunk: even degree l0 + 2 (8 lq + q), odd l0 + 2 (8 lq + q) + 1
+    double bn[2][CT][8];
+#pragma unroll
+    for (int par = 0; par < 2; ++par)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int l = m + 2 * (8 * lq + q) + par;
+          bn[par][ct][q] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+        }
+    for (int l0 = m; l0 < k; l0 += IBS_LC) {
+      const bool skip = __all(!valid || negligible(z1, z2, e));
+      bf16x8 bh[2][CT], bl[2][CT];
+#pragma unroll
+      for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            __bf16 hi, lo;
+            split_bf16(bn[par][ct][q], hi, lo);
+            bh[par][ct][q] = hi;
+            bl[par][ct][q] = lo;
+          }
+      if (l0 + IBS_LC < k) {
+#pragma unroll
+        for (int par = 0; par < 2; ++par)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int l = l0 + IBS_LC + 2 * (8 * lq + q) + par;
+              bn[par][ct][q] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
+            }
+      }
+      const double cfa = cfa_next, cfb = cfb_next;
+      cfa_next = chunk_coef<32>(am, bm, l0 + IBS_LC - m, k - m, lane);
+      cfb_next = chunk_coef<32>(am, bm, l0 + IBS_LC + 32 - m, k - m, lane);
+      // z values: 4 consecutive even (odd) steps per 8-byte store of hi and lo parts
+      bf16x4 peh, pel, poh, pol;
+      auto sink = [&](int base) {
+        return [&, base](int j, double v) {
+          const int jj = base + j;
+          __bf16 hi, lo;
+          split_bf16(v, hi, lo);
+          const int i = jj >> 1;   // position within the parity half
+          if (jj & 1) {
+            poh[i & 3] = hi;
+            pol[i & 3] = lo;
+          } else {
+            peh[i & 3] = hi;
+            pel[i & 3] = lo;
+          }
+          if ((jj & 7) == 7) {
+            *reinterpret_cast<bf16x4*>(&Z[w][lane][i - 3]) = peh;
+            *reinterpret_cast<bf16x4*>(&Z[w][lane][32 + i - 3]) = poh;
+            *reinterpret_cast<bf16x4*>(&Z[w][lane][64 + i - 3]) = pel;
+            *reinterpret_cast<bf16x4*>(&Z[w][lane][96 + i - 3]) = pol;
+          }
+        };
+      };
+      recur_chunk<32>(cfa, u, sg, z1, z2, e, sink(0));
+      recur_chunk<32>(cfb, u, sg, z1, z2, e, sink(32));
+      if (!skip) {
+        wave_lds_sync();
+        const int nl = (k - l0) < IBS_LC ? (k - l0) : IBS_LC;
+        retained += (unsigned long long)nl * (unsigned long long)(valid ? 1 : 0);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const __bf16* row = &Z[w][16 * g + li][0];
+          const bf16x8 zeh = *reinterpret_cast<const bf16x8*>(row + 8 * lq);
+          const bf16x8 zoh = *reinterpret_cast<const bf16x8*>(row + 32 + 8 * lq);
+          const bf16x8 zel = *reinterpret_cast<const bf16x8*>(row + 64 + 8 * lq);
+          const bf16x8 zol = *reinterpret_cast<const bf16x8*>(row + 96 + 8 * lq);
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            accE[g][ct] = mma3(zeh, zel, bh[0][ct], bl[0][ct], accE[g][ct]);
+            accO[g][ct] = mma3(zoh, zol, bh[1][ct], bl[1][ct], accO[g][ct]);
+          }
+        }
+        if (++since_flush == IBS_FLUSH) {
+          since_flush = 0;
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const double E = (double)accE[g][ct][v], O = (double)accO[g][ct][v];
+                accN[g][ct][v] += E + O;
+                accS[g][ct][v] += E - O;
+              }
+              accE[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+              accO[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+      }
+      wave_lds_sync();
+    }
+    // result register v of lane l holds node row 4 (l / 16) + v, column l % 16
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int tt = tile * 64 + 16 * g + 4 * lq + v;
+        if (tt < kh) {
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            const int c = ct * 16 + li;
+            double* col = FS + ((size_t)m * C + (c & ~1)) * k + (c & 1);
+            const double E = (double)accE[g][ct][v], O = (double)accO[g][ct][v];
+            col[(size_t)tt * 2] = accN[g][ct][v] + (E + O);
+            col[(size_t)(k - 1 - tt) * 2] = accS[g][ct][v] + (E - O);
+          }
+        }
+      }
+  }
+  if (counter != nullptr) {
+    for (int off = 32; off > 0; off >>= 1) retained += __shfl_down(retained, off);
+    if (lane == 0 && retained > 0) atomicAdd(counter, retained);
+  }
+}
+
+hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
+                                            const double* HM, double* R, long long part_stride,
+                                            unsigned long long* counter, hipStream_t s) {
+  const int k = T.k;
+  if (!T.sym || (k & 1)) return hipErrorInvalidValue;
+  const int ng = legendre_forward_groups_sym(k);
+  const dim3 grid(((k + 1) / 2) * ng), block(FB_NW * 64);
+  if (b.C == 32)
+    k_legendre_fwd_bf16_sym<32><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s,
+                                                       k, G.Lt, ng, counter);
+  else if (b.C == 16)
+    k_legendre_fwd_bf16_sym<16><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s,
+                                                       k, G.Lt, ng, counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
+                                            const double* S, double* FS, unsigned long long* counter,
+                                            hipStream_t s) {
+  const int k = T.k;
+  if (!T.sym || (k & 1)) return hipErrorInvalidValue;
+  const int ntb = (k / 2 + 255) / 256;
+  const dim3 grid(((k + 1) / 2) * ntb), block(256);
+  if (b.C == 32)
+    k_legendre_inv_bf16_sym<32><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt, ntb,
+                                                       counter);
+  else if (b.C == 16)
+    k_legendre_inv_bf16_sym<16><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt, ntb,
+                                                       counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 template <int C>
 static hipError_t fwd_bf16_c(const ShtTables& T, const LegTables& G, const double* HM, double* R,
                              long long part_stride, unsigned long long* counter, hipStream_t s) {

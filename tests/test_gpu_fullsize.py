@@ -130,3 +130,40 @@ def test_symmetric_grid_batches_full_size(dev, reality, nmaps, ndistinct):
                          reality).cpu().numpy()
     for i in range(nmaps):
         assert _rel(gotm[i][rings, :], refm[i % ndistinct], 0.0) < TOL
+
+
+TOL_FP32_2048 = 2e-6   # the bound stated up to L = 512 (test_gpu_mixed.py) also holds at L = 2048
+
+
+def test_fp32_symmetric_grid_full_size(data):
+    """FP32 contraction on the symmetric grid (16 real maps, L = 2048): forward against the seeded
+    coefficients, inverse on oracle rings."""
+    dev = data["fd"].device
+    got = s2.mw_forward(data["fd"], L, s2.REAL, s2.MIXED_FP32).cpu().numpy()
+    worst = max(_rel(got[i], data["flm"][i % 2], 0.0) for i in range(NMAPS))
+    print("  fp32 forward worst rel err %.3e" % worst, flush=True)
+    assert worst < TOL_FP32_2048
+    rings = [0, 1, 1023, 1024, 2047]
+    ref = oracle.inverse_sht_rings(data["flm"], L, rings, reality=True)
+    flm = torch.from_numpy(np.concatenate([data["flm"]] * (NMAPS // 2))).to(dev)
+    inv = s2.mw_inverse(flm, L, s2.REAL, s2.MIXED_FP32).cpu().numpy()
+    worst = max(_rel(inv[i][rings, :], ref[i % 2], 0.0) for i in range(NMAPS))
+    print("  fp32 inverse worst rel err %.3e" % worst, flush=True)
+    assert worst < TOL_FP32_2048
+
+
+def test_bf16x3_symmetric_grid_full_size(data):
+    """BF16x3 contraction on the symmetric grid (16 real maps, L = 2048), against the bound stated
+    for that mode (1e-4, test_gpu_mixed.py)."""
+    dev = data["fd"].device
+    got = s2.mw_forward(data["fd"], L, s2.REAL, s2.MIXED_BF16X3).cpu().numpy()
+    worst = max(_rel(got[i], data["flm"][i % 2], 0.0) for i in range(NMAPS))
+    print("  bf16x3 forward worst rel err %.3e" % worst, flush=True)
+    assert worst < 1e-4
+    rings = [0, 1, 1023, 1024, 2047]
+    ref = oracle.inverse_sht_rings(data["flm"], L, rings, reality=True)
+    flm = torch.from_numpy(np.concatenate([data["flm"]] * (NMAPS // 2))).to(dev)
+    inv = s2.mw_inverse(flm, L, s2.REAL, s2.MIXED_BF16X3).cpu().numpy()
+    worst = max(_rel(inv[i][rings, :], ref[i % 2], 0.0) for i in range(NMAPS))
+    print("  bf16x3 inverse worst rel err %.3e" % worst, flush=True)
+    assert worst < 1e-4

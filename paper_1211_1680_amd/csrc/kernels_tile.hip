@@ -83,29 +83,49 @@ __global__ void k_pack(const double* __restrict__ R, int nparts, long long pstri
   }
 }
 
-// dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks).  Without accumulation the
-// rows l >= ks of dst are zero-filled; with accumulation they are left alone (they would only
-// receive zeros), so rows and columns m >= ks are not visited at all (klim = min(ks, kd)).
+// Row q of the triangle of band-limit kl (rows ordered by m, then r = l - m): the largest m with
+// tri_off(kl, m) <= q, from the smaller root of m^2 - (2 kl + 1) m + 2 q = 0, then corrected.
+__device__ __forceinline__ void tri_row_mr(int kl, long long q, int& m, int& r) {
+  const double b = 2.0 * kl + 1.0;
+  int mm = (int)floor(0.5 * (b - sqrt(b * b - 8.0 * (double)q)));
+  mm = mm < 0 ? 0 : (mm > kl - 1 ? kl - 1 : mm);
+  while (mm > 0 && tri_off(kl, mm) > q) --mm;
+  while (mm + 1 < kl && tri_off(kl, mm + 1) <= q) ++mm;
+  m = mm;
+  r = (int)(q - tri_off(kl, mm));
+}
+
+// dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks), over the triangle of band-limit
+// klim: one thread per (row, column pair).  Without accumulation klim = kd and the rows l >= ks
+// of dst are zero-filled; with accumulation klim = min(ks, kd), so rows and columns m >= ks are
+// not visited (they would only receive zeros).
 __global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long long pstride,
                        double* __restrict__ dst, int kd, int klim, const double* __restrict__ kern,
                        const double* __restrict__ dfac, int Lt, int C, int accumulate) {
-  const int m = blockIdx.y;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int len = klim - m;
-  if (len <= 0 || idx >= len * C) return;
-  const int r = idx / C, c = idx % C;
+  const int CP = C / 2;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= tri_rows(klim) * CP) return;
+  const long long q = idx / CP;
+  const int cp = (int)(idx % CP);
+  int m, r;
+  tri_row_mr(klim, q, m, r);
   const int l = m + r;
-  double v = 0.0;
+  double2 v = make_double2(0.0, 0.0);
   if (l < ks) {
     const double d = dfac[tri_off(Lt, m) + r];
-    const size_t at = (tri_off(ks, m) + r) * C + c;
-    double x = 0.0;
-    for (int g = 0; g < nparts; ++g) x += src[at + (size_t)g * pstride];
-    v = kern[l] * d * d * x;
+    const double2* at = reinterpret_cast<const double2*>(src + (tri_off(ks, m) + r) * C) + cp;
+    double2 x = make_double2(0.0, 0.0);
+    for (int g = 0; g < nparts; ++g) {
+      const double2 y = at[(size_t)g * (pstride / 2)];
+      x.x += y.x;
+      x.y += y.y;
+    }
+    const double f = kern[l] * d * d;
+    v = make_double2(f * x.x, f * x.y);
   }
-  double* o = dst + (tri_off(kd, m) + r) * C + c;
+  double2* o = reinterpret_cast<double2*>(dst + (tri_off(kd, m) + r) * C) + cp;
   if (accumulate)
-    *o += v;
+    *o = make_double2(o->x + v.x, o->y + v.y);
   else
     *o = v;
 }
@@ -183,8 +203,11 @@ hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, in
                        long long part_stride, double* dst, int kd, const double* kern, int accumulate,
                        hipStream_t s) {
   const int klim = accumulate ? (ks < kd ? ks : kd) : kd;
-  dim3 grid((klim * b.C + 255) / 256, klim);
-  k_tile<<<grid, 256, 0, s>>>(src, ks, nparts, part_stride, dst, kd, klim, kern, G.dfac, G.Lt, b.C, accumulate);
+  if (b.C & 1) return hipErrorInvalidValue;
+  const long long total = tri_rows(klim) * (b.C / 2);
+  if (total == 0) return hipSuccess;
+  k_tile<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(src, ks, nparts, part_stride, dst, kd, klim, kern, G.dfac,
+                                                         G.Lt, b.C, accumulate);
   return hipGetLastError();
 }
 

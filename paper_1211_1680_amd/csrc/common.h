@@ -114,6 +114,14 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
 // the north/south sums in rows s < k/2 and differences in rows k/2 + s), the Legendre steps on
 // the northern nodes (the synthesis writes FS[m][s][c], s < k), and the resampling FS -> FT[t][m][c].
 hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
+// The same stages compiled for band-limit 1024 (n = 2047 by Bluestein over 4096 points).
+bool fft_k1024_applies(const ShtTables& T);
+hipError_t launch_phi_forward_1024(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                   double* GT, hipStream_t s);
+hipError_t launch_phi_inverse_1024(const ShtTables& T, const Batch& b, const double* FT, void* f,
+                                   int64_t map_stride, hipStream_t s);
+hipError_t launch_theta_1024_sym(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
+hipError_t launch_resample_1024(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
 int legendre_forward_groups_sym(int k);
 hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
                                        double* R, long long part_stride, int precision,

@@ -22,7 +22,8 @@ __device__ __forceinline__ void dft_small(double2* v) {
 }
 
 // One pass: N points, radix R, NS = product of the radices of the earlier passes, T threads.
-template <int N, int R, int NS, bool INV, int T>
+// The twiddle tables hold W_{N TS}^p (TS > 1: a shorter transform with the tables of a longer one).
+template <int N, int R, int NS, bool INV, int T, int TS = 1>
 __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo, const double2* whi) {
   constexpr int NB = N / R;
   constexpr int STRIDE = N / (NS * R);
@@ -36,7 +37,7 @@ __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = buf[lds_pad(j + r * NB)];
       if constexpr (NS > 1) {
-        const int p = (j % NS) * STRIDE;
+        const int p = (j % NS) * STRIDE * TS;
         double2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
         if (INV) w1 = conjd(w1);
         double2 w = w1;
@@ -70,6 +71,37 @@ __device__ __forceinline__ void fft4096(double2* buf, int lt, const double2* wlo
   ct_pass<4096, 8, 8, INV, T>(buf, lt, wlo, whi);
   ct_pass<4096, 8, 64, INV, T>(buf, lt, wlo, whi);
   ct_pass<4096, 8, 512, INV, T>(buf, lt, wlo, whi);
+}
+
+// 2048 = 8^3 * 4, with the twiddle tables of length 4096 (unnormalised, sign -1 or +1 with INV)
+template <bool INV, int T>
+__device__ __forceinline__ void fft2048(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  ct_pass<2048, 8, 1, INV, T, 2>(buf, lt, wlo, whi);
+  ct_pass<2048, 8, 8, INV, T, 2>(buf, lt, wlo, whi);
+  ct_pass<2048, 8, 64, INV, T, 2>(buf, lt, wlo, whi);
+  ct_pass<2048, 4, 512, INV, T, 2>(buf, lt, wlo, whi);
+}
+
+// Bluestein DFT of length n <= 2048 (here 2047) in buf[0..n), natural order in and out, over the
+// 4096-point FFT: X_j = c_j sum_q (x_q c_q) conj(c_{j-q}), c_q = exp(-+ i pi q^2 / n); bhat is the
+// FFT of conj(c) wrapped to 4096, divided by 4096.  Ends with a barrier.
+template <bool INV, int T>
+__device__ __forceinline__ void dft_bluestein4096(double2* buf, int n, int lt, const double2* wlo,
+                                                  const double2* whi, const double2* __restrict__ chirp,
+                                                  const double2* __restrict__ bhat) {
+  for (int q = lt; q < 4096; q += T) {
+    double2 v = make_double2(0.0, 0.0);
+    if (q < n) v = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
+    buf[lds_pad(q)] = v;
+  }
+  __syncthreads();
+  fft4096<false, T>(buf, lt, wlo, whi);
+  for (int q = lt; q < 4096; q += T)
+    buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(bhat[(4096 - q) & 4095]) : bhat[q]);
+  __syncthreads();
+  fft4096<true, T>(buf, lt, wlo, whi);
+  for (int q = lt; q < n; q += T) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
+  __syncthreads();
 }
 
 // 4095 = 13 * 9 * 7 * 5

@@ -1,0 +1,383 @@
+// The O(k^2 log k) stages of the MW transform at band-limit k = 1024, compiled for that size:
+// n = 2k - 1 = 2047 = 23 * 89 has no small radices, so the odd-length DFT is Bluestein's chirp
+// transform over the 4096-point FFT; the correlation of the theta stage and the symmetric grid
+// psi_s = pi (2s+1) / 2048 use the 2048-point FFT.  Same arithmetic as the general kernels
+// (kernels_fft.hip) and as the band-limit 2048 kernels (kernels_fft_k2048.hip): phi DFT (Sect. 2.1,
+// MW sampling), theta stage evaluated on the symmetric grid (its last transform), resampling
+// from the symmetric grid to the MW nodes, inverse phi DFT.  One problem per 512-thread block,
+// about 78 KiB of LDS, so two blocks share a CU.
+#include "common.h"
+#include "fft_ct.h"
+#include "../../include/s2let_mi355x.h"
+
+namespace s2let {
+
+namespace {
+constexpr int K = 1024;
+constexpr int N = 2 * K - 1;    // 2047
+constexpr int NB = 4096;        // Bluestein length
+constexpr int NC = 2048;        // correlation length and symmetric-grid circle (2k points)
+constexpr int TT = 512;
+constexpr int NBUF = lds_padded(NB);
+
+struct K1024Args {
+  const double2* tw_lo;    // W_4096^p, p < 64
+  const double2* tw_hi;    // W_4096^(64 q), q < 64
+  const double2* chirp;    // exp(-i pi q^2 / n), q < n
+  const double2* bhat;     // FFT_4096 of conj(chirp), wrapped, / 4096
+  const double2* khat0;
+  const double2* khat1;
+  const double2* hphase;
+  const double2* psph;
+  const double* pole_s;
+  const double2* rsph;
+};
+
+__device__ __forceinline__ void stage_tw(const K1024Args& A, double2* wlo, double2* whi) {
+  if (threadIdx.x < 64) {
+    wlo[threadIdx.x] = A.tw_lo[threadIdx.x];
+    whi[threadIdx.x] = A.tw_hi[threadIdx.x];
+  }
+}
+}  // namespace
+
+// phi stage, forward (see k_phi_forward): GT[(t*k + m)*C + c] for m < k.
+template <int REAL>
+__global__ __launch_bounds__(TT, 4) void k_phi_forward_1024(K1024Args A, const double* __restrict__ f,
+                                                            long long map_stride, double* __restrict__ GT,
+                                                            int C, int nb, int used, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 wlo[64], whi[64];
+  stage_tw(A, wlo, whi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int nunits = REAL ? (nb + 1) / 2 : nb;
+  const int t = valid ? p / nunits : 0;
+  const int u = valid ? p % nunits : 0;
+  const int ma = REAL ? 2 * u : u;
+  const bool hasb = REAL && (ma + 1 < nb);
+  for (int q = lt; q < N; q += TT) {
+    double2 z = make_double2(0.0, 0.0);
+    if (valid) {
+      if (REAL) {
+        z.x = f[(size_t)ma * map_stride + (size_t)t * N + q];
+        z.y = hasb ? f[(size_t)(ma + 1) * map_stride + (size_t)t * N + q] : 0.0;
+      } else {
+        z = reinterpret_cast<const double2*>(f)[(size_t)ma * map_stride + (size_t)t * N + q];
+      }
+    }
+    buf[lds_pad(q)] = z;
+  }
+  __syncthreads();
+  dft_bluestein4096<false, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  const double wphi = 2.0 * M_PI / (double)N;
+  if (valid) {
+    for (int m = lt; m < K; m += TT) {
+      const double2 zp = buf[lds_pad(m)];
+      const double2 zn = buf[lds_pad(m == 0 ? 0 : N - m)];
+      double* row = GT + ((size_t)t * K + m) * C;
+      if (REAL) {
+        row[2 * ma] = wphi * 0.5 * (zp.x + zn.x);
+        row[2 * ma + 1] = wphi * 0.5 * (zp.y - zn.y);
+        if (hasb) {
+          row[2 * ma + 2] = wphi * 0.5 * (zp.y + zn.y);
+          row[2 * ma + 3] = -wphi * 0.5 * (zp.x - zn.x);
+        }
+      } else {
+        row[4 * ma] = wphi * zp.x;
+        row[4 * ma + 1] = wphi * zp.y;
+        row[4 * ma + 2] = (m == 0) ? 0.0 : wphi * zn.x;
+        row[4 * ma + 3] = (m == 0) ? 0.0 : wphi * zn.y;
+      }
+      if (u == 0)
+        for (int c = used; c < C; ++c) row[c] = 0.0;
+    }
+  }
+}
+
+// theta stage on the symmetric grid (see k_theta_2048<true>): GT[(t*k + m)*C + c] -> HM, column-pair
+// major, entry s < k/2 the north/south sums, entry k/2 + s the differences.
+__global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const double* __restrict__ GT,
+                                                          double* __restrict__ HM, int C, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 wlo[64], whi[64];
+  stage_tw(A, wlo, whi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int ns = C / 2;
+  const int mu = valid ? p / ns : 0;
+  const int s = valid ? p % ns : 0;
+  const int mE = 2 * mu, mO = 2 * mu + 1;
+  // packed extension without the odd pole value
+  for (int t = lt; t < N; t += TT) {
+    double2 g = make_double2(0.0, 0.0);
+    if (valid) {
+      const int tt = (t < K) ? t : N - 1 - t;
+      const double sg = (t < K) ? 1.0 : -1.0;
+      const double* rE = GT + ((size_t)tt * K + mE) * C + 2 * s;
+      g.x = rE[0];
+      g.y = rE[1];
+      if (tt < K - 1) {
+        const double* rO = GT + ((size_t)tt * K + mO) * C + 2 * s;
+        g.x += sg * rO[0];
+        g.y += sg * rO[1];
+      }
+    }
+    buf[lds_pad(t)] = g;
+  }
+  __syncthreads();
+  dft_bluestein4096<false, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  constexpr int MAXV = NB / TT;   // 8 >= ceil((2K-1) / TT)
+  constexpr int NJ = 2 * K - 1;
+  double2 keep[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) {
+      const int j = idx - (K - 1);
+      keep[i] = cmul(A.hphase[idx], buf[lds_pad(j < 0 ? j + N : j)]);
+    }
+  }
+#pragma unroll
+  for (int P = 0; P < 2; ++P) {
+    __syncthreads();
+    for (int q = lt; q < NC; q += TT) buf[lds_pad(q)] = make_double2(0.0, 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * TT;
+      if (idx < NJ) {
+        const int j = idx - (K - 1);
+        if (((j - P) & 1) == 0) buf[lds_pad(((j - P) / 2) & (NC - 1))] = keep[i];
+      }
+    }
+    __syncthreads();
+    fft2048<false, TT>(buf, lt, wlo, whi);
+    const double2* kh = P == 0 ? A.khat0 : A.khat1;
+    for (int q = lt; q < NC; q += TT) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
+    __syncthreads();
+    fft2048<true, TT>(buf, lt, wlo, whi);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * TT;
+      if (idx < NJ) {
+        const int jp = idx - (K - 1);
+        if (((jp - P) & 1) == 0) keep[i] = cmul(A.psph[idx], buf[lds_pad((-(jp - P) / 2) & (NC - 1))]);
+      }
+    }
+  }
+  __syncthreads();
+  // I(j') at j' mod 2048 (slot 1024 stays empty), FFT onto the psi grid
+  if (lt == 0) buf[lds_pad(K)] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) buf[lds_pad((idx - (K - 1)) & (NC - 1))] = keep[i];
+  }
+  __syncthreads();
+  fft2048<false, TT>(buf, lt, wlo, whi);
+  if (valid) {
+    const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
+    const double2 pO = make_double2(rP[0], rP[1]);
+    for (int q = lt; q < K / 2; q += TT) {
+      const int qs = K - 1 - q;
+      const double2 a1 = buf[lds_pad(q)], a2 = buf[lds_pad(NC - 1 - q)];
+      const double2 b1 = buf[lds_pad(qs)], b2 = buf[lds_pad(NC - 1 - qs)];
+      const double2 hea = cadd(a1, a2), heb = cadd(b1, b2);
+      double2 hoa = csub(a1, a2), hob = csub(b1, b2);
+      hoa.x = fma(A.pole_s[q], pO.x, hoa.x);
+      hoa.y = fma(A.pole_s[q], pO.y, hoa.y);
+      hob.x = fma(A.pole_s[qs], pO.x, hob.x);
+      hob.y = fma(A.pole_s[qs], pO.y, hob.y);
+      double2* colE = reinterpret_cast<double2*>(HM) + ((size_t)mE * ns + s) * K;
+      double2* colO = reinterpret_cast<double2*>(HM) + ((size_t)mO * ns + s) * K;
+      colE[q] = cadd(hea, heb);
+      colE[K / 2 + q] = csub(hea, heb);
+      colO[q] = cadd(hoa, hob);
+      colO[K / 2 + q] = csub(hoa, hob);
+    }
+  }
+}
+
+// Resampling from the symmetric grid to the MW nodes (see k_resample_2048).
+__global__ __launch_bounds__(TT, 4) void k_resample_1024(K1024Args A, const double* __restrict__ FS,
+                                                         double* __restrict__ FT, int C, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 wlo[64], whi[64];
+  stage_tw(A, wlo, whi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int ns = C / 2;
+  const int mu = valid ? p / ns : 0;
+  const int s = valid ? p % ns : 0;
+  const int mE = 2 * mu, mO = 2 * mu + 1;
+  constexpr int NL = K / TT;   // 2
+  double2 fe[NL], fo[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int q = lt + i * TT;
+    fe[i] = make_double2(0.0, 0.0);
+    fo[i] = make_double2(0.0, 0.0);
+    if (valid) {
+      fe[i] = reinterpret_cast<const double2*>(FS)[((size_t)mE * ns + s) * K + q];
+      fo[i] = reinterpret_cast<const double2*>(FS)[((size_t)mO * ns + s) * K + q];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    const int q = lt + i * TT;
+    buf[lds_pad(q)] = cadd(fe[i], fo[i]);
+    buf[lds_pad(NC - 1 - q)] = csub(fe[i], fo[i]);
+  }
+  __syncthreads();
+  fft2048<false, TT>(buf, lt, wlo, whi);
+  constexpr int MAXV = NC / TT;   // 4 >= ceil((2K-1) / TT)
+  constexpr int NJ = 2 * K - 1;
+  double2 keep[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) keep[i] = cmul(A.rsph[idx], buf[lds_pad((idx - (K - 1)) & (NC - 1))]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    const int idx = lt + i * TT;
+    if (idx < NJ) {
+      const int j = idx - (K - 1);
+      buf[lds_pad(j < 0 ? j + N : j)] = keep[i];
+    }
+  }
+  __syncthreads();
+  dft_bluestein4096<true, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  if (valid) {
+    for (int t = lt; t < K; t += TT) {
+      const double2 h1 = buf[lds_pad(t)];
+      double2 he, ho;
+      if (t < K - 1) {
+        const double2 h2 = buf[lds_pad(N - 1 - t)];
+        he = cadd(h1, h2);
+        ho = csub(h1, h2);
+      } else {
+        he = cadd(h1, h1);
+        ho = make_double2(0.0, 0.0);
+      }
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mE) * C + 2 * s) = he;
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mO) * C + 2 * s) = ho;
+    }
+  }
+}
+
+// phi stage, inverse (see k_phi_inverse): FT[(t*k + m)*C + c] -> maps.
+template <int REAL>
+__global__ __launch_bounds__(TT, 4) void k_phi_inverse_1024(K1024Args A, const double* __restrict__ FT,
+                                                            double* __restrict__ f, long long map_stride, int C,
+                                                            int nb, int nprob) {
+  __shared__ double2 buf[NBUF];
+  __shared__ double2 wlo[64], whi[64];
+  stage_tw(A, wlo, whi);
+  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x;
+  const bool valid = p < nprob;
+  const int nunits = REAL ? (nb + 1) / 2 : nb;
+  const int t = valid ? p / nunits : 0;
+  const int u = valid ? p % nunits : 0;
+  const int ma = REAL ? 2 * u : u;
+  const bool hasb = REAL && (ma + 1 < nb);
+  for (int q = lt; q < N; q += TT) {
+    double2 z = make_double2(0.0, 0.0);
+    if (valid) {
+      const bool neg = q >= K;
+      const int m = neg ? N - q : q;
+      const double* row = FT + ((size_t)t * K + m) * C;
+      if (REAL) {
+        double2 a = make_double2(row[2 * ma], row[2 * ma + 1]);
+        double2 b = hasb ? make_double2(row[2 * ma + 2], row[2 * ma + 3]) : make_double2(0.0, 0.0);
+        if (neg) {
+          a = conjd(a);
+          b = conjd(b);
+        }
+        z = make_double2(a.x - b.y, a.y + b.x);
+      } else {
+        z = neg ? make_double2(row[4 * ma + 2], row[4 * ma + 3]) : make_double2(row[4 * ma], row[4 * ma + 1]);
+      }
+    }
+    buf[lds_pad(q)] = z;
+  }
+  __syncthreads();
+  dft_bluestein4096<true, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  if (valid) {
+    for (int q = lt; q < N; q += TT) {
+      const double2 v = buf[lds_pad(q)];
+      if (REAL) {
+        f[(size_t)ma * map_stride + (size_t)t * N + q] = v.x;
+        if (hasb) f[(size_t)(ma + 1) * map_stride + (size_t)t * N + q] = v.y;
+      } else {
+        reinterpret_cast<double2*>(f)[(size_t)ma * map_stride + (size_t)t * N + q] = v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+bool fft_k1024_applies(const ShtTables& T) {
+  return T.k == K && T.n == N && T.nrad == 0 && T.M == NB && T.Nc == NC && T.logP == 12 && T.loglo == 6;
+}
+
+static K1024Args k1024_args(const ShtTables& T) {
+  K1024Args a;
+  a.tw_lo = T.tw_lo;
+  a.tw_hi = T.tw_hi;
+  a.chirp = T.chirp;
+  a.bhat = T.bhat;
+  a.khat0 = T.khat0;
+  a.khat1 = T.khat1;
+  a.hphase = T.hphase;
+  a.psph = T.psph;
+  a.pole_s = T.pole_s;
+  a.rsph = T.rsph;
+  return a;
+}
+
+hipError_t launch_phi_forward_1024(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                   double* GT, hipStream_t s) {
+  const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
+  const int nprob = K * nunits;
+  const K1024Args a = k1024_args(T);
+  if (b.reality == S2LET_REAL)
+    k_phi_forward_1024<1><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+  else
+    k_phi_forward_1024<0><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_inverse_1024(const ShtTables& T, const Batch& b, const double* FT, void* f,
+                                   int64_t map_stride, hipStream_t s) {
+  const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
+  const int nprob = K * nunits;
+  const K1024Args a = k1024_args(T);
+  if (b.reality == S2LET_REAL)
+    k_phi_inverse_1024<1><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+  else
+    k_phi_inverse_1024<0><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_theta_1024_sym(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s) {
+  if (!T.sym || !fft_k1024_applies(T)) return hipErrorInvalidValue;
+  const int nprob = (K / 2) * (b.C / 2);
+  k_theta_1024_sym<<<nprob, TT, 0, s>>>(k1024_args(T), GT, HM, b.C, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample_1024(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
+  if (!T.sym || !fft_k1024_applies(T)) return hipErrorInvalidValue;
+  const int nprob = (K / 2) * (b.C / 2);
+  k_resample_1024<<<nprob, TT, 0, s>>>(k1024_args(T), FS, FT, b.C, nprob);
+  return hipGetLastError();
+}
+
+}  // namespace s2let

@@ -106,27 +106,31 @@ def test_forward_arbitrary_samples_full_size(dev):
     assert _rel(got, ref, 0.0) < TOL
 
 
-@pytest.mark.parametrize("reality,nmaps,ndistinct", [(s2.REAL, 8, 2), (s2.REAL, 16, 2), (s2.COMPLEX, 4, 1)])
-def test_symmetric_grid_batches_full_size(dev, reality, nmaps, ndistinct):
-    """At L = 2048 the FP64 transforms of batches of 16 or 32 columns (8 or 16 real maps, 4
-    complex maps) run their Legendre steps on the symmetric grid.  Samples that are not
-    band-limited (independent unit normals, so the odd-m pole terms matter) go forward; seeded
-    coefficients go inverse.  The batch repeats ndistinct maps, which the oracle evaluates."""
+@pytest.mark.parametrize("k,reality,nmaps,ndistinct", [
+    (2048, s2.REAL, 8, 2), (2048, s2.REAL, 16, 2), (2048, s2.COMPLEX, 4, 1),
+    (1024, s2.REAL, 16, 2), (1024, s2.COMPLEX, 8, 1), (1024, s2.REAL, 2, 2), (1024, s2.COMPLEX, 1, 1)])
+def test_symmetric_grid_batches_full_size(dev, k, reality, nmaps, ndistinct):
+    """At band-limits 2048 and 1024 (compiled transforms) the FP64 transforms of batches of 16 or
+    32 columns (8 or 16 real maps, 4 or 8 complex maps) run their Legendre steps on the symmetric
+    grid; smaller batches (2 real maps, 1 complex map) take the compiled phi stages with the MW-node
+    theta stage.  Samples that are not band-limited (independent unit normals, so the odd-m pole
+    terms matter) go forward; seeded coefficients go inverse.  The batch repeats ndistinct maps,
+    which the oracle evaluates."""
     real = reality == s2.REAL
-    rng = np.random.default_rng(4096 + nmaps)
-    base = rng.standard_normal((ndistinct, L, 2 * L - 1))
+    rng = np.random.default_rng(4096 + nmaps + k)
+    base = rng.standard_normal((ndistinct, k, 2 * k - 1))
     if not real:
-        base = base + 1j * rng.standard_normal((ndistinct, L, 2 * L - 1))
-    print("symmetric grid: oracle forward of %d map(s), reality=%d" % (ndistinct, reality), flush=True)
-    ref = oracle.forward_sht(base, L)
+        base = base + 1j * rng.standard_normal((ndistinct, k, 2 * k - 1))
+    print("k=%d: oracle forward of %d map(s), reality=%d, batch %d" % (k, ndistinct, reality, nmaps), flush=True)
+    ref = oracle.forward_sht(base, k)
     f = np.concatenate([base] * (nmaps // ndistinct))
-    got = s2.mw_forward(torch.from_numpy(f).to(dev), L, reality).cpu().numpy()
+    got = s2.mw_forward(torch.from_numpy(f).to(dev), k, reality).cpu().numpy()
     for i in range(nmaps):
         assert _rel(got[i], ref[i % ndistinct], 0.0) < TOL
-    flm = si.random_flm(L, ndistinct, reality=real, seed=77)
-    rings = [0, 1, 511, 1023, 1024, 2046, 2047]
-    refm = oracle.inverse_sht_rings(flm, L, rings, reality=real)
-    gotm = s2.mw_inverse(torch.from_numpy(np.concatenate([flm] * (nmaps // ndistinct))).to(dev), L,
+    flm = si.random_flm(k, ndistinct, reality=real, seed=77)
+    rings = sorted({0, 1, k // 4 - 1, k // 2 - 1, k // 2, k - 2, k - 1})
+    refm = oracle.inverse_sht_rings(flm, k, rings, reality=real)
+    gotm = s2.mw_inverse(torch.from_numpy(np.concatenate([flm] * (nmaps // ndistinct))).to(dev), k,
                          reality).cpu().numpy()
     for i in range(nmaps):
         assert _rel(gotm[i][rings, :], refm[i % ndistinct], 0.0) < TOL

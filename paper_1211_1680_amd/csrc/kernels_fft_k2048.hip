@@ -178,7 +178,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       }
     }
     __syncthreads();
-    fft4096<false, TT>(buf, lt, w6lo, w6hi);
+    fft4096_r8<false, TT>(buf, lt, w6lo, w6hi);
     const double2* kh = P == 0 ? A.khat0 : A.khat1;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
     }
     __syncthreads();
-    fft4096<true, TT>(buf, lt, w6lo, w6hi);
+    fft4096_r8<true, TT>(buf, lt, w6lo, w6hi);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       if (idx < NJ) buf[lds_pad((idx - (K - 1)) & (NC - 1))] = keep[i];
     }
     __syncthreads();
-    fft4096<false, TT>(buf, lt, w6lo, w6hi);
+    fft4096_r8<false, TT>(buf, lt, w6lo, w6hi);
     if (valid) {
       const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
       const double2 pO = make_double2(rP[0], rP[1]);

@@ -548,7 +548,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
                                                           unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
   constexpr bool F64 = sizeof(T) == sizeof(double);
+  // the coefficient rows of a chunk, loaded once per block (the four waves share them) into a
+  // double-buffered tile; row stride 40 doubles puts the rows a half wave reads (2 apart) 16
+  // banks apart
+  constexpr int SBS = 40;
+  constexpr int PER = INVM_LC * C / 256;   // doubles per thread per chunk (2 for C = 32)
   __shared__ T Z[4][INVM_LC][INVM_ZS];
+  __shared__ double Sb[2][INVM_LC][SBS];
   const int kh = k / 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
@@ -591,16 +597,25 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
     double z1, z2;
     recur_start(cm[m], s, sg, m, z1, z2, e);
     double cf_next = chunk_coef<INVM_LC>(am, bm, 0, k - m, lane);
-    // k-step sl covers the steps jd = (sl >> 1) + 8 (sl & 1) + 2 lq: sl = 0, 1 even, sl = 2, 3 odd
-    double bn[INVM_LC / 4][CT];
+    // tile element (row r, column c) of this thread: r = (tid * PER) / C, c = (tid * PER) % C + i
+    const int tr = (threadIdx.x * PER) / C, tc = (threadIdx.x * PER) % C;
+    double pre[PER];
 #pragma unroll
-    for (int sl = 0; sl < INVM_LC / 4; ++sl) {
-      const int l = m + (sl >> 1) + 8 * (sl & 1) + 2 * lq;
+    for (int i = 0; i < PER; ++i) pre[i] = (m + tr < k) ? Sm[(size_t)tr * C + tc + i] : 0.0;
+    __syncthreads();   // the previous m's last tile has been read
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
-    }
+    for (int i = 0; i < PER; ++i) Sb[0][tr][tc + i] = pre[i];
+    __syncthreads();
+    int cur = 0;
     for (int l0 = m; l0 < k; l0 += INVM_LC) {
       const bool skip = __all(!valid || negligible(z1, z2, e));
+      // the next chunk's rows, in flight during this chunk's recursion and products
+      const bool more = l0 + INVM_LC < k;
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+          pre[i] = (l0 + INVM_LC + tr < k) ? Sm[(size_t)(l0 + INVM_LC - m + tr) * C + tc + i] : 0.0;
+      }
       const double cf = cf_next;
       cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
       recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e,
@@ -611,15 +626,20 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
         retained += (unsigned long long)nl * (unsigned long long)(valid ? 1 : 0);
 #pragma unroll
         for (int sl = 0; sl < INVM_LC / 4; ++sl) {
+          // k-step sl covers the steps jd = (sl >> 1) + 8 (sl & 1) + 2 lq: sl = 0, 1 even, sl = 2, 3 odd
+          const int jd = (sl >> 1) + 8 * (sl & 1) + 2 * lq;
+          T bv[CT];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) bv[ct] = (T)Sb[cur][jd][ct * 16 + li];
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
             const T av = Z[w][4 * sl + lq][16 * g + li];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
               if (sl < 2)
-                accE[g][ct] = Mma<T>::mma(av, (T)bn[sl][ct], accE[g][ct]);
+                accE[g][ct] = Mma<T>::mma(av, bv[ct], accE[g][ct]);
               else
-                accO[g][ct] = Mma<T>::mma(av, (T)bn[sl][ct], accO[g][ct]);
+                accO[g][ct] = Mma<T>::mma(av, bv[ct], accO[g][ct]);
             }
           }
         }
@@ -643,15 +663,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
           }
         }
       }
-      // the next chunk's coefficient rows are in flight during its recursion
-      if (l0 + INVM_LC < k) {
+      if (more) {
 #pragma unroll
-        for (int sl = 0; sl < INVM_LC / 4; ++sl) {
-          const int l = l0 + INVM_LC + (sl >> 1) + 8 * (sl & 1) + 2 * lq;
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) bn[sl][ct] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
-        }
+        for (int i = 0; i < PER; ++i) Sb[cur ^ 1][tr][tc + i] = pre[i];
       }
+      __syncthreads();   // the next tile is written and this one has been read by every wave
+      cur ^= 1;
     }
 #pragma unroll
     for (int g = 0; g < 4; ++g)

@@ -13,6 +13,25 @@ namespace s2let {
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
 constexpr int lds_padded(int n) { return n + (n >> 3) + 1; }
 
+// Input of the theta stage for an even order mE and the odd order mE + 1 of one column pair:
+// ring r < K of both orders, r = lt + i T.  Every gather is issued before the first one is
+// consumed, and each ring is read once for both of its nodes on the 2 pi extension (t = r and
+// t = 2K-2-r).
+template <int K, int T>
+struct RingGather {
+  static constexpr int PER = K / T;
+  static_assert(K % T == 0, "rings per thread");
+  double2 ge[PER], go[PER];
+  __device__ __forceinline__ void load(const double* __restrict__ GT, int C, int mE, int s, int lt) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const double* row = GT + ((size_t)(lt + i * T) * K + mE) * C + 2 * s;
+      ge[i] = *reinterpret_cast<const double2*>(row);
+      go[i] = *reinterpret_cast<const double2*>(row + C);
+    }
+  }
+};
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft_small(double2* v) {
   if constexpr (R == 2 || R == 4 || R == 8 || R == 16)

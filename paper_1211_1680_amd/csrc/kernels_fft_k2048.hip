@@ -125,25 +125,26 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
 
   // packed extension without the odd pole value (applied by the pole correction, see k_theta)
   double2 racc = make_double2(0.0, 0.0);
-  for (int t = lt; t < N; t += TT) {
-    double2 g = make_double2(0.0, 0.0);
-    if (valid) {
-      const int tt = (t < K) ? t : N - 1 - t;
-      const double sg = (t < K) ? 1.0 : -1.0;
-      const double* rE = GT + ((size_t)tt * K + mE) * C + 2 * s;
-      g.x = rE[0];
-      g.y = rE[1];
-      if (tt < K - 1) {
-        const double* rO = GT + ((size_t)tt * K + mO) * C + 2 * s;
-        g.x += sg * rO[0];
-        g.y += sg * rO[1];
-        if (!SYM && t < K - 1) {
-          racc.x = fma(A.pole[t], rO[0], racc.x);
-          racc.y = fma(A.pole[t], rO[1], racc.y);
+  {
+    RingGather<K, TT> x;
+    x.load(GT, C, mE, s, lt);
+    // node r: even + odd order; node 2K-2-r (r < K-1): even - odd, the reflection's parity
+#pragma unroll
+    for (int i = 0; i < x.PER; ++i) {
+      const int r = lt + i * TT;
+      const double2 ge = valid ? x.ge[i] : make_double2(0.0, 0.0);
+      const double2 go = valid ? x.go[i] : make_double2(0.0, 0.0);
+      if (r < K - 1) {
+        buf[lds_pad(r)] = cadd(ge, go);
+        buf[lds_pad(N - 1 - r)] = csub(ge, go);
+        if (!SYM) {
+          racc.x = fma(A.pole[r], go.x, racc.x);
+          racc.y = fma(A.pole[r], go.y, racc.y);
         }
+      } else {
+        buf[lds_pad(r)] = ge;
       }
     }
-    buf[lds_pad(t)] = g;
   }
   if (!SYM) {
     const double2 prow = problem_sum(racc, TT, red_scratch);

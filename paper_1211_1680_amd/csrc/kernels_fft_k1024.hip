@@ -202,14 +202,17 @@ __global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const dou
   }
 }
 
-// Resampling from the symmetric grid to the MW nodes (see k_resample_2048).
-__global__ __launch_bounds__(TT, 4) void k_resample_1024(K1024Args A, const double* __restrict__ FS,
-                                                         double* __restrict__ FT, int C, int nprob) {
-  __shared__ double2 buf[NBUF];
+// Resampling from the symmetric grid to the MW nodes (see k_resample_2048; two problems per
+// 1024-thread block for 32-byte output pieces).
+__global__ __launch_bounds__(2 * TT) void k_resample_1024(K1024Args A, const double* __restrict__ FS,
+                                                          double* __restrict__ FT, int C, int nprob) {
+  __shared__ double2 bufs[2][NBUF];
   __shared__ double2 wlo[64], whi[64];
   stage_tw(A, wlo, whi);
-  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int lt = threadIdx.x;
+  double2* buf = bufs[threadIdx.x / TT];
+  const int p2 = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x % TT;
+  const int p = 2 * p2 + (int)(threadIdx.x / TT);
   const bool valid = p < nprob;
   const int ns = C / 2;
   const int mu = valid ? p / ns : 0;
@@ -254,20 +257,28 @@ __global__ __launch_bounds__(TT, 4) void k_resample_1024(K1024Args A, const doub
   }
   __syncthreads();
   dft_bluestein4096<true, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
-  if (valid) {
-    for (int t = lt; t < K; t += TT) {
-      const double2 h1 = buf[lds_pad(t)];
+  __syncthreads();
+  // thread T writes problem 2 p2 + (T & 1) at rings T / 2 + 512 i
+  const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
+  const int ph = 2 * p2 + h;
+  if (ph < nprob) {
+    const int muh = ph / ns, sh = ph % ns;
+    const double2* bh = bufs[h];
+#pragma unroll
+    for (int i = 0; i < K / TT; ++i) {
+      const int t = rr + i * TT;
+      const double2 h1 = bh[lds_pad(t)];
       double2 he, ho;
       if (t < K - 1) {
-        const double2 h2 = buf[lds_pad(N - 1 - t)];
+        const double2 h2 = bh[lds_pad(N - 1 - t)];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
       } else {
         he = cadd(h1, h1);
         ho = make_double2(0.0, 0.0);
       }
-      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mE) * C + 2 * s) = he;
-      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mO) * C + 2 * s) = ho;
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + 2 * muh) * C + 2 * sh) = he;
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + 2 * muh + 1) * C + 2 * sh) = ho;
     }
   }
 }
@@ -376,8 +387,8 @@ hipError_t launch_theta_1024_sym(const ShtTables& T, const Batch& b, const doubl
 
 hipError_t launch_resample_1024(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
   if (!T.sym || !fft_k1024_applies(T)) return hipErrorInvalidValue;
-  const int nprob = (K / 2) * (b.C / 2);
-  k_resample_1024<<<nprob, TT, 0, s>>>(k1024_args(T), FS, FT, b.C, nprob);
+  const int nprob = (K / 2) * (b.C / 2);   // even: K / 2 is
+  k_resample_1024<<<nprob / 2, 2 * TT, 0, s>>>(k1024_args(T), FS, FT, b.C, nprob);
   return hipGetLastError();
 }
 

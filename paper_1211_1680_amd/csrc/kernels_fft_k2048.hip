@@ -276,14 +276,18 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
 // share one complex sequence on the 2k-point circle (F(2 pi - psi) = (-1)^m F(psi)), a 4096-point
 // FFT gives the Fourier coefficients |j| <= k-1, and the 4095-point inverse DFT evaluates them at
 // theta_t = pi (2t+1) / n; the parities separate by the reflection t -> n-1-t.
-// Output FT[(t*k + m)*C + c], t < k.
-__global__ __launch_bounds__(TT, 4) void k_resample_2048(K2048Args A, const double* __restrict__ FS,
-                                                         double* __restrict__ FT, int C, int nprob) {
-  __shared__ double2 buf[NBUF];
+// Output FT[(t*k + m)*C + c], t < k.  Two problems (adjacent column pairs) per 1024-thread
+// block, so that the output rows are written in 32-byte pieces by neighbouring lanes (16-byte
+// pieces from separate blocks reach HBM as partial writes, about 2.8 times the bytes).
+__global__ __launch_bounds__(2 * TT) void k_resample_2048(K2048Args A, const double* __restrict__ FS,
+                                                          double* __restrict__ FT, int C, int nprob) {
+  __shared__ double2 bufs[2][NBUF];
   __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
-  const int p = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int lt = threadIdx.x;
+  double2* buf = bufs[threadIdx.x / TT];
+  const int p2 = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lt = threadIdx.x % TT;
+  const int p = 2 * p2 + (int)(threadIdx.x / TT);
   const bool valid = p < nprob;
   const int ns = C / 2;
   const int mu = valid ? p / ns : 0;
@@ -328,20 +332,28 @@ __global__ __launch_bounds__(TT, 4) void k_resample_2048(K2048Args A, const doub
   }
   __syncthreads();
   dft4095<true, TT>(buf, lt, w5lo, w5hi);
-  if (valid) {
-    for (int t = lt; t < K; t += TT) {
-      const double2 h1 = buf[lds_pad(t)];
+  __syncthreads();
+  // thread T writes problem 2 p2 + (T & 1) at rings T / 2 + 512 i
+  const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
+  const int ph = 2 * p2 + h;
+  if (ph < nprob) {
+    const int muh = ph / ns, sh = ph % ns;
+    const double2* bh = bufs[h];
+#pragma unroll
+    for (int i = 0; i < K / TT; ++i) {
+      const int t = rr + i * TT;
+      const double2 h1 = bh[lds_pad(t)];
       double2 he, ho;
       if (t < K - 1) {
-        const double2 h2 = buf[lds_pad(N - 1 - t)];
+        const double2 h2 = bh[lds_pad(N - 1 - t)];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
       } else {
         he = cadd(h1, h1);
         ho = make_double2(0.0, 0.0);
       }
-      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mE) * C + 2 * s) = he;
-      *reinterpret_cast<double2*>(FT + ((size_t)t * K + mO) * C + 2 * s) = ho;
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + 2 * muh) * C + 2 * sh) = he;
+      *reinterpret_cast<double2*>(FT + ((size_t)t * K + 2 * muh + 1) * C + 2 * sh) = ho;
     }
   }
 }
@@ -449,8 +461,8 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
 
 hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
   if (!T.sym || !k2048_ok(T)) return hipErrorInvalidValue;
-  const int nprob = (K / 2) * (b.C / 2);
-  k_resample_2048<<<nprob, TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
+  const int nprob = (K / 2) * (b.C / 2);   // even: K / 2 is
+  k_resample_2048<<<nprob / 2, 2 * TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
   return hipGetLastError();
 }
 

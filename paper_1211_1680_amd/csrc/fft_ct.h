@@ -17,6 +17,69 @@ constexpr int lds_padded(int n) { return n + (n >> 3) + 1; }
 // ring r < K of both orders, r = lt + i T.  Every gather is issued before the first one is
 // consumed, and each ring is read once for both of its nodes on the 2 pi extension (t = r and
 // t = 2K-2-r).
+// Ring t of one phi problem into LDS slots q < N: REAL packs map ma (real part) and map ma + 1
+// (imaginary part, zero without it); otherwise map ma is complex.  Every load is issued before
+// the first store.
+template <int N, int T, int REAL>
+__device__ __forceinline__ void load_ring(const double* __restrict__ f, long long map_stride, int ma, bool hasb,
+                                          int t, bool valid, double2* buf, int lt) {
+  constexpr int PER = (N + T - 1) / T;
+  double2 z[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int q = lt + i * T;
+    const size_t off = (size_t)t * N + (q < N ? q : 0);
+    if (REAL) {
+      z[i].x = f[(size_t)ma * map_stride + off];
+      z[i].y = hasb ? f[(size_t)(ma + 1) * map_stride + off] : 0.0;
+    } else {
+      z[i] = reinterpret_cast<const double2*>(f)[(size_t)ma * map_stride + off];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int q = lt + i * T;
+    if (q < N) buf[lds_pad(q)] = valid ? z[i] : make_double2(0.0, 0.0);
+  }
+}
+
+// Input of the inverse phi DFT of ring t (rows FT[(t*K + m)*C + c]): slot m < K takes order m,
+// slot N - m (0 < m < K) order -m.  REAL: the unit packs maps ma and ma + 1 as a + i b, with the
+// negative orders their conjugates; otherwise columns 4 ma .. 4 ma + 3 hold orders +m and -m of
+// map ma.  Each row is read once for both slots, and every load is issued before the first store.
+template <int K, int T, int REAL>
+__device__ __forceinline__ void load_orders(const double* __restrict__ FT, int C, int ma, bool hasb, int t,
+                                            bool valid, double2* buf, int lt) {
+  constexpr int N = 2 * K - 1;
+  constexpr int PER = K / T;
+  static_assert(K % T == 0, "orders per thread");
+  double2 ra[PER], rb[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const double* row = FT + ((size_t)t * K + lt + i * T) * C;
+    if (REAL) {
+      ra[i] = *reinterpret_cast<const double2*>(row + 2 * ma);
+      rb[i] = hasb ? *reinterpret_cast<const double2*>(row + 2 * ma + 2) : make_double2(0.0, 0.0);
+    } else {
+      ra[i] = *reinterpret_cast<const double2*>(row + 4 * ma);
+      rb[i] = *reinterpret_cast<const double2*>(row + 4 * ma + 2);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int m = lt + i * T;
+    const double2 a = valid ? ra[i] : make_double2(0.0, 0.0);
+    const double2 b = valid ? rb[i] : make_double2(0.0, 0.0);
+    if (REAL) {
+      buf[lds_pad(m)] = make_double2(a.x - b.y, a.y + b.x);
+      if (m > 0) buf[lds_pad(N - m)] = make_double2(a.x + b.y, b.x - a.y);
+    } else {
+      buf[lds_pad(m)] = a;
+      if (m > 0) buf[lds_pad(N - m)] = b;
+    }
+  }
+}
+
 template <int K, int T>
 struct RingGather {
   static constexpr int PER = K / T;

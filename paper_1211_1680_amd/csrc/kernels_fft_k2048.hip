@@ -60,18 +60,7 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const d
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  for (int q = lt; q < N; q += TT) {
-    double2 z = make_double2(0.0, 0.0);
-    if (valid) {
-      if (REAL) {
-        z.x = f[(size_t)ma * map_stride + (size_t)t * N + q];
-        z.y = hasb ? f[(size_t)(ma + 1) * map_stride + (size_t)t * N + q] : 0.0;
-      } else {
-        z = reinterpret_cast<const double2*>(f)[(size_t)ma * map_stride + (size_t)t * N + q];
-      }
-    }
-    buf[lds_pad(q)] = z;
-  }
+  load_ring<N, TT, REAL>(f, map_stride, ma, hasb, t, valid, buf, lt);
   __syncthreads();
   dft4095<false, TT>(buf, lt, w5lo, w5hi);
 
@@ -375,26 +364,7 @@ __global__ __launch_bounds__(TT, 4) void k_phi_inverse_2048(K2048Args A, const d
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  for (int q = lt; q < N; q += TT) {
-    double2 z = make_double2(0.0, 0.0);
-    if (valid) {
-      const bool neg = q >= K;
-      const int m = neg ? N - q : q;
-      const double* row = FT + ((size_t)t * K + m) * C;
-      if (REAL) {
-        double2 a = make_double2(row[2 * ma], row[2 * ma + 1]);
-        double2 b = hasb ? make_double2(row[2 * ma + 2], row[2 * ma + 3]) : make_double2(0.0, 0.0);
-        if (neg) {
-          a = conjd(a);
-          b = conjd(b);
-        }
-        z = make_double2(a.x - b.y, a.y + b.x);
-      } else {
-        z = neg ? make_double2(row[4 * ma + 2], row[4 * ma + 3]) : make_double2(row[4 * ma], row[4 * ma + 1]);
-      }
-    }
-    buf[lds_pad(q)] = z;
-  }
+  load_orders<K, TT, REAL>(FT, C, ma, hasb, t, valid, buf, lt);
   __syncthreads();
   dft4095<true, TT>(buf, lt, w5lo, w5hi);
 

@@ -94,18 +94,25 @@ __global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  for (int q = lt; q < n; q += A.T) {
-    double2 z = make_double2(0.0, 0.0);
-    if (valid) {
+  {
+    // every load of the ring is issued before the first store (VPT >= n / T)
+    double2 z[VPT];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int q = lt + i * A.T;
+      const size_t off = (size_t)t * n + (q < n ? q : 0);
       if (REAL) {
-        z.x = f[(size_t)ma * map_stride + (size_t)t * n + q];
-        z.y = hasb ? f[(size_t)(ma + 1) * map_stride + (size_t)t * n + q] : 0.0;
+        z[i].x = f[(size_t)ma * map_stride + off];
+        z[i].y = hasb ? f[(size_t)(ma + 1) * map_stride + off] : 0.0;
       } else {
-        const double2* fc = reinterpret_cast<const double2*>(f);
-        z = fc[(size_t)ma * map_stride + (size_t)t * n + q];
+        z[i] = reinterpret_cast<const double2*>(f)[(size_t)ma * map_stride + off];
       }
     }
-    buf[q] = z;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int q = lt + i * A.T;
+      if (q < n) buf[q] = valid ? z[i] : make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   dft_odd<false, VPT>(buf, A, lt);
@@ -171,25 +178,34 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
   // packed extension g_t = G_E(t) + G_O(t) (t < k);  G_E(n-1-t) - G_O(n-1-t) (t >= k), without
   // the odd pole value; racc accumulates the pole row sum_{t<k-1} c_t G_O(t)
   double2 racc = make_double2(0.0, 0.0);
-  for (int t = lt; t < n; t += A.T) {
-    double2 g = make_double2(0.0, 0.0);
-    if (valid) {
-      const int tt = (t < k) ? t : n - 1 - t;
-      const double sg = (t < k) ? 1.0 : -1.0;
-      const double* rE = GT + ((size_t)tt * k + mE) * C + 2 * s;
-      g.x = rE[0];
-      g.y = rE[1];
-      if (hasO && tt < k - 1) {
-        const double* rO = GT + ((size_t)tt * k + mO) * C + 2 * s;
-        g.x += sg * rO[0];
-        g.y += sg * rO[1];
-        if (t < k - 1) {
-          racc.x = fma(A.pole[t], rO[0], racc.x);
-          racc.y = fma(A.pole[t], rO[1], racc.y);
+  {
+    // each ring r < k is read once for nodes r and n-1-r, every load issued before the first
+    // store (VPT >= n / T > k / T)
+    double2 ge[VPT], go[VPT];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int r = lt + i * A.T;
+      const double* rE = GT + ((size_t)(r < k ? r : 0) * k + mE) * C + 2 * s;
+      ge[i] = *reinterpret_cast<const double2*>(rE);
+      go[i] = hasO ? *reinterpret_cast<const double2*>(rE + C) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int r = lt + i * A.T;
+      if (r < k) {
+        const double2 e = valid ? ge[i] : make_double2(0.0, 0.0);
+        if (valid && hasO && r < k - 1) {
+          const double2 o = go[i];
+          buf[r] = cadd(e, o);
+          buf[n - 1 - r] = csub(e, o);
+          racc.x = fma(A.pole[r], o.x, racc.x);
+          racc.y = fma(A.pole[r], o.y, racc.y);
+        } else {
+          buf[r] = e;
+          if (r < k - 1) buf[n - 1 - r] = e;
         }
       }
     }
-    buf[t] = g;
   }
   const double2 prow = problem_sum(racc, A.T, red_scratch);
   __syncthreads();
@@ -301,25 +317,37 @@ __global__ __launch_bounds__(512) void k_phi_inverse(FftArgs A, const double* __
   const bool hasb = REAL && (ma + 1 < nb);
 
   // spectrum Z_m at index m mod n
-  for (int q = lt; q < n; q += A.T) {
-    double2 z = make_double2(0.0, 0.0);
-    if (valid) {
-      const bool neg = q >= k;              // q = n - m  <->  m = -(n - q)
-      const int m = neg ? n - q : q;
-      const double* row = FT + ((size_t)t * k + m) * C;
+  // (slot n - m holds order -m; each row is read once for both signs, every load issued before
+  // the first store)
+  {
+    double2 ra[VPT], rb[VPT];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int m = lt + i * A.T;
+      const double* row = FT + ((size_t)t * k + (m < k ? m : 0)) * C;
       if (REAL) {
-        double2 a = make_double2(row[2 * ma], row[2 * ma + 1]);
-        double2 b = hasb ? make_double2(row[2 * ma + 2], row[2 * ma + 3]) : make_double2(0.0, 0.0);
-        if (neg) {
-          a = conjd(a);
-          b = conjd(b);
-        }
-        z = make_double2(a.x - b.y, a.y + b.x);   // a + i b
+        ra[i] = *reinterpret_cast<const double2*>(row + 2 * ma);
+        rb[i] = hasb ? *reinterpret_cast<const double2*>(row + 2 * ma + 2) : make_double2(0.0, 0.0);
       } else {
-        z = neg ? make_double2(row[4 * ma + 2], row[4 * ma + 3]) : make_double2(row[4 * ma], row[4 * ma + 1]);
+        ra[i] = *reinterpret_cast<const double2*>(row + 4 * ma);
+        rb[i] = *reinterpret_cast<const double2*>(row + 4 * ma + 2);
       }
     }
-    buf[q] = z;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int m = lt + i * A.T;
+      if (m < k) {
+        const double2 a = valid ? ra[i] : make_double2(0.0, 0.0);
+        const double2 b = valid ? rb[i] : make_double2(0.0, 0.0);
+        if (REAL) {
+          buf[m] = make_double2(a.x - b.y, a.y + b.x);   // a + i b
+          if (m > 0) buf[n - m] = make_double2(a.x + b.y, b.x - a.y);   // conj(a) + i conj(b)
+        } else {
+          buf[m] = a;
+          if (m > 0) buf[n - m] = b;
+        }
+      }
+    }
   }
   __syncthreads();
   dft_odd<true, VPT>(buf, A, lt);

@@ -31,6 +31,7 @@ struct WavTables {
   int J = 0;
   double* kappa = nullptr;  // [(J-J_min+1) * L]
   double* eta = nullptr;    // [L]
+  std::vector<int> lmin;    // per scale: the lowest degree where kappa is not zero
 };
 
 struct DevCache {
@@ -233,6 +234,14 @@ int ensure_wav(DevCache& dc, int L, int B, int J_min, int kernel, WavTables** ou
     const int ns = W.J - J_min + 1;
     std::vector<double> kappa((size_t)ns * L), eta(L);
     tiling_host_kernel(L, B, J_min, W.J, kernel, kappa.data(), eta.data());
+    // the wavelet kernels vanish below their support: coefficients there need no Legendre products
+    W.lmin.assign(ns, L);
+    for (int i = 0; i < ns; ++i)
+      for (int l = 0; l < L; ++l)
+        if (kappa[(size_t)i * L + l] != 0.0) {
+          W.lmin[i] = l;
+          break;
+        }
     if (hipMalloc((void**)&W.kappa, sizeof(double) * kappa.size()) != hipSuccess) return S2LET_ENOMEM;
     if (hipMalloc((void**)&W.eta, sizeof(double) * eta.size()) != hipSuccess) {
       hipFree(W.kappa);
@@ -258,8 +267,10 @@ double triples_of(int k) { return (double)k * (double)k * (double)(k + 1) / 2.0;
 // quadrature, Legendre analysis).  adjoint = true: the adjoint of the inverse transform,
 // g_lm = sum_{t,p} conj(Y_lm(theta_t, phi_p)) f(theta_t, phi_p): the phi DFT without its 2 pi/n
 // weight, no theta quadrature, the same Legendre analysis.
+// lmin > 0: the caller needs no degree below lmin, whose rows of R may then be left zero.
 int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const void* f,
-                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false) {
+                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false,
+                  int lmin = 0) {
   hipError_t e;
   const double k = T.k, n = T.n;
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
@@ -288,7 +299,7 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
   if (sym)
-    e = launch_legendre_forward_sym(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r), s);
+    e = launch_legendre_forward_sym(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, lmin, prof_counter(r), s);
   else
     e = launch_legendre_forward(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r), s);
   if (e != hipSuccess) return to_status(e);
@@ -300,8 +311,10 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
 // inverse phi DFT).  adjoint = true: the adjoint of the forward transform: Legendre synthesis,
 // the theta quadrature (a real symmetric operator per m, its own transpose), and the inverse phi
 // DFT times the phi weight 2 pi/n.
+// lmin > 0: the rows of S below degree lmin are zero.
 int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const double* S, void* f,
-                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false) {
+                  int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false,
+                  int lmin = 0) {
   hipError_t e;
   const double k = T.k, n = T.n;
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
@@ -316,7 +329,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
   if (sym)
-    e = launch_legendre_inverse_sym(T, G, b, S, w.HM, precision, prof_counter(r), s);
+    e = launch_legendre_inverse_sym(T, G, b, S, w.HM, precision, lmin, prof_counter(r), s);
   else
     e = launch_legendre_inverse(T, G, b, S, w.GT, precision, prof_counter(r), s);
   if (e != hipSuccess) return to_status(e);
@@ -571,7 +584,8 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
                     W->kappa + (size_t)(j - J_min) * L, 0, s);
       if (e != hipSuccess) return hip_fail(e);
       double* wout = (double*)f_wav + ((size_t)start * wsz + off) * cmul;
-      if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s, adjoint)) != S2LET_OK)
+      if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s, adjoint,
+                              W->lmin[j - J_min])) != S2LET_OK)
         return st;
       off += (int64_t)kj * (2 * kj - 1);
     }
@@ -627,7 +641,8 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
     for (int j = J_min; j <= J; ++j) {
       const int kj = bl_wav(j, L, B, multires, kernel);
       const double* win = (const double*)f_wav + ((size_t)start * wsz + off) * cmul;
-      if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s, adjoint)) != S2LET_OK)
+      if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s, adjoint,
+                              W->lmin[j - J_min])) != S2LET_OK)
         return st;
       e = tile_prof(dc.leg, b, w.R, kj, nparts_of(kj, b, precision, adjoint), w.S, L,
                     W->kappa + (size_t)(j - J_min) * L, 1, s);

@@ -123,16 +123,19 @@ hipError_t launch_phi_inverse_1024(const ShtTables& T, const Batch& b, const dou
 hipError_t launch_theta_1024_sym(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
 hipError_t launch_resample_1024(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
 int legendre_forward_groups_sym(int k);
+// lmin: the degrees below it take no products.  Forward: their rows of R are written as zero (the
+// caller needs none of them).  Inverse: their rows of S must be zero.  0 = every degree.
 hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
-                                       double* R, long long part_stride, int precision,
+                                       double* R, long long part_stride, int precision, int lmin,
                                        unsigned long long* counter, hipStream_t s);
 hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* S,
-                                       double* FS, int precision, unsigned long long* counter, hipStream_t s);
+                                       double* FS, int precision, int lmin, unsigned long long* counter,
+                                       hipStream_t s);
 hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
-                                            const double* HM, double* R, long long part_stride,
+                                            const double* HM, double* R, long long part_stride, int lmin,
                                             unsigned long long* counter, hipStream_t s);
 hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
-                                            const double* S, double* FS, unsigned long long* counter,
+                                            const double* S, double* FS, int lmin, unsigned long long* counter,
                                             hipStream_t s);
 hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
                                    int64_t map_stride, hipStream_t s);

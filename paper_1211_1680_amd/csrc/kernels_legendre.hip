@@ -432,7 +432,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
                                                           const double* __restrict__ ut,
                                                           const double* __restrict__ sx,
                                                           const double* __restrict__ st, int k, int Lt, int ng,
-                                                          unsigned long long* __restrict__ counter) {
+                                                          int lmin, unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
   constexpr int RS = 2 * ((C / 2) | 1);
   constexpr int ZBYTES = FWD_NW * FWD_LC * FWD_ZS * (int)sizeof(T);
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<T>::zero();
-      const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
+      const bool skip = !tile_live || l0 + FWD_LC <= lmin || __all(!valid || negligible(z1, z2, e));
       const double cf = cf_next;
       cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
       recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e,
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
                                                           const double* __restrict__ ut,
                                                           const double* __restrict__ sx,
                                                           const double* __restrict__ st, int k, int Lt, int ntb,
-                                                          unsigned long long* __restrict__ counter) {
+                                                          int lmin, unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
   constexpr bool F64 = sizeof(T) == sizeof(double);
   // the coefficient rows of a chunk, loaded once per block (the four waves share them) into a
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
     __syncthreads();
     int cur = 0;
     for (int l0 = m; l0 < k; l0 += INVM_LC) {
-      const bool skip = __all(!valid || negligible(z1, z2, e));
+      const bool skip = l0 + INVM_LC <= lmin || __all(!valid || negligible(z1, z2, e));
       // the next chunk's rows, in flight during this chunk's recursion and products
       const bool more = l0 + INVM_LC < k;
       if (more) {
@@ -701,51 +701,53 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
 int legendre_forward_groups_sym(int k) { return (k / 2 + FWD_TB - 1) / FWD_TB; }
 
 hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
-                                       double* R, long long part_stride, int precision,
+                                       double* R, long long part_stride, int precision, int lmin,
                                        unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   if (!T.sym || (k & 1)) return hipErrorInvalidValue;
-  if (precision == S2LET_MIXED_BF16X3) return launch_legendre_forward_bf16_sym(T, G, b, HM, R, part_stride, counter, s);
+  if (precision == S2LET_MIXED_BF16X3)
+    return launch_legendre_forward_bf16_sym(T, G, b, HM, R, part_stride, lmin, counter, s);
   const int ng = legendre_forward_groups_sym(k);
   const dim3 grid(((k + 1) / 2) * ng), block(FWD_NW * 64);
   const bool f32 = precision == S2LET_MIXED_FP32;
   if (b.C == 32 && f32)
     k_legendre_fwd_sym<32, float><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
-                                                         T.st_s, k, G.Lt, ng, counter);
+                                                         T.st_s, k, G.Lt, ng, lmin, counter);
   else if (b.C == 32)
     k_legendre_fwd_sym<32, double><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
-                                                          T.st_s, k, G.Lt, ng, counter);
+                                                          T.st_s, k, G.Lt, ng, lmin, counter);
   else if (b.C == 16 && f32)
     k_legendre_fwd_sym<16, float><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
-                                                         T.st_s, k, G.Lt, ng, counter);
+                                                         T.st_s, k, G.Lt, ng, lmin, counter);
   else if (b.C == 16)
     k_legendre_fwd_sym<16, double><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
-                                                          T.st_s, k, G.Lt, ng, counter);
+                                                          T.st_s, k, G.Lt, ng, lmin, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* S,
-                                       double* FS, int precision, unsigned long long* counter, hipStream_t s) {
+                                       double* FS, int precision, int lmin, unsigned long long* counter,
+                                       hipStream_t s) {
   const int k = T.k;
   if (!T.sym || (k & 1)) return hipErrorInvalidValue;
-  if (precision == S2LET_MIXED_BF16X3) return launch_legendre_inverse_bf16_sym(T, G, b, S, FS, counter, s);
+  if (precision == S2LET_MIXED_BF16X3) return launch_legendre_inverse_bf16_sym(T, G, b, S, FS, lmin, counter, s);
   const int ntb = (k / 2 + 255) / 256;
   const dim3 grid(((k + 1) / 2) * ntb), block(256);
   const bool f32 = precision == S2LET_MIXED_FP32;
   if (b.C == 32 && f32)
     k_legendre_inv_sym<32, float><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
-                                                         G.Lt, ntb, counter);
+                                                         G.Lt, ntb, lmin, counter);
   else if (b.C == 32)
     k_legendre_inv_sym<32, double><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
-                                                          G.Lt, ntb, counter);
+                                                          G.Lt, ntb, lmin, counter);
   else if (b.C == 16 && f32)
     k_legendre_inv_sym<16, float><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
-                                                         G.Lt, ntb, counter);
+                                                         G.Lt, ntb, lmin, counter);
   else if (b.C == 16)
     k_legendre_inv_sym<16, double><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
-                                                          G.Lt, ntb, counter);
+                                                          G.Lt, ntb, lmin, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

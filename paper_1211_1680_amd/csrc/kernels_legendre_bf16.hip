@@ -319,6 +319,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
                                                                const double* __restrict__ cm,
                                                                const double* __restrict__ ut,
                                                                const double* __restrict__ st, int k, int Lt, int ng,
+                                                               int lmin,
                                                                unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
   constexpr int RS = 2 * ((C / 2) | 1);
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[x][ct] = v4f{0.f, 0.f, 0.f, 0.f};
-      const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
+      const bool skip = !tile_live || l0 + FB_LC <= lmin || __all(!valid || negligible(z1, z2, e));
       const double cf = cf_next;
       cf_next = chunk_coef<FB_LC>(am, bm, l0 + FB_LC - m, k - m, lane);
       recur_chunk<FB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
@@ -451,7 +452,8 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
                                                                   const double* __restrict__ cm,
                                                                   const double* __restrict__ ut,
                                                                   const double* __restrict__ st, int k, int Lt,
-                                                                  int ntb, unsigned long long* __restrict__ counter) {
+                                                                  int ntb, int lmin,
+                                                                  unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
   __shared__ __align__(16) __bf16 Z[4][64][IBS_ZR];
   const int kh = k / 2;
@@ -502,7 +504,7 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
           bn[par][ct][q] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
         }
     for (int l0 = m; l0 < k; l0 += IBS_LC) {
-      const bool skip = __all(!valid || negligible(z1, z2, e));
+      const bool skip = l0 + IBS_LC <= lmin || __all(!valid || negligible(z1, z2, e));
       bf16x8 bh[2][CT], bl[2][CT];
 #pragma unroll
       for (int par = 0; par < 2; ++par)
@@ -615,7 +617,7 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
 }
 
 hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
-                                            const double* HM, double* R, long long part_stride,
+                                            const double* HM, double* R, long long part_stride, int lmin,
                                             unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   if (!T.sym || (k & 1)) return hipErrorInvalidValue;
@@ -623,17 +625,17 @@ hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables&
   const dim3 grid(((k + 1) / 2) * ng), block(FB_NW * 64);
   if (b.C == 32)
     k_legendre_fwd_bf16_sym<32><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s,
-                                                       k, G.Lt, ng, counter);
+                                                       k, G.Lt, ng, lmin, counter);
   else if (b.C == 16)
     k_legendre_fwd_bf16_sym<16><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s,
-                                                       k, G.Lt, ng, counter);
+                                                       k, G.Lt, ng, lmin, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
-                                            const double* S, double* FS, unsigned long long* counter,
+                                            const double* S, double* FS, int lmin, unsigned long long* counter,
                                             hipStream_t s) {
   const int k = T.k;
   if (!T.sym || (k & 1)) return hipErrorInvalidValue;
@@ -641,10 +643,10 @@ hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables&
   const dim3 grid(((k + 1) / 2) * ntb), block(256);
   if (b.C == 32)
     k_legendre_inv_bf16_sym<32><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt, ntb,
-                                                       counter);
+                                                       lmin, counter);
   else if (b.C == 16)
     k_legendre_inv_bf16_sym<16><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt, ntb,
-                                                       counter);
+                                                       lmin, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -38,6 +38,28 @@ struct FftArgs {
   int T, P, buf;             // threads per problem, problems per block, LDS values per problem
 };
 
+// The two-level twiddle tables (at most TWMAX entries each at the supported band-limits) copied
+// into LDS once per block: each FFT pass reads them after its LDS loads, and from global memory
+// that read put a memory latency into every pass.  The caller synchronises before the first pass.
+constexpr int TWMAX = 128;
+__device__ __forceinline__ FftArgs stage_twiddles(const FftArgs& A, double2 (*tw)[TWMAX]) {
+  FftArgs L = A;
+  const int nlo = 1 << A.loglo, nhi = (1 << A.logP) >> A.loglo, nnhi = (A.n + 63) / 64;
+  if (nlo <= TWMAX && nhi <= TWMAX && nnhi <= TWMAX) {
+    for (int i = threadIdx.x; i < TWMAX; i += blockDim.x) {
+      if (i < nlo) tw[0][i] = A.tw_lo[i];
+      if (i < nhi) tw[1][i] = A.tw_hi[i];
+      if (i < 64) tw[2][i] = A.twn_lo[i];
+      if (i < nnhi) tw[3][i] = A.twn_hi[i];
+    }
+    L.tw_lo = tw[0];
+    L.tw_hi = tw[1];
+    L.twn_lo = tw[2];
+    L.twn_hi = tw[3];
+  }
+  return L;
+}
+
 // In-place DFT of length n of buf[0..n) (natural order in and out), sign -1 or +1 (INV).
 template <bool INV, int VPT>
 __device__ void dft_odd(double2* buf, const FftArgs& A, int lt) {
@@ -58,18 +80,30 @@ __device__ void dft_odd(double2* buf, const FftArgs& A, int lt) {
     return;
   }
   // Bluestein: X_j = c_j sum_q (x_q c_q) conj(c_{j-q}) with c_q = exp(-+ i pi q^2 / n)
-  for (int q = lt; q < A.M; q += A.T) {
-    double2 v = make_double2(0.0, 0.0);
-    if (q < A.n) v = cmul(buf[q], INV ? conjd(A.chirp[q]) : A.chirp[q]);
-    buf[q] = v;
+  // (the table loops are unrolled over VPT, T VPT >= M, so that their loads issue together)
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int q = lt + i * A.T;
+    if (q < A.M) {
+      double2 v = make_double2(0.0, 0.0);
+      if (q < A.n) v = cmul(buf[q], INV ? conjd(A.chirp[q]) : A.chirp[q]);
+      buf[q] = v;
+    }
   }
   __syncthreads();
   fft_pow2<false, VPT>(buf, A.M, A.logM, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logM);
-  for (int q = lt; q < A.M; q += A.T)
-    buf[q] = cmul(buf[q], INV ? conjd(A.bhat[(A.M - q) & (A.M - 1)]) : A.bhat[q]);
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int q = lt + i * A.T;
+    if (q < A.M) buf[q] = cmul(buf[q], INV ? conjd(A.bhat[(A.M - q) & (A.M - 1)]) : A.bhat[q]);
+  }
   __syncthreads();
   fft_pow2<true, VPT>(buf, A.M, A.logM, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logM);
-  for (int q = lt; q < A.n; q += A.T) buf[q] = cmul(buf[q], INV ? conjd(A.chirp[q]) : A.chirp[q]);
+#pragma unroll
+  for (int i = 0; i < VPT; ++i) {
+    const int q = lt + i * A.T;
+    if (q < A.n) buf[q] = cmul(buf[q], INV ? conjd(A.chirp[q]) : A.chirp[q]);
+  }
   __syncthreads();
 }
 
@@ -78,10 +112,12 @@ __device__ void dft_odd(double2* buf, const FftArgs& A, int lt) {
 // Output GT[(t*k + m)*C + c] for m < k.
 // ------------------------------------------------------------------------------------------
 template <int REAL, int VPT>
-__global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __restrict__ f,
+__global__ __launch_bounds__(512) void k_phi_forward(FftArgs Ain, const double* __restrict__ f,
                                                      long long map_stride, double* __restrict__ GT,
                                                      int C, int nb, int used, int nprob) {
   extern __shared__ double2 smem[];
+  __shared__ double2 s_tw[4][TWMAX];
+  const FftArgs A = stage_twiddles(Ain, s_tw);
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
   const int pl = threadIdx.x / A.T, lt = threadIdx.x % A.T;
   const int p = blk * A.P + pl;
@@ -159,9 +195,11 @@ __global__ __launch_bounds__(512) void k_phi_forward(FftArgs A, const double* __
 // for the adjoint transform, which applies the same operator.
 // ------------------------------------------------------------------------------------------
 template <int VPT>
-__global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restrict__ GT,
+__global__ __launch_bounds__(512) void k_theta(FftArgs Ain, const double* __restrict__ GT,
                                                double* __restrict__ HM, int C, int nprob) {
   extern __shared__ double2 smem[];
+  __shared__ double2 s_tw[4][TWMAX];
+  const FftArgs A = stage_twiddles(Ain, s_tw);
   __shared__ double2 red_scratch[8];
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
   const int pl = threadIdx.x / A.T, lt = threadIdx.x % A.T;
@@ -240,7 +278,11 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
     __syncthreads();
     fft_pow2<false, VPT>(buf, Nc, A.logNc, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logNc);
     const double2* kh = P == 0 ? A.khat0 : A.khat1;
-    for (int q = lt; q < Nc; q += A.T) buf[q] = cmul(buf[q], kh[q]);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int q = lt + i * A.T;
+      if (q < Nc) buf[q] = cmul(buf[q], kh[q]);
+    }
     __syncthreads();
     fft_pow2<true, VPT>(buf, Nc, A.logNc, lt, A.T, A.tw_lo, A.tw_hi, A.loglo, A.logP - A.logNc);
 #pragma unroll
@@ -300,10 +342,12 @@ __global__ __launch_bounds__(512) void k_theta(FftArgs A, const double* __restri
 // phi stage, inverse.  Problem = (ring t, map pair) / (ring t, map).  Input FT[(t*k + m)*C + c].
 // ------------------------------------------------------------------------------------------
 template <int REAL, int VPT>
-__global__ __launch_bounds__(512) void k_phi_inverse(FftArgs A, const double* __restrict__ FT,
+__global__ __launch_bounds__(512) void k_phi_inverse(FftArgs Ain, const double* __restrict__ FT,
                                                      double* __restrict__ f, long long map_stride,
                                                      int C, int nb, int nprob) {
   extern __shared__ double2 smem[];
+  __shared__ double2 s_tw[4][TWMAX];
+  const FftArgs A = stage_twiddles(Ain, s_tw);
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
   const int pl = threadIdx.x / A.T, lt = threadIdx.x % A.T;
   const int p = blk * A.P + pl;

@@ -36,10 +36,10 @@ PEAK_HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {
     # the Legendre kernels' sources; the counters are reported only while these files are unchanged
     "sources": ["paper_1211_1680_amd/csrc/kernels_legendre.hip", "paper_1211_1680_amd/csrc/legendre_rec.h"],
-    "sha256": "abe0ae3ee3e8d6af3a46a725920e5cb5bdbfc2ac89d064947c79e071ee7c1b65",
+    "sha256": "a1ca3a7d28dd8be8ede04963f4d148a534262476b61d2ccc0a2a6d0ac33071d3",
     # k = 2048 launches of k_legendre_fwd_sym<32, double> / k_legendre_inv_sym<32, double>:
     # FETCH_SIZE + WRITE_SIZE, copy-calibrated (profiles/wavelet_L2048_16maps_fp64_hbm_traffic.txt)
-    "bytes_per_launch": {"legendre_analysis": 2.3618e9, "legendre_synthesis": 1.8697e9},
+    "bytes_per_launch": {"legendre_analysis": 2.3570e9, "legendre_synthesis": 1.8613e9},
 }
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libs2let_mi355x.so")
-SOURCES = ["kernels_fft.hip", "kernels_fft_k2048.hip", "kernels_fft_k1024.hip", "kernels_legendre.hip", "kernels_legendre_bf16.hip", "kernels_tile.hip",
+SOURCES = ["kernels_fft.hip", "kernels_fft_k2048.hip", "kernels_fft_bluestein.hip", "kernels_legendre.hip", "kernels_legendre_bf16.hip", "kernels_tile.hip",
            "plan.cpp", "abi.cpp", "batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

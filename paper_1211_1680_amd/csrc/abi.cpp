@@ -186,10 +186,10 @@ Workspace carve(void* ws, int L, int C, bool wavelet) {
 }
 
 // partial-sum layout of the forward Legendre step at band-limit k
-// The forward and inverse transforms at the band-limits with compiled transforms (1024, 2048) run
+// The forward and inverse transforms at the band-limits with compiled transforms (512, 1024, 2048) run
 // their Legendre steps on the symmetric grid (see launch_theta_2048 / launch_resample_2048).
 bool sym_path(int k, const Batch& b, int precision, bool adjoint) {
-  return (k == 2048 || k == 1024) && !adjoint && b.C >= 16;
+  return (k == 2048 || k == 1024 || k == 512) && !adjoint && b.C >= 16;
 }
 int nparts_of(int k, const Batch& b, int precision, bool adjoint) {
   return sym_path(k, b, precision, adjoint) ? legendre_forward_groups_sym(k) : legendre_forward_groups(k);
@@ -285,7 +285,7 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   if (adjoint)
     e = launch_transpose_rows(b, T.k, w.GT, w.HM, n / (2.0 * M_PI), s);
   else if (sym)
-    e = T.k == 2048 ? launch_theta_2048(T, b, w.GT, w.HM, s, true) : launch_theta_1024_sym(T, b, w.GT, w.HM, s);
+    e = T.k == 2048 ? launch_theta_2048(T, b, w.GT, w.HM, s, true) : launch_theta_sym_bs(T, b, w.GT, w.HM, s);
   else
     e = launch_theta(T, b, w.GT, w.HM, s);
   if (e != hipSuccess) return to_status(e);
@@ -338,7 +338,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     // symmetric grid -> MW nodes
     r = prof_begin(ST_RESAMPLE, s, T.k);
     if (r) r->bytes = 2.0 * colb;
-    e = T.k == 2048 ? launch_resample_2048(T, b, w.HM, w.GT, s) : launch_resample_1024(T, b, w.HM, w.GT, s);
+    e = T.k == 2048 ? launch_resample_2048(T, b, w.HM, w.GT, s) : launch_resample_bs(T, b, w.HM, w.GT, s);
     if (e != hipSuccess) return to_status(e);
     prof_end(r, s);
   }

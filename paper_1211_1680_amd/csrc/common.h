@@ -115,13 +115,15 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
 // the northern nodes (the synthesis writes FS[m][s][c], s < k), and the resampling FS -> FT[t][m][c].
 hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
 // The same stages compiled for band-limit 1024 (n = 2047 by Bluestein over 4096 points).
-bool fft_k1024_applies(const ShtTables& T);
-hipError_t launch_phi_forward_1024(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
-                                   double* GT, hipStream_t s);
-hipError_t launch_phi_inverse_1024(const ShtTables& T, const Batch& b, const double* FT, void* f,
-                                   int64_t map_stride, hipStream_t s);
-hipError_t launch_theta_1024_sym(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
-hipError_t launch_resample_1024(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
+// band-limits 512 and 1024 (kernels_fft_bluestein.hip): compiled phi, symmetric-grid theta and
+// resampling kernels; fft_bs_applies says whether T is one of them
+bool fft_bs_applies(const ShtTables& T);
+hipError_t launch_phi_forward_bs(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                 double* GT, hipStream_t s);
+hipError_t launch_phi_inverse_bs(const ShtTables& T, const Batch& b, const double* FT, void* f,
+                                 int64_t map_stride, hipStream_t s);
+hipError_t launch_theta_sym_bs(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
+hipError_t launch_resample_bs(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
 int legendre_forward_groups_sym(int k);
 // lmin: the degrees below it take no products.  Forward: their rows of R are written as zero (the
 // caller needs none of them).  Inverse: their rows of S must be zero.  0 = every degree.

@@ -167,32 +167,55 @@ __device__ __forceinline__ void fft4096(double2* buf, int lt, const double2* wlo
 }
 
 // 2048 = 8^3 * 4, with the twiddle tables of length 4096 (unnormalised, sign -1 or +1 with INV)
-template <bool INV, int T>
+template <bool INV, int T, int TS = 2>
 __device__ __forceinline__ void fft2048(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  ct_pass<2048, 8, 1, INV, T, 2>(buf, lt, wlo, whi);
-  ct_pass<2048, 8, 8, INV, T, 2>(buf, lt, wlo, whi);
-  ct_pass<2048, 8, 64, INV, T, 2>(buf, lt, wlo, whi);
-  ct_pass<2048, 4, 512, INV, T, 2>(buf, lt, wlo, whi);
+  ct_pass<2048, 8, 1, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<2048, 8, 8, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<2048, 8, 64, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<2048, 4, 512, INV, T, TS>(buf, lt, wlo, whi);
 }
 
-// Bluestein DFT of length n <= 2048 (here 2047) in buf[0..n), natural order in and out, over the
-// 4096-point FFT: X_j = c_j sum_q (x_q c_q) conj(c_{j-q}), c_q = exp(-+ i pi q^2 / n); bhat is the
-// FFT of conj(c) wrapped to 4096, divided by 4096.  Ends with a barrier.
-template <bool INV, int T>
-__device__ __forceinline__ void dft_bluestein4096(double2* buf, int n, int lt, const double2* wlo,
-                                                  const double2* whi, const double2* __restrict__ chirp,
-                                                  const double2* __restrict__ bhat) {
-  for (int q = lt; q < 4096; q += T) {
+// 1024 points (8 * 8 * 4 * 4) from the tables of W_{1024 TS}
+template <bool INV, int T, int TS>
+__device__ __forceinline__ void fft1024(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  ct_pass<1024, 8, 1, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<1024, 8, 8, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<1024, 4, 64, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<1024, 4, 256, INV, T, TS>(buf, lt, wlo, whi);
+}
+
+// The compiled power-of-two FFT of length NL from the tables of W_{NL TS}.
+template <int NL, bool INV, int T, int TS>
+__device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  if constexpr (NL == 4096) {
+    static_assert(TS == 1, "the 4096-point plan reads W_4096 directly");
+    fft4096<INV, T>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 2048) {
+    fft2048<INV, T, TS>(buf, lt, wlo, whi);
+  } else {
+    static_assert(NL == 1024, "compiled lengths: 1024, 2048, 4096");
+    fft1024<INV, T, TS>(buf, lt, wlo, whi);
+  }
+}
+
+// Bluestein DFT of length n < NL / 2 in buf[0..n), natural order in and out, over the NL-point
+// FFT (tables of W_NL): X_j = c_j sum_q (x_q c_q) conj(c_{j-q}), c_q = exp(-+ i pi q^2 / n); bhat is
+// the FFT of conj(c) wrapped to NL, divided by NL.  Ends with a barrier.
+template <int NL, bool INV, int T>
+__device__ __forceinline__ void dft_bluestein(double2* buf, int n, int lt, const double2* wlo,
+                                              const double2* whi, const double2* __restrict__ chirp,
+                                              const double2* __restrict__ bhat) {
+  for (int q = lt; q < NL; q += T) {
     double2 v = make_double2(0.0, 0.0);
     if (q < n) v = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
     buf[lds_pad(q)] = v;
   }
   __syncthreads();
-  fft4096<false, T>(buf, lt, wlo, whi);
-  for (int q = lt; q < 4096; q += T)
-    buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(bhat[(4096 - q) & 4095]) : bhat[q]);
+  fft_ct<NL, false, T, 1>(buf, lt, wlo, whi);
+  for (int q = lt; q < NL; q += T)
+    buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(bhat[(NL - q) & (NL - 1)]) : bhat[q]);
   __syncthreads();
-  fft4096<true, T>(buf, lt, wlo, whi);
+  fft_ct<NL, true, T, 1>(buf, lt, wlo, whi);
   for (int q = lt; q < n; q += T) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
   __syncthreads();
 }

@@ -480,7 +480,7 @@ static hipError_t phi_fwd_v(const FftArgs& A, const void* f, int64_t map_stride,
 hipError_t launch_phi_forward(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
                               double* GT, hipStream_t s) {
   if (fft_k2048_applies(T)) return launch_phi_forward_2048(T, b, f, map_stride, GT, s);
-  if (fft_k1024_applies(T)) return launch_phi_forward_1024(T, b, f, map_stride, GT, s);
+  if (fft_bs_applies(T)) return launch_phi_forward_bs(T, b, f, map_stride, GT, s);
   const FftArgs A = fft_args(T, false);
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = T.k * nunits;
@@ -522,7 +522,7 @@ static hipError_t phi_inv_v(const FftArgs& A, const double* FT, void* f, int64_t
 hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
                               int64_t map_stride, hipStream_t s) {
   if (fft_k2048_applies(T)) return launch_phi_inverse_2048(T, b, FT, f, map_stride, s);
-  if (fft_k1024_applies(T)) return launch_phi_inverse_1024(T, b, FT, f, map_stride, s);
+  if (fft_bs_applies(T)) return launch_phi_inverse_bs(T, b, FT, f, map_stride, s);
   const FftArgs A = fft_args(T, false);
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = T.k * nunits;

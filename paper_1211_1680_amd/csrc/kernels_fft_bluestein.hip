@@ -1,11 +1,12 @@
-// The O(k^2 log k) stages of the MW transform at band-limit k = 1024, compiled for that size:
-// n = 2k - 1 = 2047 = 23 * 89 has no small radices, so the odd-length DFT is Bluestein's chirp
-// transform over the 4096-point FFT; the correlation of the theta stage and the symmetric grid
-// psi_s = pi (2s+1) / 2048 use the 2048-point FFT.  Same arithmetic as the general kernels
-// (kernels_fft.hip) and as the band-limit 2048 kernels (kernels_fft_k2048.hip): phi DFT (Sect. 2.1,
-// MW sampling), theta stage evaluated on the symmetric grid (its last transform), resampling
-// from the symmetric grid to the MW nodes, inverse phi DFT.  One problem per 512-thread block,
-// about 78 KiB of LDS, so two blocks share a CU.
+// The O(k^2 log k) stages of the MW transform at the band-limits k = 512 and 1024, compiled for
+// those sizes.  n = 2k - 1 (1023 = 3 * 11 * 31, 2047 = 23 * 89) has a prime factor beyond the
+// compiled radices, so the odd-length DFT is Bluestein's chirp transform over the 4k-point FFT; the
+// correlation of the theta stage and the symmetric grid psi_s = pi (2s+1) / (2k) use the 2k-point
+// FFT.  Same arithmetic as the general kernels (kernels_fft.hip) and as the band-limit 2048 kernels
+// (kernels_fft_k2048.hip): phi DFT (Sect. 2.1, MW sampling), theta stage evaluated on the
+// symmetric grid (its last transform), resampling from the symmetric grid to the MW nodes, inverse
+// phi DFT.  One problem per block of BsCfg<k>::TT threads (two for the resampling); 37 KiB (k = 512)
+// or 74 KiB (k = 1024) of LDS per problem.
 #include "common.h"
 #include "fft_ct.h"
 #include "../../include/s2let_mi355x.h"
@@ -13,18 +14,23 @@
 namespace s2let {
 
 namespace {
-constexpr int K = 1024;
-constexpr int N = 2 * K - 1;    // 2047
-constexpr int NB = 4096;        // Bluestein length
-constexpr int NC = 2048;        // correlation length and symmetric-grid circle (2k points)
-constexpr int TT = 512;
-constexpr int NBUF = lds_padded(NB);
+// per band-limit: threads per problem and log2 of the twiddle table length 4k
+template <int K_> struct BsCfg;
+template <> struct BsCfg<1024> { static constexpr int TT = 512, LOGP = 12; };
+template <> struct BsCfg<512> { static constexpr int TT = 256, LOGP = 11; };
 
-struct K1024Args {
-  const double2* tw_lo;    // W_4096^p, p < 64
-  const double2* tw_hi;    // W_4096^(64 q), q < 64
+#define S2LET_BS_CONSTANTS                                                          \
+  constexpr int N = 2 * K - 1;          /* odd ring length */                        \
+  constexpr int NB = 4 * K;             /* Bluestein length and twiddle tables */    \
+  constexpr int NC = 2 * K;             /* correlation length and psi circle */      \
+  constexpr int TT = BsCfg<K>::TT;                                                  \
+  constexpr int NBUF = lds_padded(NB);
+
+struct BsArgs {
+  const double2* tw_lo;    // W_4k^p, p < 64
+  const double2* tw_hi;    // W_4k^(64 q), q < 4k / 64
   const double2* chirp;    // exp(-i pi q^2 / n), q < n
-  const double2* bhat;     // FFT_4096 of conj(chirp), wrapped, / 4096
+  const double2* bhat;     // FFT_4k of conj(chirp), wrapped, / 4k
   const double2* khat0;
   const double2* khat1;
   const double2* hphase;
@@ -33,22 +39,24 @@ struct K1024Args {
   const double2* rsph;
 };
 
-__device__ __forceinline__ void stage_tw(const K1024Args& A, double2* wlo, double2* whi) {
+template <int NB>
+__device__ __forceinline__ void stage_tw(const BsArgs& A, double2* wlo, double2* whi) {
   if (threadIdx.x < 64) {
     wlo[threadIdx.x] = A.tw_lo[threadIdx.x];
-    whi[threadIdx.x] = A.tw_hi[threadIdx.x];
+    if (threadIdx.x < NB / 64) whi[threadIdx.x] = A.tw_hi[threadIdx.x];
   }
 }
 }  // namespace
 
 // phi stage, forward (see k_phi_forward): GT[(t*k + m)*C + c] for m < k.
-template <int REAL>
-__global__ __launch_bounds__(TT, 4) void k_phi_forward_1024(K1024Args A, const double* __restrict__ f,
-                                                            long long map_stride, double* __restrict__ GT,
-                                                            int C, int nb, int used, int nprob) {
+template <int K, int REAL>
+__global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_phi_forward_bs(BsArgs A, const double* __restrict__ f,
+                                                                    long long map_stride, double* __restrict__ GT,
+                                                                    int C, int nb, int used, int nprob) {
+  S2LET_BS_CONSTANTS
   __shared__ double2 buf[NBUF];
   __shared__ double2 wlo[64], whi[64];
-  stage_tw(A, wlo, whi);
+  stage_tw<NB>(A, wlo, whi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
   const bool valid = p < nprob;
@@ -59,7 +67,7 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_1024(K1024Args A, const d
   const bool hasb = REAL && (ma + 1 < nb);
   load_ring<N, TT, REAL>(f, map_stride, ma, hasb, t, valid, buf, lt);
   __syncthreads();
-  dft_bluestein4096<false, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  dft_bluestein<NB, false, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
   const double wphi = 2.0 * M_PI / (double)N;
   if (valid) {
     for (int m = lt; m < K; m += TT) {
@@ -87,11 +95,13 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_1024(K1024Args A, const d
 
 // theta stage on the symmetric grid (see k_theta_2048<true>): GT[(t*k + m)*C + c] -> HM, column-pair
 // major, entry s < k/2 the north/south sums, entry k/2 + s the differences.
-__global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const double* __restrict__ GT,
-                                                          double* __restrict__ HM, int C, int nprob) {
+template <int K>
+__global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_theta_sym_bs(BsArgs A, const double* __restrict__ GT,
+                                                                  double* __restrict__ HM, int C, int nprob) {
+  S2LET_BS_CONSTANTS
   __shared__ double2 buf[NBUF];
   __shared__ double2 wlo[64], whi[64];
-  stage_tw(A, wlo, whi);
+  stage_tw<NB>(A, wlo, whi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
   const bool valid = p < nprob;
@@ -118,8 +128,8 @@ __global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const dou
     }
   }
   __syncthreads();
-  dft_bluestein4096<false, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
-  constexpr int MAXV = NB / TT;   // 8 >= ceil((2K-1) / TT)
+  dft_bluestein<NB, false, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  constexpr int MAXV = NB / TT;   // >= ceil((2K-1) / TT)
   constexpr int NJ = 2 * K - 1;
   double2 keep[MAXV];
 #pragma unroll
@@ -144,11 +154,11 @@ __global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const dou
       }
     }
     __syncthreads();
-    fft2048<false, TT>(buf, lt, wlo, whi);
+    fft_ct<NC, false, TT, 2>(buf, lt, wlo, whi);
     const double2* kh = P == 0 ? A.khat0 : A.khat1;
     for (int q = lt; q < NC; q += TT) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
     __syncthreads();
-    fft2048<true, TT>(buf, lt, wlo, whi);
+    fft_ct<NC, true, TT, 2>(buf, lt, wlo, whi);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
@@ -159,7 +169,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const dou
     }
   }
   __syncthreads();
-  // I(j') at j' mod 2048 (slot 1024 stays empty), FFT onto the psi grid
+  // I(j') at j' mod 2k (slot k stays empty), FFT onto the psi grid
   if (lt == 0) buf[lds_pad(K)] = make_double2(0.0, 0.0);
 #pragma unroll
   for (int i = 0; i < MAXV; ++i) {
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const dou
     if (idx < NJ) buf[lds_pad((idx - (K - 1)) & (NC - 1))] = keep[i];
   }
   __syncthreads();
-  fft2048<false, TT>(buf, lt, wlo, whi);
+  fft_ct<NC, false, TT, 2>(buf, lt, wlo, whi);
   if (valid) {
     const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
     const double2 pO = make_double2(rP[0], rP[1]);
@@ -192,12 +202,14 @@ __global__ __launch_bounds__(TT, 4) void k_theta_1024_sym(K1024Args A, const dou
 }
 
 // Resampling from the symmetric grid to the MW nodes (see k_resample_2048; two problems per
-// 1024-thread block for 32-byte output pieces).
-__global__ __launch_bounds__(2 * TT) void k_resample_1024(K1024Args A, const double* __restrict__ FS,
-                                                          double* __restrict__ FT, int C, int nprob) {
+// block, for 32-byte output pieces).
+template <int K>
+__global__ __launch_bounds__(2 * BsCfg<K>::TT) void k_resample_bs(BsArgs A, const double* __restrict__ FS,
+                                                                  double* __restrict__ FT, int C, int nprob) {
+  S2LET_BS_CONSTANTS
   __shared__ double2 bufs[2][NBUF];
   __shared__ double2 wlo[64], whi[64];
-  stage_tw(A, wlo, whi);
+  stage_tw<NB>(A, wlo, whi);
   double2* buf = bufs[threadIdx.x / TT];
   const int p2 = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x % TT;
@@ -207,7 +219,7 @@ __global__ __launch_bounds__(2 * TT) void k_resample_1024(K1024Args A, const dou
   const int mu = valid ? p / ns : 0;
   const int s = valid ? p % ns : 0;
   const int mE = 2 * mu, mO = 2 * mu + 1;
-  constexpr int NL = K / TT;   // 2
+  constexpr int NL = K / TT;
   double2 fe[NL], fo[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
@@ -226,8 +238,8 @@ __global__ __launch_bounds__(2 * TT) void k_resample_1024(K1024Args A, const dou
     buf[lds_pad(NC - 1 - q)] = csub(fe[i], fo[i]);
   }
   __syncthreads();
-  fft2048<false, TT>(buf, lt, wlo, whi);
-  constexpr int MAXV = NC / TT;   // 4 >= ceil((2K-1) / TT)
+  fft_ct<NC, false, TT, 2>(buf, lt, wlo, whi);
+  constexpr int MAXV = NC / TT;   // >= ceil((2K-1) / TT)
   constexpr int NJ = 2 * K - 1;
   double2 keep[MAXV];
 #pragma unroll
@@ -245,9 +257,9 @@ __global__ __launch_bounds__(2 * TT) void k_resample_1024(K1024Args A, const dou
     }
   }
   __syncthreads();
-  dft_bluestein4096<true, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  dft_bluestein<NB, true, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
   __syncthreads();
-  // thread T writes problem 2 p2 + (T & 1) at rings T / 2 + 512 i
+  // thread T writes problem 2 p2 + (T & 1) at rings T / 2 + TT i
   const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
   const int ph = 2 * p2 + h;
   if (ph < nprob) {
@@ -273,13 +285,14 @@ __global__ __launch_bounds__(2 * TT) void k_resample_1024(K1024Args A, const dou
 }
 
 // phi stage, inverse (see k_phi_inverse): FT[(t*k + m)*C + c] -> maps.
-template <int REAL>
-__global__ __launch_bounds__(TT, 4) void k_phi_inverse_1024(K1024Args A, const double* __restrict__ FT,
-                                                            double* __restrict__ f, long long map_stride, int C,
-                                                            int nb, int nprob) {
+template <int K, int REAL>
+__global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_phi_inverse_bs(BsArgs A, const double* __restrict__ FT,
+                                                                    double* __restrict__ f, long long map_stride,
+                                                                    int C, int nb, int nprob) {
+  S2LET_BS_CONSTANTS
   __shared__ double2 buf[NBUF];
   __shared__ double2 wlo[64], whi[64];
-  stage_tw(A, wlo, whi);
+  stage_tw<NB>(A, wlo, whi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
   const bool valid = p < nprob;
@@ -290,7 +303,7 @@ __global__ __launch_bounds__(TT, 4) void k_phi_inverse_1024(K1024Args A, const d
   const bool hasb = REAL && (ma + 1 < nb);
   load_orders<K, TT, REAL>(FT, C, ma, hasb, t, valid, buf, lt);
   __syncthreads();
-  dft_bluestein4096<true, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
+  dft_bluestein<NB, true, TT>(buf, N, lt, wlo, whi, A.chirp, A.bhat);
   if (valid) {
     for (int q = lt; q < N; q += TT) {
       const double2 v = buf[lds_pad(q)];
@@ -305,12 +318,16 @@ __global__ __launch_bounds__(TT, 4) void k_phi_inverse_1024(K1024Args A, const d
 }
 
 // ------------------------------------------------------------------------------------------
-bool fft_k1024_applies(const ShtTables& T) {
-  return T.k == K && T.n == N && T.nrad == 0 && T.M == NB && T.Nc == NC && T.logP == 12 && T.loglo == 6;
+template <int K>
+static bool bs_tables_match(const ShtTables& T) {
+  return T.k == K && T.n == 2 * K - 1 && T.nrad == 0 && T.M == 4 * K && T.Nc == 2 * K &&
+         T.logP == BsCfg<K>::LOGP && T.loglo == 6;
 }
 
-static K1024Args k1024_args(const ShtTables& T) {
-  K1024Args a;
+bool fft_bs_applies(const ShtTables& T) { return bs_tables_match<1024>(T) || bs_tables_match<512>(T); }
+
+static BsArgs bs_args(const ShtTables& T) {
+  BsArgs a;
   a.tw_lo = T.tw_lo;
   a.tw_hi = T.tw_hi;
   a.chirp = T.chirp;
@@ -324,41 +341,69 @@ static K1024Args k1024_args(const ShtTables& T) {
   return a;
 }
 
-hipError_t launch_phi_forward_1024(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
-                                   double* GT, hipStream_t s) {
+template <int K>
+static hipError_t phi_forward_k(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride, double* GT,
+                                hipStream_t s) {
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = K * nunits;
-  const K1024Args a = k1024_args(T);
+  const BsArgs a = bs_args(T);
   if (b.reality == S2LET_REAL)
-    k_phi_forward_1024<1><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_bs<K, 1><<<nprob, BsCfg<K>::TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used,
+                                                          nprob);
   else
-    k_phi_forward_1024<0><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_bs<K, 0><<<nprob, BsCfg<K>::TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used,
+                                                          nprob);
   return hipGetLastError();
 }
 
-hipError_t launch_phi_inverse_1024(const ShtTables& T, const Batch& b, const double* FT, void* f,
-                                   int64_t map_stride, hipStream_t s) {
+template <int K>
+static hipError_t phi_inverse_k(const ShtTables& T, const Batch& b, const double* FT, void* f, int64_t map_stride,
+                                hipStream_t s) {
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = K * nunits;
-  const K1024Args a = k1024_args(T);
+  const BsArgs a = bs_args(T);
   if (b.reality == S2LET_REAL)
-    k_phi_inverse_1024<1><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+    k_phi_inverse_bs<K, 1><<<nprob, BsCfg<K>::TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
   else
-    k_phi_inverse_1024<0><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+    k_phi_inverse_bs<K, 0><<<nprob, BsCfg<K>::TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
   return hipGetLastError();
 }
 
-hipError_t launch_theta_1024_sym(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s) {
-  if (!T.sym || !fft_k1024_applies(T)) return hipErrorInvalidValue;
-  const int nprob = (K / 2) * (b.C / 2);
-  k_theta_1024_sym<<<nprob, TT, 0, s>>>(k1024_args(T), GT, HM, b.C, nprob);
+hipError_t launch_phi_forward_bs(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride, double* GT,
+                                 hipStream_t s) {
+  if (bs_tables_match<1024>(T)) return phi_forward_k<1024>(T, b, f, map_stride, GT, s);
+  if (bs_tables_match<512>(T)) return phi_forward_k<512>(T, b, f, map_stride, GT, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_phi_inverse_bs(const ShtTables& T, const Batch& b, const double* FT, void* f, int64_t map_stride,
+                                 hipStream_t s) {
+  if (bs_tables_match<1024>(T)) return phi_inverse_k<1024>(T, b, FT, f, map_stride, s);
+  if (bs_tables_match<512>(T)) return phi_inverse_k<512>(T, b, FT, f, map_stride, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_theta_sym_bs(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s) {
+  if (!T.sym) return hipErrorInvalidValue;
+  const int nprob = (T.k / 2) * (b.C / 2);
+  if (bs_tables_match<1024>(T))
+    k_theta_sym_bs<1024><<<nprob, BsCfg<1024>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
+  else if (bs_tables_match<512>(T))
+    k_theta_sym_bs<512><<<nprob, BsCfg<512>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_resample_1024(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
-  if (!T.sym || !fft_k1024_applies(T)) return hipErrorInvalidValue;
-  const int nprob = (K / 2) * (b.C / 2);   // even: K / 2 is
-  k_resample_1024<<<nprob / 2, 2 * TT, 0, s>>>(k1024_args(T), FS, FT, b.C, nprob);
+hipError_t launch_resample_bs(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
+  if (!T.sym) return hipErrorInvalidValue;
+  const int nprob = (T.k / 2) * (b.C / 2);   // even: k / 2 is
+  if (bs_tables_match<1024>(T))
+    k_resample_bs<1024><<<nprob / 2, 2 * BsCfg<1024>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
+  else if (bs_tables_match<512>(T))
+    k_resample_bs<512><<<nprob / 2, 2 * BsCfg<512>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

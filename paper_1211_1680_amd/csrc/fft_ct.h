@@ -184,6 +184,14 @@ __device__ __forceinline__ void fft1024(double2* buf, int lt, const double2* wlo
   ct_pass<1024, 4, 256, INV, T, TS>(buf, lt, wlo, whi);
 }
 
+// 512 points (8 * 8 * 8) from the tables of W_{512 TS}
+template <bool INV, int T, int TS>
+__device__ __forceinline__ void fft512(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  ct_pass<512, 8, 1, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<512, 8, 8, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<512, 8, 64, INV, T, TS>(buf, lt, wlo, whi);
+}
+
 // The compiled power-of-two FFT of length NL from the tables of W_{NL TS}.
 template <int NL, bool INV, int T, int TS>
 __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo, const double2* whi) {
@@ -192,9 +200,11 @@ __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo,
     fft4096<INV, T>(buf, lt, wlo, whi);
   } else if constexpr (NL == 2048) {
     fft2048<INV, T, TS>(buf, lt, wlo, whi);
-  } else {
-    static_assert(NL == 1024, "compiled lengths: 1024, 2048, 4096");
+  } else if constexpr (NL == 1024) {
     fft1024<INV, T, TS>(buf, lt, wlo, whi);
+  } else {
+    static_assert(NL == 512, "compiled lengths: 512, 1024, 2048, 4096");
+    fft512<INV, T, TS>(buf, lt, wlo, whi);
   }
 }
 

@@ -1,12 +1,12 @@
-// The O(k^2 log k) stages of the MW transform at the band-limits k = 512 and 1024, compiled for
-// those sizes.  n = 2k - 1 (1023 = 3 * 11 * 31, 2047 = 23 * 89) has a prime factor beyond the
-// compiled radices, so the odd-length DFT is Bluestein's chirp transform over the 4k-point FFT; the
-// correlation of the theta stage and the symmetric grid psi_s = pi (2s+1) / (2k) use the 2k-point
-// FFT.  Same arithmetic as the general kernels (kernels_fft.hip) and as the band-limit 2048 kernels
-// (kernels_fft_k2048.hip): phi DFT (Sect. 2.1, MW sampling), theta stage evaluated on the
-// symmetric grid (its last transform), resampling from the symmetric grid to the MW nodes, inverse
-// phi DFT.  One problem per block of BsCfg<k>::TT threads (two for the resampling); 37 KiB (k = 512)
-// or 74 KiB (k = 1024) of LDS per problem.
+// The O(k^2 log k) stages of the MW transform at the band-limits k = 256, 512 and 1024, compiled
+// for those sizes.  n = 2k - 1 (511 = 7 * 73, 1023 = 3 * 11 * 31, 2047 = 23 * 89) has a prime
+// factor beyond the compiled radices, so the odd-length DFT is Bluestein's chirp transform over the
+// 4k-point FFT; the correlation of the theta stage and the symmetric grid psi_s = pi (2s+1) / (2k)
+// use the 2k-point FFT.  Same arithmetic as the general kernels (kernels_fft.hip) and as the
+// band-limit 2048 kernels (kernels_fft_k2048.hip): phi DFT (Sect. 2.1, MW sampling), theta stage
+// evaluated on the symmetric grid (its last transform), resampling from the symmetric grid to the
+// MW nodes, inverse phi DFT.  One problem per block of BsCfg<k>::TT threads (two for the
+// resampling); 74 KiB of LDS per problem at k = 1024, half that at 512 and a quarter at 256.
 #include "common.h"
 #include "fft_ct.h"
 #include "../../include/s2let_mi355x.h"
@@ -18,6 +18,7 @@ namespace {
 template <int K_> struct BsCfg;
 template <> struct BsCfg<1024> { static constexpr int TT = 512, LOGP = 12; };
 template <> struct BsCfg<512> { static constexpr int TT = 256, LOGP = 11; };
+template <> struct BsCfg<256> { static constexpr int TT = 128, LOGP = 10; };
 
 #define S2LET_BS_CONSTANTS                                                          \
   constexpr int N = 2 * K - 1;          /* odd ring length */                        \
@@ -324,7 +325,9 @@ static bool bs_tables_match(const ShtTables& T) {
          T.logP == BsCfg<K>::LOGP && T.loglo == 6;
 }
 
-bool fft_bs_applies(const ShtTables& T) { return bs_tables_match<1024>(T) || bs_tables_match<512>(T); }
+bool fft_bs_applies(const ShtTables& T) {
+  return bs_tables_match<1024>(T) || bs_tables_match<512>(T) || bs_tables_match<256>(T);
+}
 
 static BsArgs bs_args(const ShtTables& T) {
   BsArgs a;
@@ -373,6 +376,7 @@ hipError_t launch_phi_forward_bs(const ShtTables& T, const Batch& b, const void*
                                  hipStream_t s) {
   if (bs_tables_match<1024>(T)) return phi_forward_k<1024>(T, b, f, map_stride, GT, s);
   if (bs_tables_match<512>(T)) return phi_forward_k<512>(T, b, f, map_stride, GT, s);
+  if (bs_tables_match<256>(T)) return phi_forward_k<256>(T, b, f, map_stride, GT, s);
   return hipErrorInvalidValue;
 }
 
@@ -380,6 +384,7 @@ hipError_t launch_phi_inverse_bs(const ShtTables& T, const Batch& b, const doubl
                                  hipStream_t s) {
   if (bs_tables_match<1024>(T)) return phi_inverse_k<1024>(T, b, FT, f, map_stride, s);
   if (bs_tables_match<512>(T)) return phi_inverse_k<512>(T, b, FT, f, map_stride, s);
+  if (bs_tables_match<256>(T)) return phi_inverse_k<256>(T, b, FT, f, map_stride, s);
   return hipErrorInvalidValue;
 }
 
@@ -390,6 +395,8 @@ hipError_t launch_theta_sym_bs(const ShtTables& T, const Batch& b, const double*
     k_theta_sym_bs<1024><<<nprob, BsCfg<1024>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
   else if (bs_tables_match<512>(T))
     k_theta_sym_bs<512><<<nprob, BsCfg<512>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
+  else if (bs_tables_match<256>(T))
+    k_theta_sym_bs<256><<<nprob, BsCfg<256>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -402,6 +409,8 @@ hipError_t launch_resample_bs(const ShtTables& T, const Batch& b, const double* 
     k_resample_bs<1024><<<nprob / 2, 2 * BsCfg<1024>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
   else if (bs_tables_match<512>(T))
     k_resample_bs<512><<<nprob / 2, 2 * BsCfg<512>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
+  else if (bs_tables_match<256>(T))
+    k_resample_bs<256><<<nprob / 2, 2 * BsCfg<256>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -105,7 +105,9 @@ __device__ __forceinline__ void dft_small(double2* v) {
 
 // One pass: N points, radix R, NS = product of the radices of the earlier passes, T threads.
 // The twiddle tables hold W_{N TS}^p (TS > 1: a shorter transform with the tables of a longer one).
-template <int N, int R, int NS, bool INV, int T, int TS = 1>
+// LM / SM: bit r clear = input r of every butterfly is known to be zero (not loaded) / output r is
+// not needed (not stored).
+template <int N, int R, int NS, bool INV, int T, int TS = 1, unsigned LM = 0xFFFFu, unsigned SM = 0xFFFFu>
 __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo, const double2* whi) {
   constexpr int NB = N / R;
   constexpr int STRIDE = N / (NS * R);
@@ -117,7 +119,8 @@ __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo
     const int j = lt + i * T;
     if (j < NB) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_pad(j + r * NB)];
+      for (int r = 0; r < R; ++r)
+        v[i][r] = ((LM >> r) & 1u) ? buf[lds_pad(j + r * NB)] : make_double2(0.0, 0.0);
       if constexpr (NS > 1) {
         const int p = (j % NS) * STRIDE * TS;
         double2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
@@ -140,7 +143,8 @@ __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo
       const int kk = j % NS;
       const int base = (j - kk) * R + kk;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_pad(base + r * NS)] = v[i][r];
+      for (int r = 0; r < R; ++r)
+        if ((SM >> r) & 1u) buf[lds_pad(base + r * NS)] = v[i][r];
     }
   }
   __syncthreads();
@@ -167,29 +171,30 @@ __device__ __forceinline__ void fft4096(double2* buf, int lt, const double2* wlo
 }
 
 // 2048 = 8^3 * 4, with the twiddle tables of length 4096 (unnormalised, sign -1 or +1 with INV)
-template <bool INV, int T, int TS = 2>
+// (LM0 / SML: the first pass's load mask and the last pass's store mask, see ct_pass)
+template <bool INV, int T, int TS = 2, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
 __device__ __forceinline__ void fft2048(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  ct_pass<2048, 8, 1, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<2048, 8, 1, INV, T, TS, LM0>(buf, lt, wlo, whi);
   ct_pass<2048, 8, 8, INV, T, TS>(buf, lt, wlo, whi);
   ct_pass<2048, 8, 64, INV, T, TS>(buf, lt, wlo, whi);
-  ct_pass<2048, 4, 512, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<2048, 4, 512, INV, T, TS, 0xFFFFu, SML>(buf, lt, wlo, whi);
 }
 
 // 1024 points (8 * 8 * 4 * 4) from the tables of W_{1024 TS}
-template <bool INV, int T, int TS>
+template <bool INV, int T, int TS, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
 __device__ __forceinline__ void fft1024(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  ct_pass<1024, 8, 1, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<1024, 8, 1, INV, T, TS, LM0>(buf, lt, wlo, whi);
   ct_pass<1024, 8, 8, INV, T, TS>(buf, lt, wlo, whi);
   ct_pass<1024, 4, 64, INV, T, TS>(buf, lt, wlo, whi);
-  ct_pass<1024, 4, 256, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<1024, 4, 256, INV, T, TS, 0xFFFFu, SML>(buf, lt, wlo, whi);
 }
 
 // 512 points (8 * 8 * 8) from the tables of W_{512 TS}
-template <bool INV, int T, int TS>
+template <bool INV, int T, int TS, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
 __device__ __forceinline__ void fft512(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  ct_pass<512, 8, 1, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<512, 8, 1, INV, T, TS, LM0>(buf, lt, wlo, whi);
   ct_pass<512, 8, 8, INV, T, TS>(buf, lt, wlo, whi);
-  ct_pass<512, 8, 64, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<512, 8, 64, INV, T, TS, 0xFFFFu, SML>(buf, lt, wlo, whi);
 }
 
 // The compiled power-of-two FFT of length NL from the tables of W_{NL TS}.
@@ -205,6 +210,44 @@ __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo,
   } else {
     static_assert(NL == 512, "compiled lengths: 512, 1024, 2048, 4096");
     fft512<INV, T, TS>(buf, lt, wlo, whi);
+  }
+}
+
+// The correlation transforms of the theta stage, NL = 2k points.  One frequency-parity class fills
+// slots [0, NL/4] and [3NL/4, NL) at most, so the forward transform's input vanishes on the rest:
+// inputs 2..5 of every radix-8 first-pass butterfly (0xC3 keeps 0, 1, 6, 7).  The inverse
+// transform's outputs are read back on [0, NL/4] and (3NL/4, NL) only: outputs 0, 1 (slot NL/4)
+// and 3 of a radix-4 last pass, 0, 1, 2 (slot NL/4) and 6, 7 of a radix-8 one.
+template <int NL, int T, int TS>
+__device__ __forceinline__ void fft_corr_fwd(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  if constexpr (NL == 4096) {
+    ct_pass<4096, 8, 1, false, T, TS, 0xC3u>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 8, false, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 64, false, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 512, false, T, TS>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 2048) {
+    fft2048<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 1024) {
+    fft1024<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
+  } else {
+    static_assert(NL == 512, "correlation lengths: 512 to 4096");
+    fft512<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
+  }
+}
+template <int NL, int T, int TS>
+__device__ __forceinline__ void fft_corr_inv(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  if constexpr (NL == 4096) {
+    ct_pass<4096, 8, 1, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 8, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 64, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 512, true, T, TS, 0xFFFFu, 0xC7u>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 2048) {
+    fft2048<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 1024) {
+    fft1024<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
+  } else {
+    static_assert(NL == 512, "correlation lengths: 512 to 4096");
+    fft512<true, T, TS, 0xFFFFu, 0xC7u>(buf, lt, wlo, whi);
   }
 }
 

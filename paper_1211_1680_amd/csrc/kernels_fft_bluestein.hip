@@ -144,8 +144,9 @@ __global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_theta_sym_bs(BsArgs A, cons
 #pragma unroll
   for (int P = 0; P < 2; ++P) {
     __syncthreads();
-    for (int q = lt; q < NC; q += TT) buf[lds_pad(q)] = make_double2(0.0, 0.0);
-    __syncthreads();
+    // the class fills slots [0, k/2) and [3k/2, 2k) except slot 3k/2 for P = 0; the middle is never
+    // read (the first FFT pass skips it), so only that slot needs a zero
+    if (P == 0 && lt == 0) buf[lds_pad(3 * K / 2)] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
@@ -155,11 +156,11 @@ __global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_theta_sym_bs(BsArgs A, cons
       }
     }
     __syncthreads();
-    fft_ct<NC, false, TT, 2>(buf, lt, wlo, whi);
+    fft_corr_fwd<NC, TT, 2>(buf, lt, wlo, whi);
     const double2* kh = P == 0 ? A.khat0 : A.khat1;
     for (int q = lt; q < NC; q += TT) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
     __syncthreads();
-    fft_ct<NC, true, TT, 2>(buf, lt, wlo, whi);
+    fft_corr_inv<NC, TT, 2>(buf, lt, wlo, whi);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;

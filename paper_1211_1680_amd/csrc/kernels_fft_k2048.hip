@@ -156,9 +156,9 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
 #pragma unroll
   for (int P = 0; P < 2; ++P) {
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i) buf[lds_pad(lt + i * TT)] = make_double2(0.0, 0.0);
-    __syncthreads();
+    // the class fills slots [0, 1024) and [3072, 4096) except slot 3072 for P = 0; the middle half
+    // is never read (the first FFT pass skips it), so only that slot needs a zero
+    if (P == 0 && lt == 0) buf[lds_pad(3 * K / 2)] = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       }
     }
     __syncthreads();
-    fft4096_r8<false, TT>(buf, lt, w6lo, w6hi);
+    fft_corr_fwd<NC, TT, 1>(buf, lt, w6lo, w6hi);
     const double2* kh = P == 0 ? A.khat0 : A.khat1;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
     }
     __syncthreads();
-    fft4096_r8<true, TT>(buf, lt, w6lo, w6hi);
+    fft_corr_inv<NC, TT, 1>(buf, lt, w6lo, w6hi);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;

@@ -163,11 +163,11 @@ __device__ __forceinline__ void fft4096_r8(double2* buf, int lt, const double2* 
 // 4096 = 16^3 (unnormalised, sign -1 or +1 with INV): three passes, half of 512 threads active
 // in each; 10 % faster than four radix-8 passes with every thread active (fewer LDS round trips
 // and barriers)
-template <bool INV, int T>
+template <bool INV, int T, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
 __device__ __forceinline__ void fft4096(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  ct_pass<4096, 16, 1, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 16, 1, INV, T, 1, LM0>(buf, lt, wlo, whi);
   ct_pass<4096, 16, 16, INV, T>(buf, lt, wlo, whi);
-  ct_pass<4096, 16, 256, INV, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 16, 256, INV, T, 1, 0xFFFFu, SML>(buf, lt, wlo, whi);
 }
 
 // 2048 = 8^3 * 4, with the twiddle tables of length 4096 (unnormalised, sign -1 or +1 with INV)
@@ -197,19 +197,24 @@ __device__ __forceinline__ void fft512(double2* buf, int lt, const double2* wlo,
   ct_pass<512, 8, 64, INV, T, TS, 0xFFFFu, SML>(buf, lt, wlo, whi);
 }
 
-// The compiled power-of-two FFT of length NL from the tables of W_{NL TS}.
-template <int NL, bool INV, int T, int TS>
+// The compiled power-of-two FFT of length NL from the tables of W_{NL TS}.  LOW_IN: the input
+// vanishes on [NL/2, NL) (the first pass loads the lower half of each butterfly's inputs only);
+// LOW_OUT: only [0, NL/2) of the output is used (the last pass stores the lower half only).
+template <int NL, bool INV, int T, int TS, bool LOW_IN = false, bool LOW_OUT = false>
 __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  // first radix 16 (4096) or 8; last radix 16 (4096), 8 (512) or 4
+  constexpr unsigned LM0 = !LOW_IN ? 0xFFFFu : (NL == 4096 ? 0xFFu : 0xFu);
+  constexpr unsigned SML = !LOW_OUT ? 0xFFFFu : (NL == 4096 ? 0xFFu : NL == 512 ? 0xFu : 0x3u);
   if constexpr (NL == 4096) {
     static_assert(TS == 1, "the 4096-point plan reads W_4096 directly");
-    fft4096<INV, T>(buf, lt, wlo, whi);
+    fft4096<INV, T, LM0, SML>(buf, lt, wlo, whi);
   } else if constexpr (NL == 2048) {
-    fft2048<INV, T, TS>(buf, lt, wlo, whi);
+    fft2048<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
   } else if constexpr (NL == 1024) {
-    fft1024<INV, T, TS>(buf, lt, wlo, whi);
+    fft1024<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
   } else {
     static_assert(NL == 512, "compiled lengths: 512, 1024, 2048, 4096");
-    fft512<INV, T, TS>(buf, lt, wlo, whi);
+    fft512<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
   }
 }
 
@@ -254,21 +259,23 @@ __device__ __forceinline__ void fft_corr_inv(double2* buf, int lt, const double2
 // Bluestein DFT of length n < NL / 2 in buf[0..n), natural order in and out, over the NL-point
 // FFT (tables of W_NL): X_j = c_j sum_q (x_q c_q) conj(c_{j-q}), c_q = exp(-+ i pi q^2 / n); bhat is
 // the FFT of conj(c) wrapped to NL, divided by NL.  Ends with a barrier.
+// (n < NL / 2: the upper half of the first transform's input is zero and is neither written nor
+// read, and only the lower half of the second transform's output is stored)
 template <int NL, bool INV, int T>
 __device__ __forceinline__ void dft_bluestein(double2* buf, int n, int lt, const double2* wlo,
                                               const double2* whi, const double2* __restrict__ chirp,
                                               const double2* __restrict__ bhat) {
-  for (int q = lt; q < NL; q += T) {
+  for (int q = lt; q < NL / 2; q += T) {
     double2 v = make_double2(0.0, 0.0);
     if (q < n) v = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
     buf[lds_pad(q)] = v;
   }
   __syncthreads();
-  fft_ct<NL, false, T, 1>(buf, lt, wlo, whi);
+  fft_ct<NL, false, T, 1, true, false>(buf, lt, wlo, whi);
   for (int q = lt; q < NL; q += T)
     buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(bhat[(NL - q) & (NL - 1)]) : bhat[q]);
   __syncthreads();
-  fft_ct<NL, true, T, 1>(buf, lt, wlo, whi);
+  fft_ct<NL, true, T, 1, false, true>(buf, lt, wlo, whi);
   for (int q = lt; q < n; q += T) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
   __syncthreads();
 }

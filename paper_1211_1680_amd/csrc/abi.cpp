@@ -267,7 +267,8 @@ double triples_of(int k) { return (double)k * (double)k * (double)(k + 1) / 2.0;
 // quadrature, Legendre analysis).  adjoint = true: the adjoint of the inverse transform,
 // g_lm = sum_{t,p} conj(Y_lm(theta_t, phi_p)) f(theta_t, phi_p): the phi DFT without its 2 pi/n
 // weight, no theta quadrature, the same Legendre analysis.
-// lmin > 0: the caller needs no degree below lmin, whose rows of R may then be left zero.
+// lmin > 0: the caller needs no degree below lmin; whole chunks of rows below it stay unwritten (the
+// tiling does not read rows where its kernel vanishes).
 int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const void* f,
                   int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false,
                   int lmin = 0) {

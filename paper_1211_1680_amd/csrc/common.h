@@ -125,8 +125,9 @@ hipError_t launch_phi_inverse_bs(const ShtTables& T, const Batch& b, const doubl
 hipError_t launch_theta_sym_bs(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
 hipError_t launch_resample_bs(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
 int legendre_forward_groups_sym(int k);
-// lmin: the degrees below it take no products.  Forward: their rows of R are written as zero (the
-// caller needs none of them).  Inverse: their rows of S must be zero.  0 = every degree.
+// lmin: the degrees below it take no products.  Forward: their rows of R are left unwritten (the
+// caller reads none of them: the tiling skips rows whose kernel value is zero).  Inverse: their rows
+// of S must be zero.  0 = every degree.
 hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* HM,
                                        double* R, long long part_stride, int precision, int lmin,
                                        unsigned long long* counter, hipStream_t s);

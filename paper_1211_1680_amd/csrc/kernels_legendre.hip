@@ -486,7 +486,9 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<T>::zero();
-      const bool skip = !tile_live || l0 + FWD_LC <= lmin || __all(!valid || negligible(z1, z2, e));
+      // below the degree floor: no products, and no rows of R (the caller reads none of them)
+      const bool below = l0 + FWD_LC <= lmin;
+      const bool skip = !tile_live || below || __all(!valid || negligible(z1, z2, e));
       const double cf = cf_next;
       cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
       recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e,
@@ -507,6 +509,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
           }
         }
       }
+      if (below) continue;   // block-uniform
       __syncthreads();
 #pragma unroll
       for (int lt2 = 0; lt2 < 2; ++lt2)

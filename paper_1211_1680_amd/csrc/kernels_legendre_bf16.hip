@@ -381,7 +381,9 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[x][ct] = v4f{0.f, 0.f, 0.f, 0.f};
-      const bool skip = !tile_live || l0 + FB_LC <= lmin || __all(!valid || negligible(z1, z2, e));
+      // below the degree floor: no products, and no rows of R (the caller reads none of them)
+      const bool below = l0 + FB_LC <= lmin;
+      const bool skip = !tile_live || below || __all(!valid || negligible(z1, z2, e));
       const double cf = cf_next;
       cf_next = chunk_coef<FB_LC>(am, bm, l0 + FB_LC - m, k - m, lane);
       recur_chunk<FB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
@@ -409,6 +411,7 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
           }
         }
       }
+      if (below) continue;   // block-uniform
       __syncthreads();
 #pragma unroll
       for (int lt = 0; lt < 2; ++lt)

@@ -96,7 +96,7 @@ __device__ __forceinline__ void tri_row_mr(int kl, long long q, int& m, int& r) 
 }
 
 // dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks), over the triangle of band-limit
-// klim: one thread per (row, column pair).  Without accumulation klim = kd and the rows l >= ks
+// klim: one thread per (row, column pair); rows with kern[l] = 0 give zero without reading src.  Without accumulation klim = kd and the rows l >= ks
 // of dst are zero-filled; with accumulation klim = min(ks, kd), so rows and columns m >= ks are
 // not visited (they would only receive zeros).
 __global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long long pstride,
@@ -111,7 +111,9 @@ __global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long 
   tri_row_mr(klim, q, m, r);
   const int l = m + r;
   double2 v = make_double2(0.0, 0.0);
-  if (l < ks) {
+  // rows where the kernel vanishes are not read (a forward transform with a degree floor leaves them
+  // unwritten)
+  if (l < ks && kern[l] != 0.0) {
     const double d = dfac[tri_off(Lt, m) + r];
     const double2* at = reinterpret_cast<const double2*>(src + (tri_off(ks, m) + r) * C) + cp;
     double2 x = make_double2(0.0, 0.0);

@@ -23,6 +23,15 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nblk) {
   return x * per + (x < rem ? x : rem) + idx;
 }
 
+// A logical m-pair slot q (XCD-contiguous after xcd_swizzle) -> pair index: slot i of XCD x takes
+// pair 8 i + x, so that pairs of unequal cost (a degree floor makes the low pairs cheaper) are
+// shared evenly by the XCDs.  Identity unless npairs is a multiple of 8.
+__device__ __forceinline__ int spread_pairs(int q, int npairs) {
+  if (npairs & 7) return q;
+  const int per = npairs >> 3;
+  return (q % per) * 8 + q / per;
+}
+
 inline int next_pow2(int v) {
   int p = 1;
   while (p < v) p <<= 1;

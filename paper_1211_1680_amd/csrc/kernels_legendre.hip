@@ -562,7 +562,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int pair = blk / ntb;
+  const int pair = spread_pairs(blk / ntb, (k + 1) / 2);
   const int tile = (blk % ntb) * 4 + w;
   const int t = tile * 64 + lane;
   const bool valid = t < kh;
@@ -611,10 +611,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
     __syncthreads();
     int cur = 0;
     for (int l0 = m; l0 < k; l0 += INVM_LC) {
-      const bool skip = l0 + INVM_LC <= lmin || __all(!valid || negligible(z1, z2, e));
+      // below the degree floor the rows are zero: no products; while the next chunk is below it too,
+      // no rows are staged and the block does not synchronise (block-uniform)
+      const bool below = l0 + INVM_LC <= lmin;
+      const bool stage = l0 + INVM_LC < k && l0 + 2 * INVM_LC > lmin;
+      const bool skip = below || __all(!valid || negligible(z1, z2, e));
       // the next chunk's rows, in flight during this chunk's recursion and products
-      const bool more = l0 + INVM_LC < k;
-      if (more) {
+      if (stage) {
 #pragma unroll
         for (int i = 0; i < PER; ++i)
           pre[i] = (l0 + INVM_LC + tr < k) ? Sm[(size_t)(l0 + INVM_LC - m + tr) * C + tc + i] : 0.0;
@@ -666,12 +669,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
           }
         }
       }
-      if (more) {
+      if (stage) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) Sb[cur ^ 1][tr][tc + i] = pre[i];
+        __syncthreads();   // the next tile is written and this one has been read by every wave
+        cur ^= 1;
       }
-      __syncthreads();   // the next tile is written and this one has been read by every wave
-      cur ^= 1;
     }
 #pragma unroll
     for (int g = 0; g < 4; ++g)

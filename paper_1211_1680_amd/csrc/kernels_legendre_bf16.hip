@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
   const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int pair = blk / ntb;
+  const int pair = spread_pairs(blk / ntb, (k + 1) / 2);
   const int tile = (blk % ntb) * 4 + w;
   const int t = tile * 64 + lane;
   const bool valid = t < kh;

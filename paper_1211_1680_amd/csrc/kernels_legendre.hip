@@ -521,14 +521,19 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
             red[((size_t)w * FWD_LC + lt2 * 16 + li) * RS + c] = (double)acc[lt2][ct][v];
           }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < FWD_LC * C; idx += FWD_NW * 64) {
-        const int lloc = idx / C, c = idx % C;
+      // one column pair per thread and step: 16-byte LDS reads and global stores
+      for (int idx = threadIdx.x; idx < FWD_LC * C / 2; idx += FWD_NW * 64) {
+        const int lloc = idx / (C / 2), c = 2 * (idx % (C / 2));
         const int l = l0 + 2 * (lloc & 15) + (lloc >> 4);
         if (l < k) {
-          double sum = 0.0;
+          double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int ww = 0; ww < FWD_NW; ++ww) sum += red[(ww * FWD_LC + lloc) * RS + c];
-          Rg[(tri_off(k, m) + (l - m)) * C + c] = sum;
+          for (int ww = 0; ww < FWD_NW; ++ww) {
+            const double2 v = *reinterpret_cast<const double2*>(&red[(ww * FWD_LC + lloc) * RS + c]);
+            sum.x += v.x;
+            sum.y += v.y;
+          }
+          *reinterpret_cast<double2*>(&Rg[(tri_off(k, m) + (l - m)) * C + c]) = sum;
         }
       }
       __syncthreads();

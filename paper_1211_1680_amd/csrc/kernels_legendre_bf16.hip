@@ -423,14 +423,19 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
             red[((size_t)w * FB_LC + lt * 16 + li) * RS + c] = (double)acc[lt][ct][v];
           }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < FB_LC * C; idx += FB_NW * 64) {
-        const int lloc = idx / C, c = idx % C;
+      // one column pair per thread and step: 16-byte LDS reads and global stores
+      for (int idx = threadIdx.x; idx < FB_LC * C / 2; idx += FB_NW * 64) {
+        const int lloc = idx / (C / 2), c = 2 * (idx % (C / 2));
         const int l = l0 + 2 * (lloc & 15) + (lloc >> 4);
         if (l < k) {
-          double sum = 0.0;
+          double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int ww = 0; ww < FB_NW; ++ww) sum += red[(ww * FB_LC + lloc) * RS + c];
-          Rg[(tri_off(k, m) + (l - m)) * C + c] = sum;
+          for (int ww = 0; ww < FB_NW; ++ww) {
+            const double2 v = *reinterpret_cast<const double2*>(&red[(ww * FB_LC + lloc) * RS + c]);
+            sum.x += v.x;
+            sum.y += v.y;
+          }
+          *reinterpret_cast<double2*>(&Rg[(tri_off(k, m) + (l - m)) * C + c]) = sum;
         }
       }
       __syncthreads();

@@ -186,10 +186,10 @@ Workspace carve(void* ws, int L, int C, bool wavelet) {
 }
 
 // partial-sum layout of the forward Legendre step at band-limit k
-// The forward and inverse transforms at the band-limits with compiled transforms (128 to 2048) run
+// The forward and inverse transforms at the band-limits with compiled transforms (64 to 2048) run
 // their Legendre steps on the symmetric grid (see launch_theta_2048 / launch_resample_2048).
 bool sym_path(int k, const Batch& b, int precision, bool adjoint) {
-  return (k == 2048 || k == 1024 || k == 512 || k == 256 || k == 128) && !adjoint && b.C >= 16;
+  return (k == 2048 || k == 1024 || k == 512 || k == 256 || k == 128 || k == 64) && !adjoint && b.C >= 16;
 }
 int nparts_of(int k, const Batch& b, int precision, bool adjoint) {
   return sym_path(k, b, precision, adjoint) ? legendre_forward_groups_sym(k) : legendre_forward_groups(k);

@@ -197,6 +197,14 @@ __device__ __forceinline__ void fft512(double2* buf, int lt, const double2* wlo,
   ct_pass<512, 8, 64, INV, T, TS, 0xFFFFu, SML>(buf, lt, wlo, whi);
 }
 
+// 128 points (8 * 4 * 4) from the tables of W_{128 TS}
+template <bool INV, int T, int TS, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
+__device__ __forceinline__ void fft128(double2* buf, int lt, const double2* wlo, const double2* whi) {
+  ct_pass<128, 8, 1, INV, T, TS, LM0>(buf, lt, wlo, whi);
+  ct_pass<128, 4, 8, INV, T, TS>(buf, lt, wlo, whi);
+  ct_pass<128, 4, 32, INV, T, TS, 0xFFFFu, SML>(buf, lt, wlo, whi);
+}
+
 // 256 points (8 * 8 * 4) from the tables of W_{256 TS}
 template <bool INV, int T, int TS, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
 __device__ __forceinline__ void fft256(double2* buf, int lt, const double2* wlo, const double2* whi) {
@@ -212,7 +220,7 @@ template <int NL, bool INV, int T, int TS, bool LOW_IN = false, bool LOW_OUT = f
 __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo, const double2* whi) {
   // first radix 16 (4096) or 8; last radix 16 (4096), 8 (512) or 4
   constexpr unsigned LM0 = !LOW_IN ? 0xFFFFu : (NL == 4096 ? 0xFFu : 0xFu);
-  constexpr unsigned SML = !LOW_OUT ? 0xFFFFu : (NL == 4096 ? 0xFFu : NL == 512 ? 0xFu : 0x3u);   // (256: 4)
+  constexpr unsigned SML = !LOW_OUT ? 0xFFFFu : (NL == 4096 ? 0xFFu : NL == 512 ? 0xFu : 0x3u);
   if constexpr (NL == 4096) {
     static_assert(TS == 1, "the 4096-point plan reads W_4096 directly");
     fft4096<INV, T, LM0, SML>(buf, lt, wlo, whi);
@@ -222,9 +230,11 @@ __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo,
     fft1024<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
   } else if constexpr (NL == 512) {
     fft512<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
-  } else {
-    static_assert(NL == 256, "compiled lengths: 256 to 4096");
+  } else if constexpr (NL == 256) {
     fft256<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
+  } else {
+    static_assert(NL == 128, "compiled lengths: 128 to 4096");
+    fft128<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
   }
 }
 
@@ -246,9 +256,11 @@ __device__ __forceinline__ void fft_corr_fwd(double2* buf, int lt, const double2
     fft1024<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
   } else if constexpr (NL == 512) {
     fft512<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
-  } else {
-    static_assert(NL == 256, "correlation lengths: 256 to 4096");
+  } else if constexpr (NL == 256) {
     fft256<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
+  } else {
+    static_assert(NL == 128, "correlation lengths: 128 to 4096");
+    fft128<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
   }
 }
 template <int NL, int T, int TS>
@@ -264,9 +276,11 @@ __device__ __forceinline__ void fft_corr_inv(double2* buf, int lt, const double2
     fft1024<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
   } else if constexpr (NL == 512) {
     fft512<true, T, TS, 0xFFFFu, 0xC7u>(buf, lt, wlo, whi);
-  } else {
-    static_assert(NL == 256, "correlation lengths: 256 to 4096");
+  } else if constexpr (NL == 256) {
     fft256<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
+  } else {
+    static_assert(NL == 128, "correlation lengths: 128 to 4096");
+    fft128<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
   }
 }
 

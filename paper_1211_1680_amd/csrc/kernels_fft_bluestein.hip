@@ -1,7 +1,7 @@
-// The O(k^2 log k) stages of the MW transform at the band-limits k = 128 to 1024, compiled for
-// those sizes.  n = 2k - 1 (255 = 3 * 5 * 17, 511 = 7 * 73, 1023 = 3 * 11 * 31, 2047 = 23 * 89) has
-// a prime factor beyond the compiled radices, so the odd-length DFT is Bluestein's chirp transform
-// over the 4k-point FFT; the correlation of the theta stage and the symmetric grid
+// The O(k^2 log k) stages of the MW transform at the band-limits k = 64 to 1024, compiled for those
+// sizes.  n = 2k - 1 (127 prime, 255 = 3 * 5 * 17, 511 = 7 * 73, 1023 = 3 * 11 * 31, 2047 = 23 * 89)
+// has a prime factor beyond the compiled radices, so the odd-length DFT is Bluestein's chirp
+// transform over the 4k-point FFT; the correlation of the theta stage and the symmetric grid
 // psi_s = pi (2s+1) / (2k) use the 2k-point FFT.  Same arithmetic as the general kernels
 // (kernels_fft.hip) and as the band-limit 2048 kernels (kernels_fft_k2048.hip): phi DFT (Sect. 2.1,
 // MW sampling), theta stage evaluated on the symmetric grid (its last transform), resampling from
@@ -20,6 +20,7 @@ template <> struct BsCfg<1024> { static constexpr int TT = 512, LOGP = 12; };
 template <> struct BsCfg<512> { static constexpr int TT = 256, LOGP = 11; };
 template <> struct BsCfg<256> { static constexpr int TT = 128, LOGP = 10; };
 template <> struct BsCfg<128> { static constexpr int TT = 64, LOGP = 9; };
+template <> struct BsCfg<64> { static constexpr int TT = 32, LOGP = 8; };
 
 #define S2LET_BS_CONSTANTS                                                          \
   constexpr int N = 2 * K - 1;          /* odd ring length */                        \
@@ -43,9 +44,9 @@ struct BsArgs {
 
 template <int NB>
 __device__ __forceinline__ void stage_tw(const BsArgs& A, double2* wlo, double2* whi) {
-  if (threadIdx.x < 64) {
-    wlo[threadIdx.x] = A.tw_lo[threadIdx.x];
-    if (threadIdx.x < NB / 64) whi[threadIdx.x] = A.tw_hi[threadIdx.x];
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    wlo[i] = A.tw_lo[i];
+    if (i < NB / 64) whi[i] = A.tw_hi[i];
   }
 }
 }  // namespace
@@ -329,7 +330,7 @@ static bool bs_tables_match(const ShtTables& T) {
 
 bool fft_bs_applies(const ShtTables& T) {
   return bs_tables_match<1024>(T) || bs_tables_match<512>(T) || bs_tables_match<256>(T) ||
-         bs_tables_match<128>(T);
+         bs_tables_match<128>(T) || bs_tables_match<64>(T);
 }
 
 static BsArgs bs_args(const ShtTables& T) {
@@ -381,6 +382,7 @@ hipError_t launch_phi_forward_bs(const ShtTables& T, const Batch& b, const void*
   if (bs_tables_match<512>(T)) return phi_forward_k<512>(T, b, f, map_stride, GT, s);
   if (bs_tables_match<256>(T)) return phi_forward_k<256>(T, b, f, map_stride, GT, s);
   if (bs_tables_match<128>(T)) return phi_forward_k<128>(T, b, f, map_stride, GT, s);
+  if (bs_tables_match<64>(T)) return phi_forward_k<64>(T, b, f, map_stride, GT, s);
   return hipErrorInvalidValue;
 }
 
@@ -390,6 +392,7 @@ hipError_t launch_phi_inverse_bs(const ShtTables& T, const Batch& b, const doubl
   if (bs_tables_match<512>(T)) return phi_inverse_k<512>(T, b, FT, f, map_stride, s);
   if (bs_tables_match<256>(T)) return phi_inverse_k<256>(T, b, FT, f, map_stride, s);
   if (bs_tables_match<128>(T)) return phi_inverse_k<128>(T, b, FT, f, map_stride, s);
+  if (bs_tables_match<64>(T)) return phi_inverse_k<64>(T, b, FT, f, map_stride, s);
   return hipErrorInvalidValue;
 }
 
@@ -404,6 +407,8 @@ hipError_t launch_theta_sym_bs(const ShtTables& T, const Batch& b, const double*
     k_theta_sym_bs<256><<<nprob, BsCfg<256>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
   else if (bs_tables_match<128>(T))
     k_theta_sym_bs<128><<<nprob, BsCfg<128>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
+  else if (bs_tables_match<64>(T))
+    k_theta_sym_bs<64><<<nprob, BsCfg<64>::TT, 0, s>>>(bs_args(T), GT, HM, b.C, nprob);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -420,6 +425,8 @@ hipError_t launch_resample_bs(const ShtTables& T, const Batch& b, const double* 
     k_resample_bs<256><<<nprob / 2, 2 * BsCfg<256>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
   else if (bs_tables_match<128>(T))
     k_resample_bs<128><<<nprob / 2, 2 * BsCfg<128>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
+  else if (bs_tables_match<64>(T))
+    k_resample_bs<64><<<nprob / 2, 2 * BsCfg<64>::TT, 0, s>>>(bs_args(T), FS, FT, b.C, nprob);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

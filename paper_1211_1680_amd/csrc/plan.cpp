@@ -191,7 +191,7 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
     };
     for (int t = 0; t < k - 1; ++t) pole[t] = (double)(H(t) - H(n - 1 - t)).real();
     pole[k - 1] = (double)H(k - 1).real();
-    if (k == 2048 || k == 1024 || k == 512 || k == 256 || k == 128) {
+    if (k == 2048 || k == 1024 || k == 512 || k == 256 || k == 128 || k == 64) {
       // the same operator evaluated on the psi grid (N = 2k points psi_s = pi (2s+1) / N):
       //   H(psi_s) = (1/N) sum_j' I_j' e^{-i j' psi_s},  c_s = H(s) - H(N-1-s)  (odd fold), s < k
       const int N = 2 * k;
@@ -223,7 +223,7 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
   if ((e = upload(&T->hphase, to_d2(hph))) != hipSuccess) return e;
   if ((e = upload(&T->pole, pole)) != hipSuccess) return e;
 
-  if (k == 2048 || k == 1024 || k == 512 || k == 256 || k == 128) {
+  if (k == 2048 || k == 1024 || k == 512 || k == 256 || k == 128 || k == 64) {
     const int N = 2 * k, kh = k / 2;
     std::vector<double> us(kh), ss(kh), xs(kh, 1.0);
     for (int t = 0; t < kh; ++t) {

@@ -111,9 +111,9 @@ def test_forward_arbitrary_samples_full_size(dev):
     (1024, s2.REAL, 16, 2), (1024, s2.COMPLEX, 8, 1), (1024, s2.REAL, 2, 2), (1024, s2.COMPLEX, 1, 1),
     (512, s2.REAL, 16, 2), (512, s2.COMPLEX, 8, 1), (512, s2.REAL, 2, 2), (512, s2.COMPLEX, 1, 1),
     (256, s2.REAL, 16, 2), (256, s2.COMPLEX, 8, 1), (256, s2.REAL, 2, 2),
-    (128, s2.REAL, 16, 2), (128, s2.COMPLEX, 8, 1)])
+    (128, s2.REAL, 16, 2), (128, s2.COMPLEX, 8, 1), (64, s2.REAL, 16, 2), (64, s2.COMPLEX, 8, 1)])
 def test_symmetric_grid_batches_full_size(dev, k, reality, nmaps, ndistinct):
-    """At band-limits 2048 to 128 (compiled transforms) the FP64 transforms of batches of 16 or
+    """At band-limits 2048 to 64 (compiled transforms) the FP64 transforms of batches of 16 or
     32 columns (8 or 16 real maps, 4 or 8 complex maps) run their Legendre steps on the symmetric
     grid; smaller batches (2 real maps, 1 complex map) take the compiled phi stages with the MW-node
     theta stage.  Samples that are not band-limited (independent unit normals, so the odd-m pole

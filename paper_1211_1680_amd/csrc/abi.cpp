@@ -357,16 +357,18 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   return S2LET_OK;
 }
 
+// (kacc: rows below it accumulate into dst, rows above are written; zero_fill: rows >= ks of dst
+// up to kd are zeroed)
 hipError_t tile_prof(const LegTables& G, const Batch& b, const double* src, int ks, int nparts, double* dst, int kd,
-                     const double* kern, int accumulate, hipStream_t s) {
+                     const double* kern, int kacc, bool zero_fill, hipStream_t s) {
   ProfRec* r = prof_begin(ST_TILE, s, kd);
   if (r) {
-    // coefficients read once, destination written (and read when accumulating, rows < ks only)
-    const double kk = std::min(ks, kd);
-    const double tk = kk * (kk + 1) / 2.0;
-    r->bytes = 8.0 * b.used * (accumulate ? 3.0 * tk : tk + (double)tri_rows(kd));
+    // coefficients read once, destination written (and read where accumulating)
+    const double kk = std::min(ks, kd), ka = std::min(kacc, (int)kk);
+    const double tk = kk * (kk + 1) / 2.0, ta = ka * (ka + 1) / 2.0;
+    r->bytes = 8.0 * b.used * (2.0 * tk + ta + (zero_fill ? (double)tri_rows(kd) - tk : 0.0));
   }
-  hipError_t e = launch_tile(G, b, src, ks, nparts, pstride_of(ks, b), dst, kd, kern, accumulate, s);
+  hipError_t e = launch_tile(G, b, src, ks, nparts, pstride_of(ks, b), dst, kd, kern, kacc, zero_fill, s);
   prof_end(r, s);
   return e;
 }
@@ -573,7 +575,7 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
     const double* fin = (const double*)f + (size_t)start * msz * cmul;
     if ((st = forward_batch(*TL, dc.leg, b, fin, msz, w, precision, s, adjoint)) != S2LET_OK) return st;
     // scaling part, Eq. (6)
-    hipError_t e = tile_prof(dc.leg, b, w.R, L, nparts_of(L, b, precision, adjoint), w.S, kP, W->eta, 0, s);
+    hipError_t e = tile_prof(dc.leg, b, w.R, L, nparts_of(L, b, precision, adjoint), w.S, kP, W->eta, 0, true, s);
     if (e != hipSuccess) return hip_fail(e);
     double* pout = (double*)f_scal + (size_t)start * psz * cmul;
     if ((st = inverse_batch(*TP, dc.leg, b, w.S, pout, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
@@ -582,7 +584,7 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
     for (int j = J_min; j <= J; ++j) {
       const int kj = bl_wav(j, L, B, multires, kernel);
       e = tile_prof(dc.leg, b, w.R, L, nparts_of(L, b, precision, adjoint), w.S, kj,
-                    W->kappa + (size_t)(j - J_min) * L, 0, s);
+                    W->kappa + (size_t)(j - J_min) * L, 0, true, s);
       if (e != hipSuccess) return hip_fail(e);
       double* wout = (double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = inverse_batch(*TJ[j - J_min], dc.leg, b, w.S, wout, wsz, w, precision, s, adjoint,
@@ -635,8 +637,15 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
     // scaling part
     const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
     if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
-    hipError_t e = tile_prof(dc.leg, b, w.R, kP, nparts_of(kP, b, precision, adjoint), w.S, L, W->eta, 0, s);
+    // S is built over the degrees the contributions cover so far (kcov): each tiling accumulates
+    // below kcov and writes the new rows above it, so no row is zero-filled first -- unless the scales
+    // stop short of L, which the band-limits of Eqs. (4), (8) rule out
+    int kmax = kP;
+    for (int j = J_min; j <= J; ++j) kmax = std::max(kmax, bl_wav(j, L, B, multires, kernel));
+    hipError_t e = tile_prof(dc.leg, b, w.R, kP, nparts_of(kP, b, precision, adjoint), w.S, L, W->eta, 0,
+                             kmax < L, s);
     if (e != hipSuccess) return hip_fail(e);
+    int kcov = kmax < L ? L : kP;
     // wavelet scales, accumulated per Eq. (8)
     int64_t off = 0;
     for (int j = J_min; j <= J; ++j) {
@@ -646,8 +655,9 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
                               W->lmin[j - J_min])) != S2LET_OK)
         return st;
       e = tile_prof(dc.leg, b, w.R, kj, nparts_of(kj, b, precision, adjoint), w.S, L,
-                    W->kappa + (size_t)(j - J_min) * L, 1, s);
+                    W->kappa + (size_t)(j - J_min) * L, kcov, false, s);
       if (e != hipSuccess) return hip_fail(e);
+      kcov = std::max(kcov, kj);
       off += (int64_t)kj * (2 * kj - 1);
     }
     double* fout = (double*)f + (size_t)start * msz * cmul;

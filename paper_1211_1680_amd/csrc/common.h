@@ -183,10 +183,11 @@ hipError_t launch_unpack_flm(const LegTables& G, const Batch& b, int k, const do
 // (and the symmetry for real maps).
 hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const double* R, int nparts,
                            long long part_stride, double2* flm, hipStream_t s);
-// Tiling: dst[tri_off(kd,m)+l-m][c] (=|+=) kern[l] * d_lm^2 * sum_g src_g[tri_off(ks,m)+l-m][c]
-// for l < min(ks, kd); rows with l >= ks of dst are zeroed when accumulate == 0.
+// Tiling: dst[tri_off(kd,m)+l-m][c] (+= for l < kacc, = above) kern[l] * d_lm^2 *
+// sum_g src_g[tri_off(ks,m)+l-m][c] for l < min(ks, kd); with zero_fill, rows l >= ks of dst (up to
+// kd) are set to zero, otherwise they are left as they are.
 hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, int nparts,
-                       long long part_stride, double* dst, int kd, const double* kern, int accumulate,
+                       long long part_stride, double* dst, int kd, const double* kern, int kacc, bool zero_fill,
                        hipStream_t s);
 
 }  // namespace s2let

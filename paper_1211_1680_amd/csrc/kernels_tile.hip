@@ -95,13 +95,12 @@ __device__ __forceinline__ void tri_row_mr(int kl, long long q, int& m, int& r) 
   r = (int)(q - tri_off(kl, mm));
 }
 
-// dst (band-limit kd) (=|+=) kern[l] d_lm^2 src (band-limit ks), over the triangle of band-limit
-// klim: one thread per (row, column pair); rows with kern[l] = 0 give zero without reading src.  Without accumulation klim = kd and the rows l >= ks
-// of dst are zero-filled; with accumulation klim = min(ks, kd), so rows and columns m >= ks are
-// not visited (they would only receive zeros).
+// dst (band-limit kd) (+= for rows l < kacc, = above) kern[l] d_lm^2 src (band-limit ks), over the
+// triangle of band-limit klim: one thread per (row, column pair); rows with kern[l] = 0 give zero
+// without reading src.  klim = min(ks, kd), or kd to zero-fill the rows l >= ks of dst.
 __global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long long pstride,
                        double* __restrict__ dst, int kd, int klim, const double* __restrict__ kern,
-                       const double* __restrict__ dfac, int Lt, int C, int accumulate) {
+                       const double* __restrict__ dfac, int Lt, int C, int kacc) {
   const int CP = C / 2;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= tri_rows(klim) * CP) return;
@@ -126,7 +125,7 @@ __global__ void k_tile(const double* __restrict__ src, int ks, int nparts, long 
     v = make_double2(f * x.x, f * x.y);
   }
   double2* o = reinterpret_cast<double2*>(dst + (tri_off(kd, m) + r) * C) + cp;
-  if (accumulate)
+  if (l < kacc)
     *o = make_double2(o->x + v.x, o->y + v.y);
   else
     *o = v;
@@ -202,14 +201,14 @@ hipError_t launch_pack_flm(const LegTables& G, const Batch& b, int k, const doub
 }
 
 hipError_t launch_tile(const LegTables& G, const Batch& b, const double* src, int ks, int nparts,
-                       long long part_stride, double* dst, int kd, const double* kern, int accumulate,
+                       long long part_stride, double* dst, int kd, const double* kern, int kacc, bool zero_fill,
                        hipStream_t s) {
-  const int klim = accumulate ? (ks < kd ? ks : kd) : kd;
+  const int klim = zero_fill ? kd : (ks < kd ? ks : kd);
   if (b.C & 1) return hipErrorInvalidValue;
   const long long total = tri_rows(klim) * (b.C / 2);
   if (total == 0) return hipSuccess;
   k_tile<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(src, ks, nparts, part_stride, dst, kd, klim, kern, G.dfac,
-                                                         G.Lt, b.C, accumulate);
+                                                         G.Lt, b.C, kacc);
   return hipGetLastError();
 }
 

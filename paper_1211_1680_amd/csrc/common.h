@@ -59,6 +59,8 @@ struct ShtTables {
   int logNc = 0;
   double2* khat0 = nullptr;    // FFT_Nc of Kt_0(c) = w_e(-2c), wrapped, / (Nc n^2)
   double2* khat1 = nullptr;    // FFT_Nc of Kt_1(c) = w_e(2 - 2c), wrapped, / (Nc n^2)
+  double* khr = nullptr;       // real part of khat0 (Kt_0 is real and even, so khat0 is real; Kt_1 is
+                               // Kt_0 shifted by one, so class 1 may use it with the output read one slot lower)
   int logP = 0;     // P = 2^logP = max(M, Nc): one twiddle table for every power-of-two length
   int loglo = 0;    // two-level twiddle split: W_P^p = lo[p & (2^loglo - 1)] * hi[p >> loglo]
   double2* tw_lo = nullptr;    // exp(-2 pi i p / P), p < 2^loglo

@@ -107,32 +107,37 @@ __device__ __forceinline__ void dft_small(double2* v) {
 // The twiddle tables hold W_{N TS}^p (TS > 1: a shorter transform with the tables of a longer one).
 // LM / SM: bit r clear = input r of every butterfly is known to be zero (not loaded) / output r is
 // not needed (not stored).
+// inputs j + r N/R of butterfly j of a pass, with the pass's twiddles applied
+template <int N, int R, int NS, bool INV, int TS, unsigned LM>
+__device__ __forceinline__ void ct_gather(const double2* buf, int j, double2* v, const double2* wlo,
+                                          const double2* whi) {
+  constexpr int NB = N / R;
+  constexpr int STRIDE = N / (NS * R);
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = ((LM >> r) & 1u) ? buf[lds_pad(j + r * NB)] : make_double2(0.0, 0.0);
+  if constexpr (NS > 1) {
+    const int p = (j % NS) * STRIDE * TS;
+    double2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
+    if (INV) w1 = conjd(w1);
+    double2 w = w1;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      v[r] = cmul(v[r], w);
+      if (r + 1 < R) w = cmul(w, w1);
+    }
+  }
+}
+
 template <int N, int R, int NS, bool INV, int T, int TS = 1, unsigned LM = 0xFFFFu, unsigned SM = 0xFFFFu>
 __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo, const double2* whi) {
   constexpr int NB = N / R;
-  constexpr int STRIDE = N / (NS * R);
   constexpr int PER = (NB + T - 1) / T;
   static_assert(N % (NS * R) == 0, "radix plan does not divide the length");
   double2 v[PER][R];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = lt + i * T;
-    if (j < NB) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        v[i][r] = ((LM >> r) & 1u) ? buf[lds_pad(j + r * NB)] : make_double2(0.0, 0.0);
-      if constexpr (NS > 1) {
-        const int p = (j % NS) * STRIDE * TS;
-        double2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
-        if (INV) w1 = conjd(w1);
-        double2 w = w1;
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          v[i][r] = cmul(v[i][r], w);
-          if (r + 1 < R) w = cmul(w, w1);
-        }
-      }
-    }
+    if (j < NB) ct_gather<N, R, NS, INV, TS, LM>(buf, j, v[i], wlo, whi);
   }
   __syncthreads();
 #pragma unroll
@@ -158,6 +163,48 @@ __device__ __forceinline__ void fft4096_r8(double2* buf, int lt, const double2* 
   ct_pass<4096, 8, 8, INV, T>(buf, lt, wlo, whi);
   ct_pass<4096, 8, 64, INV, T>(buf, lt, wlo, whi);
   ct_pass<4096, 8, 512, INV, T>(buf, lt, wlo, whi);
+}
+
+// Circular convolution of the 4096 slots with a kernel whose spectrum kr is real (unnormalised
+// transforms: kr carries the 1/4096).  Four radix-8 passes forward and four inverse, except that
+// the last forward pass and the first inverse pass touch the same slots j + 512 r (j < 512), so
+// one pass does both with the spectrum scaling in between, in registers: one LDS round trip and
+// two barriers fewer than transform, scale, transform.  LM0 / SML: load mask of the first pass,
+// store mask of the last (see ct_pass).
+template <int T, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
+__device__ __forceinline__ void conv4096_real(double2* buf, int lt, const double2* wlo, const double2* whi,
+                                              const double* __restrict__ kr) {
+  constexpr int NB = 512;
+  constexpr int PER = (NB + T - 1) / T;
+  ct_pass<4096, 8, 1, false, T, 1, LM0>(buf, lt, wlo, whi);
+  ct_pass<4096, 8, 8, false, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 8, 64, false, T>(buf, lt, wlo, whi);
+  double2 v[PER][8];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) ct_gather<4096, 8, 512, false, 1, 0xFFFFu>(buf, j, v[i], wlo, whi);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+      double k[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) k[r] = kr[j + r * NB];
+      dft_small<8, false>(v[i]);   // bin j + 512 r in v[i][r]
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[i][r] = make_double2(v[i][r].x * k[r], v[i][r].y * k[r]);
+      dft_small<8, true>(v[i]);    // first inverse pass (no twiddles), outputs 8 j + r
+#pragma unroll
+      for (int r = 0; r < 8; ++r) buf[lds_pad(8 * j + r)] = v[i][r];
+    }
+  }
+  __syncthreads();
+  ct_pass<4096, 8, 8, true, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 8, 64, true, T>(buf, lt, wlo, whi);
+  ct_pass<4096, 8, 512, true, T, 1, 0xFFFFu, SML>(buf, lt, wlo, whi);
 }
 
 // 4096 = 16^3 (unnormalised, sign -1 or +1 with INV): three passes, half of 512 threads active

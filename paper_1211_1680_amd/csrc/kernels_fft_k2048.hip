@@ -22,8 +22,7 @@ struct K2048Args {
   const double2* tw4096_hi;   // W_4096^(64 q), q < 64
   const double2* tw4095_lo;
   const double2* tw4095_hi;
-  const double2* khat0;
-  const double2* khat1;
+  const double* khr;          // real correlation spectrum (both parity classes)
   const double2* hphase;
   const double* pole;         // pole column of the odd-parity theta operator
   const double2* psph;        // symmetric grid: theta-stage output phase
@@ -168,22 +167,21 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       }
     }
     __syncthreads();
-    fft_corr_fwd<NC, TT, 1>(buf, lt, w6lo, w6hi);
-    const double2* kh = P == 0 ? A.khat0 : A.khat1;
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i) {
-      const int q = lt + i * TT;
-      buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
-    }
-    __syncthreads();
-    fft_corr_inv<NC, TT, 1>(buf, lt, w6lo, w6hi);
+    // the class-1 kernel is the class-0 kernel shifted by one slot: convolve with the class-0
+    // kernel and read class 1 one slot lower; either class reads only slots [0, 1024) and
+    // [3072, 4096), so the last pass stores no others
+    // (the opaque copy of the table address keeps the compiler from holding the spectrum in
+    // registers across both classes, which spills)
+    const double* kr = A.khr;
+    asm volatile("" : "+s"(kr));
+    conv4096_real<TT, 0xC3u, 0xC3u>(buf, lt, w6lo, w6hi, kr);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
       if (idx < NJ) {
         const int jp = idx - (K - 1);
         if (((jp - P) & 1) == 0)
-          keep[i] = cmul(SYM ? A.psph[idx] : A.hphase[idx], buf[lds_pad((-(jp - P) / 2) & (NC - 1))]);
+          keep[i] = cmul(SYM ? A.psph[idx] : A.hphase[idx], buf[lds_pad((-(jp - P) / 2 - P) & (NC - 1))]);
       }
     }
   }
@@ -393,8 +391,7 @@ static K2048Args k2048_args(const ShtTables& T) {
   a.tw4096_hi = T.tw_hi;
   a.tw4095_lo = T.twn_lo;
   a.tw4095_hi = T.twn_hi;
-  a.khat0 = T.khat0;
-  a.khat1 = T.khat1;
+  a.khr = T.khr;
   a.hphase = T.hphase;
   a.pole = T.pole;
   a.psph = T.psph;

@@ -133,6 +133,11 @@ hipError_t build_sht_tables(int k, ShtTables* T) {
     host_fft(kt);
     for (auto& v : kt) v /= (LD)Nc * (LD)n * (LD)n;
     if ((e = upload(Q == 0 ? &T->khat0 : &T->khat1, to_d2(kt))) != hipSuccess) return e;
+    if (Q == 0) {
+      std::vector<double> kr(Nc);
+      for (int q = 0; q < Nc; ++q) kr[q] = (double)kt[q].real();
+      if ((e = upload(&T->khr, kr)) != hipSuccess) return e;
+    }
   }
   // W_P two-level table
   {
@@ -257,6 +262,7 @@ void free_sht_tables(ShtTables* T) {
   hipFree(T->bhat);
   hipFree(T->khat0);
   hipFree(T->khat1);
+  hipFree(T->khr);
   hipFree(T->tw_lo);
   hipFree(T->tw_hi);
   hipFree(T->xt);

@@ -165,25 +165,24 @@ __device__ __forceinline__ void fft4096_r8(double2* buf, int lt, const double2* 
   ct_pass<4096, 8, 512, INV, T>(buf, lt, wlo, whi);
 }
 
-// Circular convolution of the 4096 slots with a kernel whose spectrum kr is real (unnormalised
-// transforms: kr carries the 1/4096).  Four radix-8 passes forward and four inverse, except that
-// the last forward pass and the first inverse pass touch the same slots j + 512 r (j < 512), so
-// one pass does both with the spectrum scaling in between, in registers: one LDS round trip and
-// two barriers fewer than transform, scale, transform.  LM0 / SML: load mask of the first pass,
-// store mask of the last (see ct_pass).
-template <int T, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
-__device__ __forceinline__ void conv4096_real(double2* buf, int lt, const double2* wlo, const double2* whi,
+// Circular convolution of one frequency-parity class of the theta stage (NL = 2k slots, tables of
+// W_{NL TS}) with a kernel whose spectrum kr is real (unnormalised transforms: kr carries the
+// 1/NL).  The input lies on [0, NL/4) and [3NL/4, NL) and the output is read there only, so the
+// first pass loads and the last pass stores no other slots.  The forward plan is the inverse plan
+// reversed, so both meet in a radix-8 pass: the last forward pass and the first inverse pass touch
+// the same slots j + r NL/8 (j < NL/8), and one pass does both with the spectrum scaling in
+// between, in registers (one LDS round trip and two barriers fewer than transform, scale,
+// transform).
+template <int NL, int T, int TS>
+__device__ __forceinline__ void corr_conv_mid(double2* buf, int lt, const double2* wlo, const double2* whi,
                                               const double* __restrict__ kr) {
-  constexpr int NB = 512;
+  constexpr int NB = NL / 8;
   constexpr int PER = (NB + T - 1) / T;
-  ct_pass<4096, 8, 1, false, T, 1, LM0>(buf, lt, wlo, whi);
-  ct_pass<4096, 8, 8, false, T>(buf, lt, wlo, whi);
-  ct_pass<4096, 8, 64, false, T>(buf, lt, wlo, whi);
   double2 v[PER][8];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = lt + i * T;
-    if (j < NB) ct_gather<4096, 8, 512, false, 1, 0xFFFFu>(buf, j, v[i], wlo, whi);
+    if (j < NB) ct_gather<NL, 8, NB, false, TS, 0xFFFFu>(buf, j, v[i], wlo, whi);
   }
   __syncthreads();
 #pragma unroll
@@ -193,7 +192,7 @@ __device__ __forceinline__ void conv4096_real(double2* buf, int lt, const double
       double k[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) k[r] = kr[j + r * NB];
-      dft_small<8, false>(v[i]);   // bin j + 512 r in v[i][r]
+      dft_small<8, false>(v[i]);   // bin j + NB r in v[i][r]
 #pragma unroll
       for (int r = 0; r < 8; ++r) v[i][r] = make_double2(v[i][r].x * k[r], v[i][r].y * k[r]);
       dft_small<8, true>(v[i]);    // first inverse pass (no twiddles), outputs 8 j + r
@@ -202,9 +201,57 @@ __device__ __forceinline__ void conv4096_real(double2* buf, int lt, const double
     }
   }
   __syncthreads();
-  ct_pass<4096, 8, 8, true, T>(buf, lt, wlo, whi);
-  ct_pass<4096, 8, 64, true, T>(buf, lt, wlo, whi);
-  ct_pass<4096, 8, 512, true, T, 1, 0xFFFFu, SML>(buf, lt, wlo, whi);
+}
+
+template <int NL, int T, int TS>
+__device__ __forceinline__ void corr_conv(double2* buf, int lt, const double2* wlo, const double2* whi,
+                                          const double* __restrict__ kr) {
+  // a radix-8 first (last) pass keeps inputs (outputs) 0, 1, 6, 7; a radix-4 one keeps 0 and 3
+  constexpr unsigned M8 = 0xC3u, M4 = 0x9u;
+  if constexpr (NL == 4096) {   // 8 8 8 | 8 | 8 8 8
+    ct_pass<4096, 8, 1, false, T, TS, M8>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 8, false, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 64, false, T, TS>(buf, lt, wlo, whi);
+    corr_conv_mid<4096, T, TS>(buf, lt, wlo, whi, kr);
+    ct_pass<4096, 8, 8, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 64, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<4096, 8, 512, true, T, TS, 0xFFFFu, M8>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 2048) {   // 4 8 8 | 8 | 8 8 4
+    ct_pass<2048, 4, 1, false, T, TS, M4>(buf, lt, wlo, whi);
+    ct_pass<2048, 8, 4, false, T, TS>(buf, lt, wlo, whi);
+    ct_pass<2048, 8, 32, false, T, TS>(buf, lt, wlo, whi);
+    corr_conv_mid<2048, T, TS>(buf, lt, wlo, whi, kr);
+    ct_pass<2048, 8, 8, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<2048, 8, 64, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<2048, 4, 512, true, T, TS, 0xFFFFu, M4>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 1024) {   // 4 4 8 | 8 | 8 4 4
+    ct_pass<1024, 4, 1, false, T, TS, M4>(buf, lt, wlo, whi);
+    ct_pass<1024, 4, 4, false, T, TS>(buf, lt, wlo, whi);
+    ct_pass<1024, 8, 16, false, T, TS>(buf, lt, wlo, whi);
+    corr_conv_mid<1024, T, TS>(buf, lt, wlo, whi, kr);
+    ct_pass<1024, 8, 8, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<1024, 4, 64, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<1024, 4, 256, true, T, TS, 0xFFFFu, M4>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 512) {   // 8 8 | 8 | 8 8
+    ct_pass<512, 8, 1, false, T, TS, M8>(buf, lt, wlo, whi);
+    ct_pass<512, 8, 8, false, T, TS>(buf, lt, wlo, whi);
+    corr_conv_mid<512, T, TS>(buf, lt, wlo, whi, kr);
+    ct_pass<512, 8, 8, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<512, 8, 64, true, T, TS, 0xFFFFu, M8>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 256) {   // 4 8 | 8 | 8 4
+    ct_pass<256, 4, 1, false, T, TS, M4>(buf, lt, wlo, whi);
+    ct_pass<256, 8, 4, false, T, TS>(buf, lt, wlo, whi);
+    corr_conv_mid<256, T, TS>(buf, lt, wlo, whi, kr);
+    ct_pass<256, 8, 8, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<256, 4, 64, true, T, TS, 0xFFFFu, M4>(buf, lt, wlo, whi);
+  } else {   // 4 4 | 8 | 4 4
+    static_assert(NL == 128, "correlation lengths: 128 to 4096");
+    ct_pass<128, 4, 1, false, T, TS, M4>(buf, lt, wlo, whi);
+    ct_pass<128, 4, 4, false, T, TS>(buf, lt, wlo, whi);
+    corr_conv_mid<128, T, TS>(buf, lt, wlo, whi, kr);
+    ct_pass<128, 4, 8, true, T, TS>(buf, lt, wlo, whi);
+    ct_pass<128, 4, 32, true, T, TS, 0xFFFFu, M4>(buf, lt, wlo, whi);
+  }
 }
 
 // 4096 = 16^3 (unnormalised, sign -1 or +1 with INV): three passes, half of 512 threads active
@@ -282,52 +329,6 @@ __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo,
   } else {
     static_assert(NL == 128, "compiled lengths: 128 to 4096");
     fft128<INV, T, TS, LM0, SML>(buf, lt, wlo, whi);
-  }
-}
-
-// The correlation transforms of the theta stage, NL = 2k points.  One frequency-parity class fills
-// slots [0, NL/4] and [3NL/4, NL) at most, so the forward transform's input vanishes on the rest:
-// inputs 2..5 of every radix-8 first-pass butterfly (0xC3 keeps 0, 1, 6, 7).  The inverse
-// transform's outputs are read back on [0, NL/4] and (3NL/4, NL) only: outputs 0, 1 (slot NL/4)
-// and 3 of a radix-4 last pass, 0, 1, 2 (slot NL/4) and 6, 7 of a radix-8 one.
-template <int NL, int T, int TS>
-__device__ __forceinline__ void fft_corr_fwd(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  if constexpr (NL == 4096) {
-    ct_pass<4096, 8, 1, false, T, TS, 0xC3u>(buf, lt, wlo, whi);
-    ct_pass<4096, 8, 8, false, T, TS>(buf, lt, wlo, whi);
-    ct_pass<4096, 8, 64, false, T, TS>(buf, lt, wlo, whi);
-    ct_pass<4096, 8, 512, false, T, TS>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 2048) {
-    fft2048<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 1024) {
-    fft1024<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 512) {
-    fft512<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 256) {
-    fft256<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
-  } else {
-    static_assert(NL == 128, "correlation lengths: 128 to 4096");
-    fft128<false, T, TS, 0xC3u>(buf, lt, wlo, whi);
-  }
-}
-template <int NL, int T, int TS>
-__device__ __forceinline__ void fft_corr_inv(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  if constexpr (NL == 4096) {
-    ct_pass<4096, 8, 1, true, T, TS>(buf, lt, wlo, whi);
-    ct_pass<4096, 8, 8, true, T, TS>(buf, lt, wlo, whi);
-    ct_pass<4096, 8, 64, true, T, TS>(buf, lt, wlo, whi);
-    ct_pass<4096, 8, 512, true, T, TS, 0xFFFFu, 0xC7u>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 2048) {
-    fft2048<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 1024) {
-    fft1024<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 512) {
-    fft512<true, T, TS, 0xFFFFu, 0xC7u>(buf, lt, wlo, whi);
-  } else if constexpr (NL == 256) {
-    fft256<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
-  } else {
-    static_assert(NL == 128, "correlation lengths: 128 to 4096");
-    fft128<true, T, TS, 0xFFFFu, 0xBu>(buf, lt, wlo, whi);
   }
 }
 

@@ -34,8 +34,7 @@ struct BsArgs {
   const double2* tw_hi;    // W_4k^(64 q), q < 4k / 64
   const double2* chirp;    // exp(-i pi q^2 / n), q < n
   const double2* bhat;     // FFT_4k of conj(chirp), wrapped, / 4k
-  const double2* khat0;
-  const double2* khat1;
+  const double* khr;          // real correlation spectrum (both parity classes)
   const double2* hphase;
   const double2* psph;
   const double* pole_s;
@@ -158,17 +157,19 @@ __global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_theta_sym_bs(BsArgs A, cons
       }
     }
     __syncthreads();
-    fft_corr_fwd<NC, TT, 2>(buf, lt, wlo, whi);
-    const double2* kh = P == 0 ? A.khat0 : A.khat1;
-    for (int q = lt; q < NC; q += TT) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], kh[q]);
-    __syncthreads();
-    fft_corr_inv<NC, TT, 2>(buf, lt, wlo, whi);
+    // the class-1 kernel is the class-0 kernel shifted by one slot: convolve with the class-0
+    // kernel and read class 1 one slot lower (either class then reads slots [0, k/2) and
+    // [3k/2, 2k) only).  The opaque copy of the table address keeps the compiler from holding
+    // the spectrum in registers across both classes.
+    const double* kr = A.khr;
+    asm volatile("" : "+s"(kr));
+    corr_conv<NC, TT, 2>(buf, lt, wlo, whi, kr);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
       if (idx < NJ) {
         const int jp = idx - (K - 1);
-        if (((jp - P) & 1) == 0) keep[i] = cmul(A.psph[idx], buf[lds_pad((-(jp - P) / 2) & (NC - 1))]);
+        if (((jp - P) & 1) == 0) keep[i] = cmul(A.psph[idx], buf[lds_pad((-(jp - P) / 2 - P) & (NC - 1))]);
       }
     }
   }
@@ -339,8 +340,7 @@ static BsArgs bs_args(const ShtTables& T) {
   a.tw_hi = T.tw_hi;
   a.chirp = T.chirp;
   a.bhat = T.bhat;
-  a.khat0 = T.khat0;
-  a.khat1 = T.khat1;
+  a.khr = T.khr;
   a.hphase = T.hphase;
   a.psph = T.psph;
   a.pole_s = T.pole_s;

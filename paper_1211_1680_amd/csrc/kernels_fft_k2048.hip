@@ -168,13 +168,12 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
     }
     __syncthreads();
     // the class-1 kernel is the class-0 kernel shifted by one slot: convolve with the class-0
-    // kernel and read class 1 one slot lower; either class reads only slots [0, 1024) and
-    // [3072, 4096), so the last pass stores no others
-    // (the opaque copy of the table address keeps the compiler from holding the spectrum in
-    // registers across both classes, which spills)
+    // kernel and read class 1 one slot lower (either class then reads slots [0, 1024) and
+    // [3072, 4096) only).  The opaque copy of the table address keeps the compiler from holding
+    // the spectrum in registers across both classes, which spills.
     const double* kr = A.khr;
     asm volatile("" : "+s"(kr));
-    conv4096_real<TT, 0xC3u, 0xC3u>(buf, lt, w6lo, w6hi, kr);
+    corr_conv<NC, TT, 1>(buf, lt, w6lo, w6hi, kr);
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;

@@ -30,6 +30,40 @@ struct K2048Args {
   const double2* rsph;        // symmetric grid: resampling phase
 };
 
+// First radix-13 pass of the inverse 4095-point DFT, straight from the 4096-point FFT's output:
+// DFT input i is bin j = i (i < K) or j = i - 4095 (i >= K), held in FFT slot j mod 4096, i.e. slot
+// i or i + 1, and is taken times the phase ph[j + K - 1].  Replaces a gather into registers, a
+// barrier, a scatter to the DFT's order and another barrier.
+template <int T>
+__device__ __forceinline__ void dft4095_inv_first_from_fft(double2* buf, int lt, const double2* __restrict__ ph) {
+  constexpr int R = 13, NB = N / R;
+  constexpr int PER = (NB + T - 1) / T;
+  double2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int x = j + r * NB;
+        const bool lo = x < K;
+        v[i][r] = cmul(ph[lo ? x + K - 1 : x - K], buf[lds_pad(lo ? x : x + 1)]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+      dft_small<R, true>(v[i]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds_pad(j * R + r)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void stage_tables(const K2048Args& A, double2* w6lo, double2* w6hi, double2* w5lo,
                                              double2* w5hi) {
   const int lt = threadIdx.x;
@@ -299,26 +333,11 @@ __global__ __launch_bounds__(2 * TT) void k_resample_2048(K2048Args A, const dou
   }
   __syncthreads();
   fft4096<false, TT>(buf, lt, w6lo, w6hi);
-  constexpr int MAXV = NC / TT;
-  constexpr int NJ = 2 * K - 1;
-  double2 keep[MAXV];
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    const int idx = lt + i * TT;
-    if (idx < NJ) keep[i] = cmul(A.rsph[idx], buf[lds_pad((idx - (K - 1)) & (NC - 1))]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    const int idx = lt + i * TT;
-    if (idx < NJ) {
-      const int j = idx - (K - 1);
-      buf[lds_pad(j < 0 ? j + N : j)] = keep[i];
-    }
-  }
-  __syncthreads();
-  dft4095<true, TT>(buf, lt, w5lo, w5hi);
-  __syncthreads();
+  // bins |j| <= K-1 times the phase, inverse 4095-point DFT onto the MW nodes
+  dft4095_inv_first_from_fft<TT>(buf, lt, A.rsph);
+  ct_pass<4095, 9, 13, true, TT>(buf, lt, w5lo, w5hi);
+  ct_pass<4095, 7, 117, true, TT>(buf, lt, w5lo, w5hi);
+  ct_pass<4095, 5, 819, true, TT>(buf, lt, w5lo, w5hi);
   // thread T writes problem 2 p2 + (T & 1) at rings T / 2 + 512 i
   const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
   const int ph = 2 * p2 + h;

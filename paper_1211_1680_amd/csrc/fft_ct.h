@@ -332,6 +332,89 @@ __device__ __forceinline__ void fft_ct(double2* buf, int lt, const double2* wlo,
   }
 }
 
+// The middle of Bluestein's convolution: forward NL-point FFT of an input that vanishes on
+// [NL/2, NL), product with bhat (conjugated and reflected for INV), inverse FFT of which only
+// [0, NL/2) is stored.  The forward plan is the inverse plan reversed, and the pass where they meet
+// does the last forward butterfly, the product and the first inverse butterfly in registers.
+template <int NL, int RM, bool INV, int T>
+__device__ __forceinline__ void bluestein_mid(double2* buf, int lt, const double2* wlo, const double2* whi,
+                                              const double2* __restrict__ bhat) {
+  constexpr int NB = NL / RM;
+  constexpr int PER = (NB + T - 1) / T;
+  double2 v[PER][RM];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) ct_gather<NL, RM, NB, false, 1, 0xFFFFu>(buf, j, v[i], wlo, whi);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+      dft_small<RM, false>(v[i]);   // bin j + NB r in v[i][r]
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        const int q = j + r * NB;
+        v[i][r] = cmul(v[i][r], INV ? conjd(bhat[(NL - q) & (NL - 1)]) : bhat[q]);
+      }
+      dft_small<RM, true>(v[i]);    // first inverse pass (no twiddles), outputs RM j + r
+#pragma unroll
+      for (int r = 0; r < RM; ++r) buf[lds_pad(RM * j + r)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int NL, bool INV, int T>
+__device__ __forceinline__ void bluestein_conv(double2* buf, int lt, const double2* wlo, const double2* whi,
+                                               const double2* __restrict__ bhat) {
+  // lower half of a first pass's inputs / last pass's outputs: radix 4, 8, 16
+  constexpr unsigned H4 = 0x3u, H8 = 0xFu, H16 = 0xFFu;
+  if constexpr (NL == 4096) {   // 16 16 | 16 | 16 16
+    ct_pass<4096, 16, 1, false, T, 1, H16>(buf, lt, wlo, whi);
+    ct_pass<4096, 16, 16, false, T>(buf, lt, wlo, whi);
+    bluestein_mid<4096, 16, INV, T>(buf, lt, wlo, whi, bhat);
+    ct_pass<4096, 16, 16, true, T>(buf, lt, wlo, whi);
+    ct_pass<4096, 16, 256, true, T, 1, 0xFFFFu, H16>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 2048) {   // 4 8 8 | 8 | 8 8 4
+    ct_pass<2048, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    ct_pass<2048, 8, 4, false, T>(buf, lt, wlo, whi);
+    ct_pass<2048, 8, 32, false, T>(buf, lt, wlo, whi);
+    bluestein_mid<2048, 8, INV, T>(buf, lt, wlo, whi, bhat);
+    ct_pass<2048, 8, 8, true, T>(buf, lt, wlo, whi);
+    ct_pass<2048, 8, 64, true, T>(buf, lt, wlo, whi);
+    ct_pass<2048, 4, 512, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 1024) {   // 4 4 8 | 8 | 8 4 4
+    ct_pass<1024, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    ct_pass<1024, 4, 4, false, T>(buf, lt, wlo, whi);
+    ct_pass<1024, 8, 16, false, T>(buf, lt, wlo, whi);
+    bluestein_mid<1024, 8, INV, T>(buf, lt, wlo, whi, bhat);
+    ct_pass<1024, 8, 8, true, T>(buf, lt, wlo, whi);
+    ct_pass<1024, 4, 64, true, T>(buf, lt, wlo, whi);
+    ct_pass<1024, 4, 256, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 512) {   // 8 8 | 8 | 8 8
+    ct_pass<512, 8, 1, false, T, 1, H8>(buf, lt, wlo, whi);
+    ct_pass<512, 8, 8, false, T>(buf, lt, wlo, whi);
+    bluestein_mid<512, 8, INV, T>(buf, lt, wlo, whi, bhat);
+    ct_pass<512, 8, 8, true, T>(buf, lt, wlo, whi);
+    ct_pass<512, 8, 64, true, T, 1, 0xFFFFu, H8>(buf, lt, wlo, whi);
+  } else if constexpr (NL == 256) {   // 4 8 | 8 | 8 4
+    ct_pass<256, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    ct_pass<256, 8, 4, false, T>(buf, lt, wlo, whi);
+    bluestein_mid<256, 8, INV, T>(buf, lt, wlo, whi, bhat);
+    ct_pass<256, 8, 8, true, T>(buf, lt, wlo, whi);
+    ct_pass<256, 4, 64, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+  } else {   // 4 4 | 8 | 4 4
+    static_assert(NL == 128, "Bluestein lengths: 128 to 4096");
+    ct_pass<128, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    ct_pass<128, 4, 4, false, T>(buf, lt, wlo, whi);
+    bluestein_mid<128, 8, INV, T>(buf, lt, wlo, whi, bhat);
+    ct_pass<128, 4, 8, true, T>(buf, lt, wlo, whi);
+    ct_pass<128, 4, 32, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+  }
+}
+
 // Bluestein DFT of length n < NL / 2 in buf[0..n), natural order in and out, over the NL-point
 // FFT (tables of W_NL): X_j = c_j sum_q (x_q c_q) conj(c_{j-q}), c_q = exp(-+ i pi q^2 / n); bhat is
 // the FFT of conj(c) wrapped to NL, divided by NL.  Ends with a barrier.
@@ -347,11 +430,7 @@ __device__ __forceinline__ void dft_bluestein(double2* buf, int n, int lt, const
     buf[lds_pad(q)] = v;
   }
   __syncthreads();
-  fft_ct<NL, false, T, 1, true, false>(buf, lt, wlo, whi);
-  for (int q = lt; q < NL; q += T)
-    buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(bhat[(NL - q) & (NL - 1)]) : bhat[q]);
-  __syncthreads();
-  fft_ct<NL, true, T, 1, false, true>(buf, lt, wlo, whi);
+  bluestein_conv<NL, INV, T>(buf, lt, wlo, whi, bhat);
   for (int q = lt; q < n; q += T) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
   __syncthreads();
 }

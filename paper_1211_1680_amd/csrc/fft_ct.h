@@ -366,52 +366,111 @@ __device__ __forceinline__ void bluestein_mid(double2* buf, int lt, const double
   __syncthreads();
 }
 
+// First forward pass of Bluestein's convolution with the input chirp applied on load: input q < n
+// times c_q (conjugated for INV), zero on [n, NL); the upper half [NL/2, NL) is not loaded.
+template <int NL, int R, bool INV, int T>
+__device__ __forceinline__ void bluestein_first(double2* buf, int lt, int n, const double2* __restrict__ chirp) {
+  constexpr int NB = NL / R;
+  constexpr int PER = (NB + T - 1) / T;
+  double2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int q = j + r * NB;
+        v[i][r] = (r < R / 2 && q < n) ? cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q])
+                                       : make_double2(0.0, 0.0);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+      dft_small<R, false>(v[i]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lds_pad(j * R + r)] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Last inverse pass of Bluestein's convolution with the output chirp applied on store: outputs
+// j + r NL/R of the lower half only, output q < n times c_q (conjugated for INV).
+template <int NL, int R, bool INV, int T>
+__device__ __forceinline__ void bluestein_last(double2* buf, int lt, const double2* wlo, const double2* whi, int n,
+                                               const double2* __restrict__ chirp) {
+  constexpr int NB = NL / R;
+  constexpr int PER = (NB + T - 1) / T;
+  double2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) ct_gather<NL, R, NB, true, 1, 0xFFFFu>(buf, j, v[i], wlo, whi);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = lt + i * T;
+    if (j < NB) {
+      dft_small<R, true>(v[i]);
+#pragma unroll
+      for (int r = 0; r < R / 2; ++r) {
+        const int q = j + r * NB;
+        buf[lds_pad(q)] = q < n ? cmul(v[i][r], INV ? conjd(chirp[q]) : chirp[q]) : v[i][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <int NL, bool INV, int T>
-__device__ __forceinline__ void bluestein_conv(double2* buf, int lt, const double2* wlo, const double2* whi,
-                                               const double2* __restrict__ bhat) {
-  // lower half of a first pass's inputs / last pass's outputs: radix 4, 8, 16
-  constexpr unsigned H4 = 0x3u, H8 = 0xFu, H16 = 0xFFu;
+__device__ __forceinline__ void bluestein_conv(double2* buf, int n, int lt, const double2* wlo, const double2* whi,
+                                               const double2* __restrict__ chirp, const double2* __restrict__ bhat) {
   if constexpr (NL == 4096) {   // 16 16 | 16 | 16 16
-    ct_pass<4096, 16, 1, false, T, 1, H16>(buf, lt, wlo, whi);
+    bluestein_first<4096, 16, INV, T>(buf, lt, n, chirp);
     ct_pass<4096, 16, 16, false, T>(buf, lt, wlo, whi);
     bluestein_mid<4096, 16, INV, T>(buf, lt, wlo, whi, bhat);
     ct_pass<4096, 16, 16, true, T>(buf, lt, wlo, whi);
-    ct_pass<4096, 16, 256, true, T, 1, 0xFFFFu, H16>(buf, lt, wlo, whi);
+    bluestein_last<4096, 16, INV, T>(buf, lt, wlo, whi, n, chirp);
   } else if constexpr (NL == 2048) {   // 4 8 8 | 8 | 8 8 4
-    ct_pass<2048, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    bluestein_first<2048, 4, INV, T>(buf, lt, n, chirp);
     ct_pass<2048, 8, 4, false, T>(buf, lt, wlo, whi);
     ct_pass<2048, 8, 32, false, T>(buf, lt, wlo, whi);
     bluestein_mid<2048, 8, INV, T>(buf, lt, wlo, whi, bhat);
     ct_pass<2048, 8, 8, true, T>(buf, lt, wlo, whi);
     ct_pass<2048, 8, 64, true, T>(buf, lt, wlo, whi);
-    ct_pass<2048, 4, 512, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+    bluestein_last<2048, 4, INV, T>(buf, lt, wlo, whi, n, chirp);
   } else if constexpr (NL == 1024) {   // 4 4 8 | 8 | 8 4 4
-    ct_pass<1024, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    bluestein_first<1024, 4, INV, T>(buf, lt, n, chirp);
     ct_pass<1024, 4, 4, false, T>(buf, lt, wlo, whi);
     ct_pass<1024, 8, 16, false, T>(buf, lt, wlo, whi);
     bluestein_mid<1024, 8, INV, T>(buf, lt, wlo, whi, bhat);
     ct_pass<1024, 8, 8, true, T>(buf, lt, wlo, whi);
     ct_pass<1024, 4, 64, true, T>(buf, lt, wlo, whi);
-    ct_pass<1024, 4, 256, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+    bluestein_last<1024, 4, INV, T>(buf, lt, wlo, whi, n, chirp);
   } else if constexpr (NL == 512) {   // 8 8 | 8 | 8 8
-    ct_pass<512, 8, 1, false, T, 1, H8>(buf, lt, wlo, whi);
+    bluestein_first<512, 8, INV, T>(buf, lt, n, chirp);
     ct_pass<512, 8, 8, false, T>(buf, lt, wlo, whi);
     bluestein_mid<512, 8, INV, T>(buf, lt, wlo, whi, bhat);
     ct_pass<512, 8, 8, true, T>(buf, lt, wlo, whi);
-    ct_pass<512, 8, 64, true, T, 1, 0xFFFFu, H8>(buf, lt, wlo, whi);
+    bluestein_last<512, 8, INV, T>(buf, lt, wlo, whi, n, chirp);
   } else if constexpr (NL == 256) {   // 4 8 | 8 | 8 4
-    ct_pass<256, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    bluestein_first<256, 4, INV, T>(buf, lt, n, chirp);
     ct_pass<256, 8, 4, false, T>(buf, lt, wlo, whi);
     bluestein_mid<256, 8, INV, T>(buf, lt, wlo, whi, bhat);
     ct_pass<256, 8, 8, true, T>(buf, lt, wlo, whi);
-    ct_pass<256, 4, 64, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+    bluestein_last<256, 4, INV, T>(buf, lt, wlo, whi, n, chirp);
   } else {   // 4 4 | 8 | 4 4
     static_assert(NL == 128, "Bluestein lengths: 128 to 4096");
-    ct_pass<128, 4, 1, false, T, 1, H4>(buf, lt, wlo, whi);
+    bluestein_first<128, 4, INV, T>(buf, lt, n, chirp);
     ct_pass<128, 4, 4, false, T>(buf, lt, wlo, whi);
     bluestein_mid<128, 8, INV, T>(buf, lt, wlo, whi, bhat);
     ct_pass<128, 4, 8, true, T>(buf, lt, wlo, whi);
-    ct_pass<128, 4, 32, true, T, 1, 0xFFFFu, H4>(buf, lt, wlo, whi);
+    bluestein_last<128, 4, INV, T>(buf, lt, wlo, whi, n, chirp);
   }
 }
 
@@ -424,15 +483,7 @@ template <int NL, bool INV, int T>
 __device__ __forceinline__ void dft_bluestein(double2* buf, int n, int lt, const double2* wlo,
                                               const double2* whi, const double2* __restrict__ chirp,
                                               const double2* __restrict__ bhat) {
-  for (int q = lt; q < NL / 2; q += T) {
-    double2 v = make_double2(0.0, 0.0);
-    if (q < n) v = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
-    buf[lds_pad(q)] = v;
-  }
-  __syncthreads();
-  bluestein_conv<NL, INV, T>(buf, lt, wlo, whi, bhat);
-  for (int q = lt; q < n; q += T) buf[lds_pad(q)] = cmul(buf[lds_pad(q)], INV ? conjd(chirp[q]) : chirp[q]);
-  __syncthreads();
+  bluestein_conv<NL, INV, T>(buf, n, lt, wlo, whi, chirp, bhat);
 }
 
 // 4095 = 13 * 9 * 7 * 5

@@ -127,3 +127,36 @@ def test_packed_even_weight_with_pole_column():
     assert np.max(np.abs(pole.imag)) < 1e-15
     assert np.max(np.abs(he - full(GE, 0))) < 1e-14
     assert np.max(np.abs(ho + pole * GO[k - 1] - full(GO, 1))) < 1e-14
+
+
+@pytest.mark.parametrize("k", [32, 64, 2048])
+def test_parity_class_kernels_share_one_real_spectrum(k):
+    """The theta correlation of each frequency-parity class Q uses the kernel Kt_Q(c) = w(2Q - 2c),
+    c in [Q - (k-1), Q + (k-1)], wrapped to Nc = 2k slots (the even part of w, Sect. 2.1).  The
+    kernels use one real table for both: Kt_0 is real and even, so its spectrum is real; Kt_1 is
+    Kt_0 shifted by one slot, so class 1 equals the class-0 convolution read one slot lower.  Also
+    checked: after that shift every class reads its output on [0, Nc/4) and [3Nc/4, Nc) only."""
+    Nc = 2 * k
+    kt = []
+    for Q in (0, 1):
+        v = np.zeros(Nc, complex)
+        c = np.arange(Q - (k - 1), Q + k)
+        v[c % Nc] = _w(2 * Q - 2 * c, odd_terms=False)
+        kt.append(v)
+    np.testing.assert_array_equal(kt[1], np.roll(kt[0], 1))
+    spec = np.fft.fft(kt[0])
+    assert np.max(np.abs(spec.imag)) <= 1e-13 * np.max(np.abs(spec.real))
+    np.testing.assert_allclose(spec.real, spec.real[(-np.arange(Nc)) % Nc], rtol=0, atol=1e-13 * np.max(np.abs(spec)))
+
+    rng = np.random.default_rng(7)
+    j = np.arange(-(k - 1), k)
+    for P in (0, 1):
+        cls = j[(j - P) % 2 == 0]
+        x = np.zeros(Nc, complex)
+        x[((cls - P) // 2) % Nc] = rng.standard_normal(cls.size) + 1j * rng.standard_normal(cls.size)
+        direct = np.fft.ifft(np.fft.fft(x) * np.fft.fft(kt[P]))
+        shared = np.fft.ifft(np.fft.fft(x) * spec.real)
+        rd = (-(cls - P) // 2) % Nc
+        np.testing.assert_allclose(shared[(rd - P) % Nc], direct[rd], rtol=0, atol=1e-12 * np.max(np.abs(direct)))
+        slot = (rd - P) % Nc
+        assert np.all((slot < Nc // 4) | (slot >= 3 * Nc // 4))

@@ -9,6 +9,7 @@ from the paper.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseli
 Functions and the passages they follow:
   mw_nodes ................ Sect. 2.1 (MW sampling: (L-1)(2L-1)+1 equiangular samples)
   inverse_sht ............. Eq. (1), truncated at the band-limit (Sect. 2.1)
+  inverse_sht_rings ....... Eq. (1) on a chosen set of rings (checks of large outputs)
   inverse_sht_direct ...... Eq. (1) by direct Y_lm summation (small L only)
   forward_sht ............. Eq. (2), evaluated exactly by the MW quadrature (Sect. 2.1)
   quadrature_weight ....... the sin(theta) integral weights used by that quadrature
@@ -19,7 +20,10 @@ Functions and the passages they follow:
   noise_std ............... wavelet-space noise level of Sect. 4.3 (Eq. (19) and Eq. (15))
   hard_threshold .......... Eq. (23); snr: Eqs. (20)-(21); denoise: Sect. 4.3
 
-Parity status: every function above is pinned by tests/test_oracle_pins.py except the
+Parity status: every function above is pinned by tests/test_oracle_pins.py (the adjoints by
+tests/test_oracle_adjoint.py, the B-spline and denoising functions by
+tests/test_oracle_denoise.py); inverse_sht_rings against the full synthesis and direct Y_lm
+summation, kappa_lambda against the two 30-digit terms of Eq. (13).  Not pinned: the
 absolute values of k_lambda (Eq. (12)), which the paper does not print: they are checked
 against an independent high-precision quadrature only ("parity unpinned" for the absolute
 kernel values).

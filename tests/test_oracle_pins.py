@@ -171,6 +171,39 @@ def test_inverse_vs_direct_summation(k):
     assert np.max(np.abs(a - b)) < 1e-12
 
 
+@pytest.mark.parametrize("k", [2, 7, 16, 33, 128])
+@pytest.mark.parametrize("reality", [False, True])
+def test_inverse_rings_is_inverse_on_those_rings(k, reality):
+    """Eq. (1) on selected rings: the ring-subset synthesis returns exactly the rows of the
+    full synthesis (pinned above against direct Y_lm summation), for rings in any order, with
+    duplicates, the south pole and the first ring; even and odd k, real and complex maps."""
+    flm = si.random_flm(k, 2, reality=True, seed=11 + k) if reality else si.random_flm_unit(k, 2, seed=11 + k)
+    full = oracle.inverse_sht(flm, k, reality=reality)
+    rng = np.random.default_rng(k)
+    rings = np.concatenate([[k - 1, 0], rng.integers(0, k, size=min(k, 9)), [k - 1, k // 2, 0]])
+    sub = oracle.inverse_sht_rings(flm, k, rings, reality=reality)
+    assert sub.shape == (2, rings.size, 2 * k - 1)
+    assert np.isrealobj(sub) == reality
+    assert np.max(np.abs(sub - full[:, rings, :])) <= 1e-14 * max(1.0, np.max(np.abs(full)))
+    # the empty ring set, and every ring in reverse order
+    assert oracle.inverse_sht_rings(flm, k, np.zeros(0, dtype=int), reality=reality).shape == (2, 0, 2 * k - 1)
+    rev = oracle.inverse_sht_rings(flm, k, np.arange(k)[::-1], reality=reality)
+    assert np.max(np.abs(rev - full[:, ::-1, :])) <= 1e-14 * max(1.0, np.max(np.abs(full)))
+    with pytest.raises(ValueError):
+        oracle.inverse_sht_rings(flm, k, [k], reality=reality)
+
+
+def test_inverse_rings_vs_direct_summation():
+    """The ring-subset synthesis against direct Y_lm summation (scipy), independent of the
+    separable evaluation the full synthesis uses."""
+    k = 12
+    flm = si.random_flm_unit(k, 1, seed=5)
+    rings = [11, 3, 3, 0, 7]
+    a = oracle.inverse_sht_rings(flm, k, rings)
+    b = oracle.inverse_sht_direct(flm, k)[:, rings, :]
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
 def test_phi_integral_exact_on_trig_polynomial():
     """A single mode Y_lm is recovered exactly (phi integral of a trigonometric polynomial)."""
     k = 9
@@ -249,6 +282,42 @@ def test_k_lambda_vs_mpmath():
     # the two reference points quoted in the blueprint of this project (30-digit mpmath)
     assert abs(oracle.k_lambda(0.75, 2.0) - 0.45255230486403153) < 2e-15
     assert abs(oracle.k_lambda(0.5, 3.0) - 0.89517435052472923) < 2e-15
+
+
+def test_kappa_lambda_vs_mpmath_difference():
+    """Eq. (13) directly: kappa_lambda(t)^2 = k_lambda(t/lambda) - k_lambda(t), both terms of the
+    difference evaluated independently at 30 digits (tanh-sinh) and subtracted in that precision.
+    The oracle evaluates the difference as one integral, so this checks that rewrite, at both ends
+    of the support (1/lambda, lambda) and at its centre t = 1."""
+    import mpmath
+    mpmath.mp.dps = 30
+
+    def k_mp(t, lam):
+        lam, t = mpmath.mpf(lam), mpmath.mpf(t)
+        if t <= 1 / lam:
+            return mpmath.mpf(1)
+        if t >= 1:
+            return mpmath.mpf(0)
+
+        def g(u):
+            x = 2 * lam * (u - 1 / lam) / (lam - 1) - 1
+            if abs(x) >= 1:
+                return mpmath.mpf(0)
+            return mpmath.exp(-2 / (1 - x * x)) / u
+        return mpmath.quad(g, [t, 1]) / mpmath.quad(g, [1 / lam, (1 / lam + 1) / 2, 1])
+
+    for lam in (2, 3):
+        edges = [1.0 / lam + 1e-3, 1.0 / lam + 0.05, 0.8, 1.0, 1.3, lam - 0.05, lam - 1e-3]
+        for t in edges:
+            ref = k_mp(mpmath.mpf(t) / lam, lam) - k_mp(t, lam)
+            got = oracle.kappa_lambda(t, float(lam)) ** 2
+            assert abs(got - float(ref)) < 1e-14, (lam, t)
+            if float(ref) > 1e-12:      # away from the 30-digit reference's own cancellation
+                assert abs(got - float(ref)) < 1e-13 * float(ref), (lam, t)
+        # outside the support, and its ends: exactly zero
+        for t in (0.0, 0.5 / lam, 1.0 / lam, float(lam), lam + 0.5):
+            assert oracle.kappa_lambda(t, float(lam)) == 0.0
+        assert oracle.kappa_lambda(1.0, float(lam)) == 1.0
 
 
 @pytest.mark.parametrize("L,B,J_min", [(64, 2, 0), (128, 3, 2), (512, 2, 2), (300, 3, 1)])

@@ -307,7 +307,7 @@ def forward_sht_adjoint(flm: np.ndarray, k: int, reality: bool = False) -> np.nd
     P = js[:, None] + js[None, :]
     W = quadrature_weight(P)
     WH = np.ascontiguousarray(W.conj().T)
-    Gb_hat = np.einsum("ab,xbm->xam", WH, Ib)
+    Gb_hat = np.matmul(WH[None], Ib)                  # sum_b WH[a, b] I_bar[x, b, m]
     # 3^H: Ghat = phase D / n, D = fft(g) at js  ->  g_bar = n ifft(conj(phase) Ghat_bar / n)
     Db = np.zeros((nmaps, n, n), dtype=np.complex128)
     Db[:, js % n, :] = np.exp(1j * np.pi * js / n)[None, :, None] * Gb_hat / n

@@ -7,9 +7,14 @@ min(2^(j+1), L), scaling map at 2^J_min = 8), harmonic coefficients drawn with
 C_l = 1/(l(l+1)), seed 3.  Inputs are synthesised on the device before the timed region (as in
 the paper's protocol, Sect. 3.3, input synthesis is not timed) and stay resident in HBM.
 
-Prints one JSON line.  Besides throughput it reports the roofline position of the dominant
-kernel (summed HIP-event time of its launches inside the timed region, against its
-algorithmic work) and the CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line.  `value` comes from K steps timed with the library's per-launch timing
+off.  The same K steps are then run again with every launch bracketed by HIP events on its own
+stream: per-stage times and the roofline position of the dominant kernel (the summed event time
+of its launches against their algorithmic work) come from that second pass.  Also reported: the
+FP32 and BF16x3 contraction modes (throughput, per-scale error against the FP64 run, and both
+rooflines of their Legendre stages: matrix cores and the FP64 recursion), the uneven-batch
+workload, the paper's accuracy/timing sweep (Sect. 3.3), and the CPU oracle timed on one map of
+the workload.
 """
 from __future__ import annotations
 
@@ -80,31 +85,47 @@ def workload_triples(L, B, J_min, multires, s2):
     return 2.0 * (triples(L) + sum(triples(k) for k in ks)), ks
 
 
-def cpu_baseline(L, B, J_min, multires, s2):
-    """Oracle timed on a bounded sample: one inverse + one forward SHT of one real map at L
-    (the unit that dominates the workload), scaled to analysis+synthesis of one map by the
-    ratio of (l, m, theta) triples."""
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(L, B, J_min, multires):
+    """The oracle (test infrastructure, FP64, plain sums in C/OpenMP and numpy) timed on the host's
+    cores on a bounded sample of the workload: the wavelet analysis and synthesis of ONE of its
+    maps, in full, at the workload's parameters.  Input synthesis is not timed (Sect. 3.3)."""
     import numpy as np
     import oracle
     import s2let_inputs as si
     flm = si.random_flm(L, 1, reality=True, seed=3)
     oracle.build()
-    t0 = time.perf_counter()
     f = oracle.inverse_sht(flm, L, reality=True)
-    back = oracle.forward_sht(f, L)
-    dt = time.perf_counter() - t0
-    err = float(np.max(np.abs(back - flm)))
-    full, _ = workload_triples(L, B, J_min, multires, s2)
-    scale = full / (2.0 * triples(L))
+    t0 = time.perf_counter()
+    wav, scal = oracle.analysis(f, L, B, J_min, multires, True)
+    t1 = time.perf_counter()
+    rec = oracle.synthesis(wav, scal, L, B, J_min, multires, True)
+    t2 = time.perf_counter()
+    err = float(np.max(np.abs(rec - f)) / np.max(np.abs(f)))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
-        "value": 1.0 / (dt * scale),
+        "value": 1.0 / (t2 - t0),
         "unit": "maps/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": ("one inverse + one forward SHT of one real map at L=%d (%.1f s, round-trip "
-                   "error %.1e), scaled by the triple ratio %.3f of one map's analysis+synthesis"
-                   % (L, dt, err, scale)),
+        "cpu": cpu_model(),
+        "sample": ("wavelet analysis (%.1f s) + synthesis (%.1f s) of one real map of the workload, "
+                   "L=%d, B=%d, J_min=%d, multiresolution, timed in full (not scaled); relative "
+                   "round-trip error %.1e" % (t1 - t0, t2 - t1, L, B, J_min, err)),
     }
 
 
@@ -157,6 +178,86 @@ def stage_rates(stages):
     return out
 
 
+# Peaks the mixed-precision contraction is held against: FP32 MFMA, and BF16 MFMA divided by the
+# three products of the split (hi*hi + hi*lo + lo*hi) that make one FP64-equivalent product.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+MIXED_PEAK = {"fp32": PEAK_FP32_TFLOPS, "bf16x3": PEAK_BF16_TFLOPS / 3.0}
+
+
+def mixed_roofline(st, mode, C):
+    """Both rooflines of a mixed-precision Legendre stage at the top band-limit: the contraction's
+    algorithmic flops (2 C per retained pair) against the matrix-core peak of its type, and the
+    FP64 recursion's (3 per (l, m, theta) triple) against the FP64 vector peak."""
+    if st["ms"] <= 0:
+        return None
+    sec = st["ms"] * 1e-3
+    triples = st["flops_full"] / (3.0 + 2.0 * C)
+    rec_tf = 3.0 * triples / sec / 1e12
+    con_tf = (st["flops_retained"] - 3.0 * triples) / sec / 1e12
+    mfma, valu = con_tf / MIXED_PEAK[mode], rec_tf / PEAK_FP64_TFLOPS
+    return {"bound": "mfma" if mfma >= valu else "fp64-valu",
+            "contraction_tflops": round(con_tf, 2), "contraction_peak": round(MIXED_PEAK[mode], 1),
+            "mfma_frac": round(mfma, 4), "recursion_tflops": round(rec_tf, 2),
+            "recursion_peak": PEAK_FP64_TFLOPS, "valu_frac": round(valu, 4),
+            "fp64_equivalent_tflops": round(st["flops_retained"] / sec / 1e12, 2),
+            "avg_launch_ms": st["ms"] / max(st["launches"], 1), "launches": st["launches"]}
+
+
+def scale_errors(r, r64, ks, kP, J_min):
+    """Max and RMS error of each output of a mixed-precision run against the FP64 run (itself
+    within 1e-10 of the oracle at this size), relative to that output's max |FP64|."""
+    out = {}
+    views = [("scal", kP, r["f_scal"], r64["f_scal"], 0)]
+    off = 0
+    for j, k in enumerate(ks):
+        views.append(("j=%d" % (J_min + j), k, r["f_wav"], r64["f_wav"], off))
+        off += k * (2 * k - 1)
+    for name, k, a, b, o in views:
+        n = k * (2 * k - 1)
+        d = (a[:, o:o + n] - b[:, o:o + n]).abs()
+        den = b[:, o:o + n].abs().max().item()
+        den = den if den > 0 else 1.0
+        out[name] = {"k": k, "rel_max": d.max().item() / den, "rel_rms": d.square().mean().sqrt().item() / den}
+    return out
+
+
+def paper_sweep(s2, torch, si, dev, reps=5):
+    """The paper's accuracy and timing protocol (Sect. 3.3, Fig. 4): complex f_lm ~ N(0, 1),
+    L = 2^2 ... 2^11, lambda = 2, J_0 = 0, full resolution and multiresolution, one map;
+    epsilon = max |f_lm - f_lm^rec| through inverse, analysis, synthesis, forward, and
+    t_c = (t_ana + t_syn) / 2 (input synthesis and the final forward transform untimed),
+    median of `reps` runs with CUDA events on the current stream."""
+    rows = []
+    for i in range(2, 12):
+        L = 2 ** i
+        flm = torch.from_numpy(si.random_flm_unit(L, 1, seed=L)).to(dev)
+        f = s2.mw_inverse(flm, L, s2.COMPLEX)
+        row = {"L": L}
+        for mode, mr in (("full", False), ("multires", True)):
+            ta, ts = [], []
+            for _ in range(reps + 1):
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record()
+                w, sc = s2.analysis(f, L, 2, 0, mr, s2.COMPLEX)
+                e1.record()
+                rec = s2.synthesis(w, sc, L, 2, 0, mr, s2.COMPLEX)
+                e2.record()
+                torch.cuda.synchronize()
+                ta.append(e0.elapsed_time(e1))
+                ts.append(e1.elapsed_time(e2))
+            back = s2.mw_forward(rec, L, s2.COMPLEX)
+            eps = float((back - flm).abs().max().item())
+            tc = 0.5 * (sorted(ta[1:])[reps // 2] + sorted(ts[1:])[reps // 2])
+            row[mode] = {"eps": eps, "t_c_ms": round(tc, 4)}
+            del w, sc, rec, back
+        row["full_over_multires"] = round(row["full"]["t_c_ms"] / row["multires"]["t_c_ms"], 2)
+        rows.append(row)
+    return {"protocol": "complex f_lm ~ N(0,1), lambda=2, J_0=0, one map, FP64; eps = max|f_lm - f_lm^rec|; "
+                        "t_c = (t_ana + t_syn)/2 on the GPU (median of %d)" % reps,
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +270,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven-batching measurement (256 maps of L in {64..512})")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the paper's accuracy/timing sweep (L = 4 ... 2048, one complex map)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB (read "
                          "and written once) so that a hardware-counter run can calibrate its byte "
@@ -209,20 +312,29 @@ def main():
 
         for _ in range(args.warmup):
             step()
-        torch.cuda.synchronize()
-        s2.profile_enable(True)
+        # the headline: K steps with the library's per-launch timing off
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # the same K steps again with every launch bracketed by HIP events on its stream (and the
+        # Legendre kernels counting their retained pairs): per-stage time and the roofline
+        s2.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dt_prof = time.perf_counter() - t0
         stages = {name: s2.profile_query(name) for name in s2.STAGES}
         at_L = {name: s2.profile_query(name, L) for name in s2.STAGES}
         s2.profile_enable(False)
-        return dict(dt=dt, stages=stages, at_L=at_L, f_wav=f_wav, f_scal=f_scal, rec=rec)
+        return dict(dt=dt, dt_prof=dt_prof, stages=stages, at_L=at_L, f_wav=f_wav, f_scal=f_scal, rec=rec)
 
     r64 = run_mode(s2.FP64)
+    progress("fp64: %.2f ms per step" % (1e3 * r64["dt"] / args.steps))
     dt, stages = r64["dt"], r64["stages"]
     err = float((r64["rec"] - f).abs().max().item() / f.abs().max().item())
 
@@ -265,6 +377,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_profiled": 1e3 * r64["dt_prof"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -282,35 +395,39 @@ def main():
 
     # mixed precision: same workload, Legendre contraction on lower-precision matrix cores
     mixed = {}
+    C = 2 * nmaps
+    ks = [s2.bandlimit_wav(j, L, B, multires) for j in range(J_min, s2.j_max(L, B) + 1)]
     for name in [m for m in args.mixed.split(",") if m and m != "none"]:
         try:
             r = run_mode(PRECISIONS[name])
         except s2.S2letError as exc:
             mixed[name] = {"status": str(exc)}
             continue
-        d_w = (r["f_wav"] - r64["f_wav"]).abs()
-        d_r = (r["rec"] - r64["rec"]).abs()
-        wmax = r64["f_wav"].abs().max().item()
-        fmax = r64["rec"].abs().max().item()
+        progress("%s: %.2f ms per step" % (name, 1e3 * r["dt"] / args.steps))
+        per_scale = scale_errors(r, r64, ks, kP, J_min)
         lst = {n: v for n, v in r["stages"].items()}
         mixed[name] = {
             "value": nmaps * args.steps / r["dt"], "unit": "maps/s",
             "ms_per_step": 1e3 * r["dt"] / args.steps,
             "speedup_vs_fp64": dt / r["dt"],
             "stage_ms_per_step": {n: round(v["ms"] / args.steps, 3) for n, v in lst.items()},
-            "legendre_equiv_tflops": {n: round(v["flops_retained"] / (v["ms"] * 1e-3) / 1e12, 1)
-                                      for n, v in lst.items() if n.startswith("legendre") and v["ms"] > 0},
-            "wavelet_maps_rel_max_err_vs_fp64": d_w.max().item() / wmax,
-            "wavelet_maps_rel_rms_err_vs_fp64": (d_w.square().mean().sqrt().item()) / wmax,
-            "reconstruction_rel_max_err_vs_fp64": d_r.max().item() / fmax,
+            "roofline": {n: mixed_roofline(r["at_L"][n], name, C) for n in ("legendre_analysis", "legendre_synthesis")},
+            "error_vs_fp64_per_scale": per_scale,
+            "reconstruction_rel_max_err_vs_fp64": (r["rec"] - r64["rec"]).abs().max().item() /
+                                                   r64["rec"].abs().max().item(),
         }
         del r
     if mixed:
         out["mixed"] = mixed
     if not args.no_batch:
         out["batch"] = batch_workload(s2, torch, si, dev, args.steps)
+        progress("uneven batches: %.0f maps/s" % out["batch"]["value"])
+    if not args.no_sweep:
+        out["paper_sweep"] = paper_sweep(s2, torch, si, dev)
+        progress("paper sweep done")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(L, B, J_min, multires, s2)
+        progress("CPU oracle: analysis + synthesis of one map at L=%d" % L)
+        out["cpu_baseline"] = cpu_baseline(L, B, J_min, multires)
     print(json.dumps(out), flush=True)
 
 

@@ -166,9 +166,10 @@ int s2let_axisym_synthesis_kernel(void* f, const void* f_wav, const void* f_scal
                                   int multires, int kernel, int reality, int precision, int nmaps, void* ws,
                                   size_t ws_bytes, void* stream);
 
-/* Wavelet denoising by hard thresholding (Sect. 4.2).  For white noise with E|n_lm|^2 = sigma^2
+/* Wavelet denoising by hard thresholding (Sect. 4.3).  For white noise with E|n_lm|^2 = sigma^2
  * (Eq. (19)) the wavelet maps of scale j carry noise of standard deviation
- *   sigma_j = sigma * sqrt( sum_l (2l+1)/(4 pi) kappa_j(l)^2 )           (Eq. (22)),
+ *   sigma_j = sigma * sqrt( sum_l (2l+1)/(4 pi) kappa_j(l)^2 )
+ * (the noise-model relation stated, unnumbered, right after Eq. (22), with Psi^j_l0 from Eq. (15)),
  * written to sigma_wav[j - J_min] (host, J - J_min + 1 doubles).  s2let_hard_threshold sets to zero
  * every sample of the wavelet maps (device, layout of s2let_axisym_analysis) of scale j whose
  * magnitude is below thresholds[j - J_min] (host array; Eq. (23) with T_j = 3 sigma_j, read with

@@ -19,7 +19,7 @@ __all__ = [
     "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
     "mw_forward_adjoint", "mw_inverse_adjoint", "analysis_adjoint", "synthesis_adjoint",
     "BatchPlan", "profile_enable", "profile_query", "STAGES",
-    "KERNEL_SD", "KERNEL_BSPLINE", "KERNEL_NEEDLET", "noise_std", "hard_threshold", "denoise", "snr",
+    "KERNEL_SD", "KERNEL_BSPLINE", "KERNEL_NEEDLET", "noise_std", "hard_threshold", "denoise",
 ]
 
 REAL, COMPLEX = 0, 1
@@ -188,20 +188,27 @@ def _workspace(nbytes: int, device, workspace=None):
     if nbytes == 0:
         raise S2letError(EINVAL, "s2let_workspace_size")
     if workspace is not None:
-        if workspace.numel() * workspace.element_size() < nbytes:
+        _need_cuda(workspace, "workspace", torch.uint8, device=device)
+        if workspace.numel() < nbytes:
             raise S2letError(ENOMEM, "workspace")
         return workspace
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def _need_cuda(t, name, dtype):
+def _need_cuda(t, name, dtype, numel=None, device=None):
+    """Checks a tensor handed to the C ABI: the library sees only its address, so the dtype,
+    device, layout and (when given) element count are checked here."""
     torch = _torch()
-    if not t.is_cuda:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise ValueError("%s must be a device tensor" % name)
     if t.dtype != dtype:
         raise ValueError("%s must have dtype %s" % (name, dtype))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
+    if device is not None and t.device != torch.device(device):
+        raise ValueError("%s must be on %s (it is on %s)" % (name, device, t.device))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must hold %d elements (it holds %d)" % (name, numel, t.numel()))
     return t
 
 
@@ -252,11 +259,14 @@ def analysis(f, L: int, B: int, J_min: int, multires: bool = True, reality: int 
     if f.numel() != nmaps * mw_size(L):
         raise ValueError("f must hold nmaps * L * (2L-1) samples")
     kP = bandlimit_scal(J_min, L, B, multires, kernel)
+    nw, ns = nmaps * wav_size(L, B, J_min, multires, kernel), nmaps * mw_size(kP)
     if out is None:
-        f_wav = torch.empty((nmaps, wav_size(L, B, J_min, multires, kernel)), dtype=dt, device=f.device)
-        f_scal = torch.empty((nmaps, mw_size(kP)), dtype=dt, device=f.device)
+        f_wav = torch.empty((nmaps, nw // nmaps), dtype=dt, device=f.device)
+        f_scal = torch.empty((nmaps, ns // nmaps), dtype=dt, device=f.device)
     else:
         f_wav, f_scal = out
+        _need_cuda(f_wav, "out[0] (f_wav)", dt, nw, f.device)
+        _need_cuda(f_scal, "out[1] (f_scal)", dt, ns, f.device)
     ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
                     f.device, workspace)
     _check(_lib.s2let_axisym_analysis_kernel(f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), L, B, J_min,
@@ -272,12 +282,12 @@ def synthesis(f_wav, f_scal, L: int, B: int, J_min: int, multires: bool = True,
     torch = _torch()
     dt = _map_dtype(reality)
     _need_cuda(f_wav, "f_wav", dt)
-    _need_cuda(f_scal, "f_scal", dt)
     nmaps = f_wav.shape[0] if f_wav.dim() == 2 else 1
     if f_wav.numel() != nmaps * wav_size(L, B, J_min, multires, kernel):
         raise ValueError("f_wav has the wrong size")
-    if f_scal.numel() != nmaps * mw_size(bandlimit_scal(J_min, L, B, multires, kernel)):
-        raise ValueError("f_scal has the wrong size")
+    _need_cuda(f_scal, "f_scal", dt, nmaps * mw_size(bandlimit_scal(J_min, L, B, multires, kernel)), f_wav.device)
+    if out is not None:
+        _need_cuda(out, "out", dt, nmaps * mw_size(L), f_wav.device)
     f = out if out is not None else torch.empty((nmaps, L, 2 * L - 1), dtype=dt, device=f_wav.device)
     ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
                     f_wav.device, workspace)
@@ -314,15 +324,6 @@ def denoise(y, L: int, B: int, J_min: int, sigma: float, multires: bool = True, 
     f_wav, f_scal = analysis(y, L, B, J_min, multires, reality, precision, kernel=kernel)
     hard_threshold(f_wav, nsigma * noise_std(L, B, J_min, sigma, kernel), L, B, J_min, multires, reality, kernel)
     return synthesis(f_wav, f_scal, L, B, J_min, multires, reality, precision, kernel=kernel)
-
-
-def snr(s_lm, y_lm):
-    """SNR(y) = 10 log10(||s||^2 / ||y - s||^2) in dB, energies summed over harmonic coefficients
-    (Eqs. (20)-(21)); device or host tensors of f_lm."""
-    torch = _torch()
-    num = torch.sum(torch.abs(s_lm) ** 2)
-    den = torch.sum(torch.abs(y_lm - s_lm) ** 2)
-    return float(10.0 * torch.log10(num / den))
 
 
 def mw_inverse_adjoint(f, L: int, reality: int = REAL, precision: int = FP64, workspace=None):
@@ -364,12 +365,12 @@ def analysis_adjoint(f_wav, f_scal, L: int, B: int, J_min: int, multires: bool =
     torch = _torch()
     dt = _map_dtype(reality)
     _need_cuda(f_wav, "f_wav", dt)
-    _need_cuda(f_scal, "f_scal", dt)
     nmaps = f_wav.shape[0] if f_wav.dim() == 2 else 1
     if f_wav.numel() != nmaps * wav_size(L, B, J_min, multires):
         raise ValueError("f_wav has the wrong size")
-    if f_scal.numel() != nmaps * mw_size(bandlimit_scal(J_min, L, B, multires)):
-        raise ValueError("f_scal has the wrong size")
+    _need_cuda(f_scal, "f_scal", dt, nmaps * mw_size(bandlimit_scal(J_min, L, B, multires)), f_wav.device)
+    if out is not None:
+        _need_cuda(out, "out", dt, nmaps * mw_size(L), f_wav.device)
     f = out if out is not None else torch.empty((nmaps, L, 2 * L - 1), dtype=dt, device=f_wav.device)
     ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
                     f_wav.device, workspace)
@@ -391,11 +392,14 @@ def synthesis_adjoint(f, L: int, B: int, J_min: int, multires: bool = True, real
     if f.numel() != nmaps * mw_size(L):
         raise ValueError("f must hold nmaps * L * (2L-1) samples")
     kP = bandlimit_scal(J_min, L, B, multires)
+    nw, ns = nmaps * wav_size(L, B, J_min, multires), nmaps * mw_size(kP)
     if out is None:
-        f_wav = torch.empty((nmaps, wav_size(L, B, J_min, multires)), dtype=dt, device=f.device)
-        f_scal = torch.empty((nmaps, mw_size(kP)), dtype=dt, device=f.device)
+        f_wav = torch.empty((nmaps, nw // nmaps), dtype=dt, device=f.device)
+        f_scal = torch.empty((nmaps, ns // nmaps), dtype=dt, device=f.device)
     else:
         f_wav, f_scal = out
+        _need_cuda(f_wav, "out[0] (f_wav)", dt, nw, f.device)
+        _need_cuda(f_scal, "out[1] (f_scal)", dt, ns, f.device)
     ws = _workspace(workspace_size(L, B, J_min, multires, reality, precision, nmaps, True),
                     f.device, workspace)
     _check(_lib.s2let_axisym_synthesis_adjoint(f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), L, B,
@@ -450,6 +454,7 @@ class BatchPlan:
         self.wav_off = [int(x) // cm for x in wo]
         self.scal_off = [int(x) // cm for x in so]
         self.ws = torch.empty(int(_lib.s2let_batch_workspace_size(h)), dtype=torch.uint8, device=self.device)
+        self._captured = None
 
     def _dtype(self):
         return _map_dtype(self.reality)
@@ -464,17 +469,27 @@ class BatchPlan:
     def _ws(self):
         return self.ws.data_ptr(), self.ws.numel()
 
+    def _check_bufs(self, f, f_wav=None, f_scal=None, rec=None):
+        dt = self._dtype()
+        _need_cuda(f, "f", dt, self.totals[0], self.device)
+        if f_wav is not None:
+            _need_cuda(f_wav, "f_wav", dt, self.totals[1], self.device)
+        if f_scal is not None:
+            _need_cuda(f_scal, "f_scal", dt, self.totals[2], self.device)
+        if rec is not None:
+            _need_cuda(rec, "rec", dt, self.totals[0], self.device)
+
     def analysis(self, f, out=None):
-        _need_cuda(f, "f", self._dtype())
         f_wav, f_scal, _ = self.outputs() if out is None else (out[0], out[1], None)
+        self._check_bufs(f, f_wav, f_scal)
         _check(_lib.s2let_batch_analysis(self._h, f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), *self._ws(),
                                          _stream(self.device)), "s2let_batch_analysis")
         return f_wav, f_scal
 
     def run(self, f, out=None):
         """Analysis then synthesis: returns (f_wav, f_scal, reconstruction)."""
-        _need_cuda(f, "f", self._dtype())
         f_wav, f_scal, rec = self.outputs() if out is None else out
+        self._check_bufs(f, f_wav, f_scal, rec)
         _check(_lib.s2let_batch_run(self._h, f_wav.data_ptr(), f_scal.data_ptr(), rec.data_ptr(), f.data_ptr(),
                                     *self._ws(), _stream(self.device)), "s2let_batch_run")
         return f_wav, f_scal, rec
@@ -482,19 +497,28 @@ class BatchPlan:
     def autotune(self, f, out):
         s_, c_, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
         f_wav, f_scal, rec = out
+        self._check_bufs(f, f_wav, f_scal, rec)
+        # a new configuration discards any captured graph (and the buffers it was bound to)
+        self._captured = None
         _check(_lib.s2let_batch_autotune(self._h, f_wav.data_ptr(), f_scal.data_ptr(), rec.data_ptr(),
                                          f.data_ptr(), *self._ws(), _stream(self.device), ctypes.byref(s_),
                                          ctypes.byref(c_), ctypes.byref(ms)), "s2let_batch_autotune")
         return s_.value, c_.value, ms.value
 
     def capture(self, f, out):
-        """Capture run(f, out) into a HIP graph on the current (non-default) stream."""
+        """Capture run(f, out) into a HIP graph on the current (non-default) stream.  The graph
+        writes through the addresses of f and out, so the plan keeps both alive until the next
+        capture, autotune or close."""
         f_wav, f_scal, rec = out
+        self._check_bufs(f, f_wav, f_scal, rec)
         _check(_lib.s2let_batch_graph_capture(self._h, f_wav.data_ptr(), f_scal.data_ptr(), rec.data_ptr(),
                                               f.data_ptr(), *self._ws(), _stream(self.device)),
                "s2let_batch_graph_capture")
+        self._captured = (f, f_wav, f_scal, rec)
 
     def replay(self):
+        if getattr(self, "_captured", None) is None:
+            raise RuntimeError("BatchPlan.replay: no captured graph (call capture() first)")
         _check(_lib.s2let_batch_graph_launch(self._h, _stream(self.device)), "s2let_batch_graph_launch")
 
     def map_view(self, flat, i, kind="map"):
@@ -516,6 +540,7 @@ class BatchPlan:
         if getattr(self, "_h", None):
             _lib.s2let_batch_destroy(self._h)
             self._h = None
+        self._captured = None
 
     def __del__(self):
         try:

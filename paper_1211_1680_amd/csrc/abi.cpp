@@ -188,9 +188,16 @@ Workspace carve(void* ws, int L, int C, bool wavelet) {
 // partial-sum layout of the forward Legendre step at band-limit k
 // The forward and inverse transforms at the band-limits with compiled transforms (64 to 2048) run
 // their Legendre steps on the symmetric grid (see launch_theta_2048 / launch_resample_2048).
+// The adjoint of the inverse transform (a Legendre analysis of unweighted phi sums at the MW
+// nodes, with no quadrature whose output could be evaluated on another grid) keeps the MW nodes.
 bool sym_path(int k, const Batch& b, int precision, bool adjoint) {
   return (k == 2048 || k == 1024 || k == 512 || k == 256 || k == 128 || k == 64) && !adjoint && b.C >= 16;
 }
+// The Legendre synthesis F_m(theta) = sum_l f_lm lambda_lm(theta) is a band-limited function of
+// theta whatever it feeds, so the inverse transform and the adjoint of the forward transform
+// (synthesis, then the quadrature's transpose) both evaluate it on the symmetric grid and
+// resample it to the MW nodes.
+bool sym_inverse_path(int k, const Batch& b) { return sym_path(k, b, S2LET_FP64, false); }
 int nparts_of(int k, const Batch& b, int precision, bool adjoint) {
   return sym_path(k, b, precision, adjoint) ? legendre_forward_groups_sym(k) : legendre_forward_groups(k);
 }
@@ -320,7 +327,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   const double k = T.k, n = T.n;
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
   const double colb = 8.0 * b.used * k * k;
-  const bool sym = sym_path(T.k, b, precision, adjoint);
+  const bool sym = sym_inverse_path(T.k, b);
   ProfRec* r = prof_begin(ST_LEG_INV, s, T.k);
   if (r) {
     r->triples = sym ? triples_of(T.k) / 2.0 : triples_of(T.k);

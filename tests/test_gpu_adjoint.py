@@ -9,8 +9,9 @@
     b_l = exp(-l(l+1) sigma^2 / 2), sigma = 0.005, d = b s + n with s drawn from
     C_l = 1/(l(l+1)) and n white (variance 1e-4 per coefficient), lam = 0.1, seed 4,
     checked against the explicit adjoint formula and against central finite differences (the
-    loss is quadratic, so the central difference is exact up to rounding), and at L = 32
-    against the oracle's gradient."""
+    loss is quadratic, so the central difference is exact up to rounding), and against the
+    oracle's gradient at L = 32 and at the workload's own size, in FP64 and with the FP32
+    contraction (stated bound 1e-5)."""
 import sys
 
 import numpy as np
@@ -133,11 +134,27 @@ def _workload(L, nm, seed=4, sigma=0.005):
     return bl, d, f0
 
 
-def _loss_gpu(f, bl_t, d_t, L, B, J_min, lam):
-    flm = ad.mw_forward_ad(f, L)
+def _loss_gpu(f, bl_t, d_t, L, B, J_min, lam, precision=s2.FP64):
+    flm = ad.mw_forward_ad(f, L, s2.REAL, precision)
     r = bl_t[None, :] * flm - d_t
-    f_wav, _ = ad.analysis_ad(f, L, B, J_min, True)
+    f_wav, _ = ad.analysis_ad(f, L, B, J_min, True, s2.REAL, precision)
     return torch.sum(torch.abs(r) ** 2) + lam * torch.sum(f_wav * f_wav)
+
+
+def _grad_gpu(f0, bl, d, L, B, J_min, lam, precision, dev):
+    f = _to_dev(f0, dev).requires_grad_(True)
+    loss = _loss_gpu(f, _to_dev(bl, dev), _to_dev(d, dev), L, B, J_min, lam, precision)
+    loss.backward()
+    return f.grad.detach()
+
+
+def _grad_oracle(f0, bl, d, L, B, J_min, lam):
+    """The loss gradient from the oracle's transforms and adjoints:
+    2 A^H (b (b f_lm - d)) + 2 lam W^H (W^j(f), 0), A the forward transform, W the analysis."""
+    r = bl[None, :] * oracle.forward_sht(f0, L) - d
+    wav, scal = oracle.analysis(f0, L, B, J_min, True, True)
+    return 2.0 * oracle.forward_sht_adjoint(bl[None, :] * r, L, True) + \
+        2.0 * lam * oracle.analysis_adjoint(wav, np.zeros_like(scal), L, B, J_min, True, True)
 
 
 @pytest.mark.parametrize("L,nm", [(64, 2), (1024, 8)])
@@ -172,14 +189,41 @@ def test_loss_gradient(dev, L, nm):
         assert abs(fdv - gv) <= 1e-8 * max(abs(gv), 1e-30) + 1e-12 * abs(lp) / h
 
 
-def test_loss_gradient_against_oracle(dev):
+# Stated bound of the FP32-contraction gradient against the FP64 oracle's (relative max error):
+# each transform in the chain carries the FP32 contraction's <= 2e-6 (test_gpu_mixed.py).
+TOL_GRAD_FP32 = 1e-5
+
+
+@pytest.mark.parametrize("precision", [s2.FP64, s2.MIXED_FP32])
+def test_loss_gradient_against_oracle(dev, precision):
     L, nm, B, J_min, lam = 32, 2, 2, 2, 0.1
     bl, d, f0 = _workload(L, nm)
-    f = _to_dev(f0, dev).requires_grad_(True)
-    loss = _loss_gpu(f, _to_dev(bl, dev), _to_dev(d, dev), L, B, J_min, lam)
-    loss.backward()
-    r = bl[None, :] * oracle.forward_sht(f0, L) - d
-    wav, scal = oracle.analysis(f0, L, B, J_min, True, True)
-    ref = 2.0 * oracle.forward_sht_adjoint(bl[None, :] * r, L, True) + \
-        2.0 * lam * oracle.analysis_adjoint(wav, np.zeros_like(scal), L, B, J_min, True, True)
-    assert _rel(f.grad.cpu().numpy(), ref) < TOL
+    got = _grad_gpu(f0, bl, d, L, B, J_min, lam, precision, dev)
+    ref = _grad_oracle(f0, bl, d, L, B, J_min, lam)
+    assert _rel(got.cpu().numpy(), ref) < (TOL if precision == s2.FP64 else TOL_GRAD_FP32)
+
+
+@pytest.fixture(scope="module")
+def grad_ref_1024():
+    L, nm, B, J_min, lam = 1024, 8, 2, 2, 0.1
+    bl, d, f0 = _workload(L, nm)
+    _log("oracle gradient of maps 0, 1 at L=%d" % L)
+    return _grad_oracle(f0[:2], bl, d[:2], L, B, J_min, lam)
+
+
+@pytest.mark.parametrize("precision", [s2.FP64, s2.MIXED_FP32])
+def test_loss_gradient_full_size_against_oracle(dev, grad_ref_1024, precision):
+    """The differentiation workload at its size (8 real maps, L = 1024, B = 2, J_min = 2,
+    multiresolution) in FP64 and FP32: the gradient of every map from the GPU's adjoints against
+    the oracle's gradient of the first two maps (the loss is a sum over maps, so each map's
+    gradient depends on that map alone), and in FP32 also against the FP64 GPU gradient."""
+    L, nm, B, J_min, lam = 1024, 8, 2, 2, 0.1
+    bl, d, f0 = _workload(L, nm)
+    _log("loss gradient L=%d nmaps=%d precision=%d: GPU" % (L, nm, precision))
+    got = _grad_gpu(f0, bl, d, L, B, J_min, lam, precision, dev).cpu().numpy()
+    ref = grad_ref_1024
+    tol = TOL if precision == s2.FP64 else TOL_GRAD_FP32
+    assert _rel(got[:2], ref) < tol
+    if precision != s2.FP64:
+        g64 = _grad_gpu(f0, bl, d, L, B, J_min, lam, s2.FP64, dev).cpu().numpy()
+        assert _rel(got, g64) < tol

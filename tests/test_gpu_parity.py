@@ -114,8 +114,9 @@ def test_round_trip_moderate(dev):
     back = s2.mw_forward(f, L, s2.COMPLEX).cpu().numpy()
     err = oracle.max_abs_err(back, flm)
     _log("  round trip L=%d: %.3e" % (L, err))
-    # the paper finds round-trip errors growing as O(L) at floating-point level (Sect. 3.3)
-    assert err < 2e-14 * L
+    # the paper finds round-trip errors of unit coefficients at floating-point level, growing as
+    # O(L) (Sect. 3.3); 1e-12 at L = 256 leaves about 15x room over the measured 6e-14
+    assert err < 1e-12
 
 
 # ------------------------------------------------------------------ wavelets
@@ -164,16 +165,68 @@ def test_wavelet_synthesis_parity(dev, L, B, J_min, multires, reality):
     assert _rel(rec, f) < TOL
 
 
-def test_wavelet_round_trip_config_512_complex(dev):
-    """One complex map, L=512, B=2, J_min=2, multiresolution: analysis then synthesis returns
-    the seeded coefficients; the harmonic transforms match the oracle."""
+@pytest.mark.parametrize("L,B,J_min,multires,reality", WAVELET_CASES)
+def test_wavelet_synthesis_of_arbitrary_maps(dev, L, B, J_min, multires, reality):
+    """Eq. (8) applied to wavelet and scaling maps that no analysis produced (independent normal
+    samples on every scale's grid, south-pole rings included), against the oracle's synthesis:
+    the scales' forward transforms, the tiling sum and the inverse are all exercised on
+    inconsistent input."""
+    _log("synthesis of arbitrary maps", L, B, J_min, multires, reality)
+    real = reality == s2.REAL
+    rng = np.random.default_rng(7 * L + B + J_min)
+    nm = 2
+
+    def rmap(k):
+        x = rng.standard_normal((nm, k, 2 * k - 1))
+        return x if real else x + 1j * rng.standard_normal((nm, k, 2 * k - 1))
+
+    wav = [rmap(oracle.bandlimit_wav(j, L, B, multires)) for j in range(J_min, oracle.j_max(L, B) + 1)]
+    scal = rmap(oracle.bandlimit_scal(J_min, L, B, multires))
+    ref = oracle.synthesis(wav, scal, L, B, J_min, multires, real)
+    f_wav = np.concatenate([w.reshape(nm, -1) for w in wav], axis=1)
+    got = s2.synthesis(_to_dev(f_wav, dev), _to_dev(scal.reshape(nm, -1), dev), L, B, J_min, multires,
+                       reality).cpu().numpy()
+    assert _rel(got, ref) < TOL
+
+
+# FP32 contraction: stated bound (relative max error against the FP64 oracle), test_gpu_mixed.py
+TOL_FP32 = 2e-6
+
+
+@pytest.fixture(scope="module")
+def config_512_complex():
+    """One complex map, L = 512, C_l = 1/(l(l+1)), seed 1; B = 2, J_min = 2, multiresolution
+    (scaling map at k = 4, scales at k = 8 ... 512): the oracle's map, scale maps and synthesis."""
     L, B, J_min = 512, 2, 2
     flm = si.random_flm(L, 1, reality=False, seed=1)
     f = oracle.inverse_sht(flm, L)
-    fd = _to_dev(f, dev)
-    got_flm = s2.mw_forward(fd, L, s2.COMPLEX).cpu().numpy()
-    assert _rel(got_flm, flm) < TOL
-    f_wav, f_scal = s2.analysis(fd, L, B, J_min, True, s2.COMPLEX)
-    rec = s2.synthesis(f_wav, f_scal, L, B, J_min, True, s2.COMPLEX)
-    back = s2.mw_forward(rec, L, s2.COMPLEX).cpu().numpy()
-    assert _rel(back, flm) < TOL
+    _log("config L=512 complex: oracle analysis and synthesis")
+    wav, scal = oracle.analysis(f, L, B, J_min, True, False)
+    rec = oracle.synthesis(wav, scal, L, B, J_min, True, False)
+    return dict(L=L, B=B, J_min=J_min, flm=flm, f=f, wav=wav, scal=scal, rec=rec)
+
+
+@pytest.mark.parametrize("precision", [s2.FP64, s2.MIXED_FP32])
+def test_config_512_complex_against_oracle(dev, config_512_complex, precision):
+    """The complex-map configuration in FP64 and FP32 side by side: the forward and inverse SHT,
+    every wavelet scale and the scaling map of the analysis, and the synthesis, each against the
+    oracle (1e-10 in FP64, the stated 2e-6 in FP32).  Per-scale errors are printed."""
+    c = config_512_complex
+    L, B, J_min = c["L"], c["B"], c["J_min"]
+    tol = TOL if precision == s2.FP64 else TOL_FP32
+    fd = _to_dev(c["f"], dev)
+    _log("config L=512 complex, precision %d: SHT" % precision)
+    assert _rel(s2.mw_forward(fd, L, s2.COMPLEX, precision).cpu().numpy(), c["flm"]) < tol
+    assert _rel(s2.mw_inverse(_to_dev(c["flm"], dev), L, s2.COMPLEX, precision).cpu().numpy(), c["f"]) < tol
+    f_wav, f_scal = s2.analysis(fd, L, B, J_min, True, s2.COMPLEX, precision)
+    floor = 1e-6 * float(np.max(np.abs(c["f"])))
+    kP = oracle.bandlimit_scal(J_min, L, B, True)
+    _log("  scaling map k=%d" % kP)
+    assert _rel(f_scal.cpu().numpy().reshape(1, kP, 2 * kP - 1), c["scal"], floor) < tol
+    for j, g, r in zip(range(J_min, oracle.j_max(L, B) + 1), s2.split_wav(f_wav, L, B, J_min, True), c["wav"]):
+        _log("  scale j=%d k=%d" % (j, r.shape[1]))
+        assert _rel(g.cpu().numpy(), r, floor) < tol
+    _log("  synthesis")
+    rec = s2.synthesis(f_wav, f_scal, L, B, J_min, True, s2.COMPLEX, precision).cpu().numpy()
+    assert _rel(rec, c["rec"]) < tol
+    assert _rel(rec, c["f"]) < tol

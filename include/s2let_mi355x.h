@@ -44,7 +44,9 @@ enum {
   S2LET_EINVAL = -1,        /* invalid argument (nothing launched) */
   S2LET_ENOMEM = -2,        /* workspace too small, or the plan cache could not allocate */
   S2LET_EHIP = -3,          /* a HIP runtime call failed */
-  S2LET_EUNSUPPORTED = -4   /* valid by the paper, outside this library's limits */
+  S2LET_EUNSUPPORTED = -4,  /* valid by the paper, outside this library's limits */
+  S2LET_ENOTREADY = -5,     /* s2let_axisym_analysis_noalloc: plan tables not built on this device */
+  S2LET_ESCRATCH = -6       /* s2let_axisym_analysis_noalloc: needs more than its static scratch */
 };
 
 enum { S2LET_REAL = 0, S2LET_COMPLEX = 1 };                       /* reality */
@@ -116,6 +118,26 @@ int mw_inverse(void* f, const void* flm, int L, int reality, int precision, int 
 int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
                           int multires, int reality, int precision, int nmaps, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* Allocation-free variant of s2let_axisym_analysis, for callers that cannot allocate device
+ * memory while they run (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, layouts and result as s2let_axisym_analysis with the
+ * S2LET_KERNEL_SD kernels, without ws / ws_bytes: the workspace is a static device array of
+ * S2LET_NOALLOC_SCRATCH_BYTES inside the library, one per device, held until the process ends.
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library routine, and no
+ * profiling events.
+ *  - S2LET_ESCRATCH if the call needs more workspace than that array holds, i.e. if
+ *    s2let_workspace_size(L, B, J_min, multires, reality, precision, nmaps, 1) exceeds
+ *    S2LET_NOALLOC_SCRATCH_BYTES (e.g. 16 real maps at L = 256 fit, at L = 512 they do not).
+ *  - S2LET_ENOTREADY if the plan tables for these sizes (recursion coefficients, DFT tables,
+ *    wavelet kernels of (L, B, J_min)) have not been built on the current device by an earlier
+ *    allocating call: run s2let_axisym_analysis once with the same L, B, J_min and multires first.
+ *  - Every call on a device uses that device's one array and leaves its contents behind (no part
+ *    of it needs to start at zero): calls that overlap on one device, on different streams or
+ *    threads, race and give wrong results.  Serialise them. */
+#define S2LET_NOALLOC_SCRATCH_BYTES (64u << 20)
+int s2let_axisym_analysis_noalloc(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                                  int multires, int reality, int precision, int nmaps, void* stream);
 
 /* Axisymmetric wavelet synthesis, Eq. (8): a forward SHT of every scale at its band-limit,
  * the harmonic tiling sum, and one inverse SHT at L.  Same layouts as the analysis, with

@@ -17,6 +17,7 @@ __all__ = [
     "REAL", "COMPLEX", "FP64", "MIXED_FP32", "MIXED_BF16X3", "MAX_L", "S2letError", "lib",
     "j_max", "bandlimit_wav", "bandlimit_scal", "mw_size", "wav_size", "tiling_axisym",
     "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
+    "analysis_noalloc", "NOALLOC_SCRATCH_BYTES",
     "mw_forward_adjoint", "mw_inverse_adjoint", "analysis_adjoint", "synthesis_adjoint",
     "BatchPlan", "profile_enable", "profile_query", "STAGES",
     "KERNEL_SD", "KERNEL_BSPLINE", "KERNEL_NEEDLET", "noise_std", "hard_threshold", "denoise",
@@ -26,7 +27,8 @@ REAL, COMPLEX = 0, 1
 FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
 KERNEL_SD, KERNEL_BSPLINE, KERNEL_NEEDLET = 0, 1, 2
 MAX_L = 2048
-OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTREADY, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 64 << 20   # S2LET_NOALLOC_SCRATCH_BYTES
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libs2let_mi355x.so")
@@ -65,6 +67,7 @@ def _load():
         "mw_inverse": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_analysis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_synthesis": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
+        "s2let_axisym_analysis_noalloc": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp]),
         "mw_forward_adjoint": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
         "mw_inverse_adjoint": (i, [vp, vp, i, i, i, i, vp, sz, vp]),
         "s2let_axisym_analysis_adjoint": (i, [vp, vp, vp, i, i, i, i, i, i, i, vp, sz, vp]),
@@ -273,6 +276,27 @@ def analysis(f, L: int, B: int, J_min: int, multires: bool = True, reality: int 
                                              int(multires), kernel, reality, precision, nmaps, ws.data_ptr(),
                                              ws.numel() * ws.element_size(), _stream(f.device)),
            "s2let_axisym_analysis_kernel")
+    return f_wav, f_scal
+
+
+def analysis_noalloc(f, L: int, B: int, J_min: int, multires: bool, reality: int, precision: int, out):
+    """Wavelet analysis through the allocation-free entry point s2let_axisym_analysis_noalloc:
+    the library's static device scratch replaces the workspace, and the caller passes the outputs
+    out = (f_wav [nmaps, wav_size], f_scal [nmaps, mw_size(k_Phi)]).  The plan tables must exist
+    on the device (one earlier `analysis` call with the same L, B, J_min, multires); calls that
+    overlap on one device race.  Returns out."""
+    dt = _map_dtype(reality)
+    _need_cuda(f, "f", dt)
+    nmaps = f.shape[0] if f.dim() == 3 else 1
+    if f.numel() != nmaps * mw_size(L):
+        raise ValueError("f must hold nmaps * L * (2L-1) samples")
+    kP = bandlimit_scal(J_min, L, B, multires)
+    f_wav, f_scal = out
+    _need_cuda(f_wav, "out[0] (f_wav)", dt, nmaps * wav_size(L, B, J_min, multires), f.device)
+    _need_cuda(f_scal, "out[1] (f_scal)", dt, nmaps * mw_size(kP), f.device)
+    _check(_lib.s2let_axisym_analysis_noalloc(f_wav.data_ptr(), f_scal.data_ptr(), f.data_ptr(), L, B, J_min,
+                                              int(multires), reality, precision, nmaps, _stream(f.device)),
+           "s2let_axisym_analysis_noalloc")
     return f_wav, f_scal
 
 

@@ -65,8 +65,11 @@ struct Prof {
 constexpr int kProfSlots = 8192;
 Prof g_prof;
 
+// set while an allocation-free call runs on this thread: no events are created for it
+thread_local bool g_prof_suspended = false;
+
 ProfRec* prof_begin(int stage, hipStream_t s, int k) {
-  if (!g_prof.on) return nullptr;
+  if (!g_prof.on || g_prof_suspended) return nullptr;
   ProfRec r{};
   r.stage = stage;
   r.k = k;
@@ -206,8 +209,10 @@ long long pstride_of(int k, const Batch& b) { return (long long)tri_rows(k) * b.
 // ---- plan cache (lock held by caller) ----
 int get_device(int* dev) { return to_status(hipGetDevice(dev)); }
 
-int ensure_leg(DevCache& dc) {
+// build = false: look up only; a missing table gives S2LET_ENOTREADY (nothing is allocated).
+int ensure_leg(DevCache& dc, bool build = true) {
   if (dc.leg.Lt == 0) {
+    if (!build) return S2LET_ENOTREADY;
     hipError_t e = build_leg_tables(S2LET_MAX_L, &dc.leg);
     if (e != hipSuccess) {
       free_leg_tables(&dc.leg);
@@ -217,9 +222,10 @@ int ensure_leg(DevCache& dc) {
   return S2LET_OK;
 }
 
-int ensure_sht(DevCache& dc, int k, ShtTables** out) {
+int ensure_sht(DevCache& dc, int k, ShtTables** out, bool build = true) {
   auto it = dc.sht.find(k);
   if (it == dc.sht.end()) {
+    if (!build) return S2LET_ENOTREADY;
     ShtTables T;
     hipError_t e = build_sht_tables(k, &T);
     if (e != hipSuccess) {
@@ -232,10 +238,11 @@ int ensure_sht(DevCache& dc, int k, ShtTables** out) {
   return S2LET_OK;
 }
 
-int ensure_wav(DevCache& dc, int L, int B, int J_min, int kernel, WavTables** out) {
+int ensure_wav(DevCache& dc, int L, int B, int J_min, int kernel, WavTables** out, bool build = true) {
   auto key = std::make_tuple(L, B, J_min, kernel);
   auto it = dc.wav.find(key);
   if (it == dc.wav.end()) {
+    if (!build) return S2LET_ENOTREADY;
     WavTables W;
     W.J = jmax_int(L, B);
     const int ns = W.J - J_min + 1;
@@ -544,9 +551,11 @@ S2LET_API int mw_forward_adjoint(void* f, const void* flm, int L, int reality, i
 // Map at L -> wavelet and scaling maps.  adjoint = false: the analysis, Eqs. (4) and (6).
 // adjoint = true: the adjoint of the synthesis of Eq. (8) (inverse-transform adjoint at L, the
 // real diagonal kernels and truncation, forward-transform adjoints at each scale).
+// build_plans = false: the plan tables must already be cached for this device (S2LET_ENOTREADY
+// otherwise), so that the call allocates nothing.
 int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min, int multires,
                              int reality, int precision, int nmaps, void* ws, size_t ws_bytes, void* stream,
-                             bool adjoint, int cap, int kernel) {
+                             bool adjoint, int cap, int kernel, bool build_plans) {
   if (!f_wav || !f_scal || !f || !aligned16(f_wav) || !aligned16(f_scal) || !aligned16(f))
     return S2LET_EINVAL;
   int st = check_wavelet(L, B, J_min, multires);
@@ -557,19 +566,20 @@ int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int
   if ((st = prologue(L, reality, precision, nmaps, ws, ws_bytes, true, &dev, cap)) != S2LET_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!build_plans && g_cache.find(dev) == g_cache.end()) return S2LET_ENOTREADY;
   DevCache& dc = g_cache[dev];
-  if ((st = ensure_leg(dc)) != S2LET_OK) return st;
+  if ((st = ensure_leg(dc, build_plans)) != S2LET_OK) return st;
   WavTables* W;
-  if ((st = ensure_wav(dc, L, B, J_min, kernel, &W)) != S2LET_OK) return st;
+  if ((st = ensure_wav(dc, L, B, J_min, kernel, &W, build_plans)) != S2LET_OK) return st;
   const int J = W->J;
   const int kP = bl_scal(J_min, L, B, multires, kernel);
   ShtTables *TL, *TP;
-  if ((st = ensure_sht(dc, L, &TL)) != S2LET_OK) return st;
-  if ((st = ensure_sht(dc, kP, &TP)) != S2LET_OK) return st;
+  if ((st = ensure_sht(dc, L, &TL, build_plans)) != S2LET_OK) return st;
+  if ((st = ensure_sht(dc, kP, &TP, build_plans)) != S2LET_OK) return st;
   std::vector<ShtTables*> TJ;
   for (int j = J_min; j <= J; ++j) {
     ShtTables* t;
-    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires, kernel), &t)) != S2LET_OK) return st;
+    if ((st = ensure_sht(dc, bl_wav(j, L, B, multires, kernel), &t, build_plans)) != S2LET_OK) return st;
     TJ.push_back(t);
   }
   const int bcap = cap > 0 ? std::min(cap, batch_cap(reality)) : batch_cap(reality);
@@ -677,7 +687,52 @@ S2LET_API int s2let_axisym_analysis(void* f_wav, void* f_scal, const void* f, in
                                     int multires, int reality, int precision, int nmaps, void* ws,
                                     size_t ws_bytes, void* stream) {
   return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, false, 0, S2LET_KERNEL_SD);
+                           stream, false, 0, S2LET_KERNEL_SD, true);
+}
+
+// ---- the allocation-free analysis ----
+// Its workspace is this file-scope device array: each device that loads the library holds its own
+// copy until the process ends.  Host code never uses the array's name as an address (on the host it
+// names a stand-in, not device memory); it uses the per-device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.
+static __device__ __align__(256) char scratch[S2LET_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::map<int, void*> g_scratch_addr;   // device -> that device's copy of scratch (under g_mu)
+
+// Clears the per-thread switch that keeps profiling events out of an allocation-free call.
+struct ProfSuspend {
+  ProfSuspend() { g_prof_suspended = true; }
+  ~ProfSuspend() { g_prof_suspended = false; }
+};
+}  // namespace
+
+S2LET_API int s2let_axisym_analysis_noalloc(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min,
+                                            int multires, int reality, int precision, int nmaps, void* stream) {
+  int st = check_common(reality, precision, nmaps);
+  if (st != S2LET_OK) return st;
+  if ((st = check_wavelet(L, B, J_min, multires)) != S2LET_OK) return st;
+  if (L > S2LET_MAX_L) return S2LET_EUNSUPPORTED;
+  const Batch b = make_batch(reality, std::min(nmaps, batch_cap(reality)));
+  const size_t need = ws_bytes_for(L, b.C, true);
+  if (need > (size_t)S2LET_NOALLOC_SCRATCH_BYTES) return S2LET_ESCRATCH;
+  int dev;
+  if ((st = get_device(&dev)) != S2LET_OK) return st;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || p == nullptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      it = g_scratch_addr.emplace(dev, p).first;
+    }
+    ws = it->second;
+  }
+  ProfSuspend quiet;
+  return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws,
+                                 (size_t)S2LET_NOALLOC_SCRATCH_BYTES, stream, false, 0, S2LET_KERNEL_SD, false);
 }
 
 S2LET_API int s2let_axisym_synthesis(void* f, const void* f_wav, const void* f_scal, int L, int B,
@@ -698,7 +753,7 @@ S2LET_API int s2let_axisym_synthesis_adjoint(void* f_wav, void* f_scal, const vo
                                              int multires, int reality, int precision, int nmaps, void* ws,
                                              size_t ws_bytes, void* stream) {
   return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                           stream, true, 0, S2LET_KERNEL_SD);
+                           stream, true, 0, S2LET_KERNEL_SD, true);
 }
 
 S2LET_API int s2let_bandlimit_wav_kernel(int j, int L, int B, int multires, int kernel) {
@@ -736,7 +791,7 @@ S2LET_API int s2let_axisym_analysis_kernel(void* f_wav, void* f_scal, const void
                                            int multires, int kernel, int reality, int precision, int nmaps,
                                            void* ws, size_t ws_bytes, void* stream) {
   return s2let_wav_map_to_scales(f_wav, f_scal, f, L, B, J_min, multires, reality, precision, nmaps, ws, ws_bytes,
-                                 stream, false, 0, kernel);
+                                 stream, false, 0, kernel, true);
 }
 
 S2LET_API int s2let_axisym_synthesis_kernel(void* f, const void* f_wav, const void* f_scal, int L, int B,
@@ -879,6 +934,10 @@ S2LET_API const char* s2let_strerror(int status) {
     case S2LET_ENOMEM: return "workspace too small or out of device memory";
     case S2LET_EHIP: return "HIP runtime error";
     case S2LET_EUNSUPPORTED: return "unsupported by this library (size or precision)";
+    case S2LET_ENOTREADY:
+      return "plan tables for these sizes are not built on this device yet (run the allocating call once first)";
+    case S2LET_ESCRATCH:
+      return "the call needs more workspace than the allocation-free entry point's static scratch holds";
   }
   return "unknown status";
 }

@@ -22,7 +22,7 @@
 // capped wavelet drivers of abi.cpp
 int s2let_wav_map_to_scales(void* f_wav, void* f_scal, const void* f, int L, int B, int J_min, int multires,
                             int reality, int precision, int nmaps, void* ws, size_t ws_bytes, void* stream,
-                            bool adjoint, int cap, int kernel);
+                            bool adjoint, int cap, int kernel, bool build_plans);
 int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int L, int B, int J_min,
                             int multires, int reality, int precision, int nmaps, void* ws, size_t ws_bytes,
                             void* stream, bool adjoint, int cap, int kernel);
@@ -123,7 +123,7 @@ int run(s2let_batch* b, void* f_wav, void* f_scal, void* rec, const void* f, voi
     double* rc = stage + g.st_rec;
     if ((st = copy_segments(b, (const double*)f, in, g.seg_first[0], n, s)) != S2LET_OK) return st;
     if ((st = s2let_wav_map_to_scales(wv, sc, in, g.L, g.B, b->J_min, b->multires, b->reality, b->precision, n,
-                                      wsg, b->ws_stream, s, false, b->cap, S2LET_KERNEL_SD)) != S2LET_OK)
+                                      wsg, b->ws_stream, s, false, b->cap, S2LET_KERNEL_SD, true)) != S2LET_OK)
       return st;
     if ((st = copy_segments(b, wv, (double*)f_wav, g.seg_first[1], n, s)) != S2LET_OK) return st;
     if ((st = copy_segments(b, sc, (double*)f_scal, g.seg_first[2], n, s)) != S2LET_OK) return st;

@@ -34,8 +34,9 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_strerror():
     assert b"gfx950" in s2.lib.s2let_version()
-    for st in (0, -1, -2, -3, -4):
+    for st in (0, -1, -2, -3, -4, -5, -6):
         assert len(s2.lib.s2let_strerror(st)) > 0
+        assert s2.lib.s2let_strerror(st) != b"unknown status"
 
 
 @pytest.mark.parametrize("L,B", [(3, 2), (4, 2), (5, 2), (64, 2), (65, 2), (66, 2), (128, 3), (2048, 2),
@@ -101,6 +102,14 @@ def test_invalid_arguments_rejected_without_device():
     assert a(buf, buf, buf, 64, 2, -1, 1, 0, 0, 1, ws, 1 << 40, None) == s2.EINVAL
     assert lib.s2let_j_max(2, 2) == s2.EINVAL and lib.s2let_j_max(10, 1) == s2.EINVAL
     assert lib.s2let_workspace_size(64, 2, 6, 1, 0, 0, 1, 1) == 0
+    # the allocation-free analysis validates the same way, then refuses inputs whose workspace
+    # exceeds its static scratch (16 real maps at L = 512), all before any device call
+    n = lib.s2let_axisym_analysis_noalloc
+    assert n(buf, buf, buf, 64, 2, 6, 1, 0, 0, 1, None) == s2.EINVAL
+    assert n(buf, buf, buf, 64, 2, 0, 1, 0, 9, 1, None) == s2.EINVAL
+    assert n(buf, buf, buf, 4096, 2, 3, 1, 0, 0, 1, None) == s2.EUNSUPPORTED
+    assert s2.workspace_size(512, 2, 2, True, s2.REAL, s2.FP64, 16, True) > s2.NOALLOC_SCRATCH_BYTES
+    assert n(buf, buf, buf, 512, 2, 2, 1, 0, 0, 16, None) == s2.ESCRATCH
 
 
 def test_workspace_size_monotone():

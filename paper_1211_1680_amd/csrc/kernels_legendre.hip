@@ -420,9 +420,29 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
 // s < k/2 (FP64, C >= 16).  With lambda_lm(pi - psi) = (-1)^(l+m) lambda_lm(psi), a degree of
 // even l+m meets the sum H(s) + H(k-1-s) of the theta stage's output and one of odd l+m the
 // difference, so every (l, m) runs the recursion and the contraction over k/2 nodes instead of
-// k.  A chunk starts at l0 = m + 32 i (16 i), so l+m has the parity of the step j within it;
-// the z tile keeps even steps in its first half and odd steps in its second.
+// k.  A chunk starts at l0 = m + 32 i (16 i), so l+m has the parity of the step j within it.
+//
+// Analysis.  Block: one m pair, one group of 512 northern nodes, 8 waves.  Each wave runs the
+// recursion for 64 nodes and writes a 32-degree chunk into a block-wide LDS tile Z[32][512] (even
+// steps in rows 0..15, odd steps in rows 16..31).  The contraction is divided by output tile
+// rather than by node: wave w owns the 16-column x 16-degree tile (column block ct, parity p) over
+// one slice of the 512 nodes (2 slices for C = 32, 4 for C = 16), with that slice's operands
+// (sums or differences of H) in registers.  So the cross-wave reduction adds 2 (4) partial tiles
+// per output instead of 8, and it runs while the next chunk's recursion fills Z.  Two barriers
+// per chunk: Z complete before the products; products done (Z free, partial tiles written)
+// before the next recursion.  Wave-uniform skips: a recursion wave whose 64 nodes are all below
+// 2^-1100 (or past k/2) flags the chunk, and the contraction skips its 16 k-steps.
 // ------------------------------------------------------------------------------------------
+constexpr int FS_NW = 8;                 // waves per block
+constexpr int FS_LC = 32;                // degrees per chunk (16 even + 16 odd)
+constexpr int FS_TB = FS_NW * 64;        // northern nodes per block
+constexpr int FS_PS = 18;                // partial-tile row stride (elements)
+// row stride of Z: (stride x row + k) mod (banks / element) distinct for the 16 rows x 4 nodes a
+// half-wave (FP64) or wave (FP32) reads per k-step
+template <typename T> struct FsZStride;
+template <> struct FsZStride<double> { static constexpr int v = FS_TB + 2; };
+template <> struct FsZStride<float> { static constexpr int v = FS_TB + 4; };
+
 template <int C, typename T>
 __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restrict__ HM, double* __restrict__ R,
                                                           long long part_stride,
@@ -434,35 +454,176 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
                                                           const double* __restrict__ st, int k, int Lt, int ng,
                                                           int lmin, unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
-  constexpr int RS = 2 * ((C / 2) | 1);
-  constexpr int ZBYTES = FWD_NW * FWD_LC * FWD_ZS * (int)sizeof(T);
-  constexpr int RBYTES = FWD_NW * FWD_LC * RS * (int)sizeof(double);
-  __shared__ __align__(16) char smem[ZBYTES > RBYTES ? ZBYTES : RBYTES];
-  T (*Z)[FWD_LC][FWD_ZS] = reinterpret_cast<T (*)[FWD_LC][FWD_ZS]>(smem);
-  double* red = reinterpret_cast<double*>(smem);
+  constexpr int NKS = FS_NW / (2 * CT);   // node slices per output tile
+  constexpr int KS = FS_TB / NKS;         // nodes per slice
+  constexpr int NK = KS / 4;              // k-steps per slice
+  constexpr int SRC = KS / 64;            // recursion waves per slice
+  constexpr int ZS = FsZStride<T>::v;
+  __shared__ __align__(16) T Z[FS_LC][ZS];
+  __shared__ __align__(16) T P[FS_NW][16][FS_PS];
+  __shared__ double2 coef[FS_NW][FS_LC];   // each wave's copy of a chunk's recursion coefficients
+  __shared__ int negl[FS_NW];              // recursion wave w contributes nothing to this chunk
   unsigned long long retained = 0;
   const int kh = k / 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
   const int pair = blockIdx.x / ng;
   const int grp = blockIdx.x % ng;
-  const int tile = grp * FWD_NW + w;
+  // recursion role: nodes grp*512 + w*64 + lane
+  const int tile = grp * FS_NW + w;
   const int t = tile * 64 + lane;
   const bool valid = t < kh;
   const bool tile_live = tile * 64 < kh;
+  const int nt = tile_live ? ((kh - tile * 64) < 64 ? (kh - tile * 64) : 64) : 0;
   const double u = valid ? ut[t] : -1.0;
   const double sg = 1.0;   // every node (and every idle lane) is northern
   const double s = valid ? st[t] : 1.0;
+  // contraction role: column block ct, parity p, node slice h
+  const int ct = w % CT, p = (w / CT) & 1, h = w / (2 * CT);
   const int nm = (k - 1 - pair > pair) ? 2 : 1;
   double* __restrict__ Rg = R + (size_t)grp * part_stride;
+  double2* cfl = coef[w];
+
+  // the output rows of one chunk: the slices' partial tiles added in order, one column pair per
+  // thread, 16-byte global stores
+  auto reduce = [&](int m, int l0) {
+    for (int idx = threadIdx.x; idx < FS_LC * C / 2; idx += FS_NW * 64) {
+      const int cp = idx % (C / 2), rest = idx / (C / 2);
+      const int r = rest & 15, pr = rest >> 4;
+      const int c = 2 * cp, ctt = c >> 4, cl = c & 15;
+      const int l = l0 + 2 * r + pr;
+      if (l < k) {
+        double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int hh = 0; hh < NKS; ++hh) {
+          const T* pt = &P[(hh * 2 + pr) * CT + ctt][r][cl];
+          sum.x += (double)pt[0];
+          sum.y += (double)pt[1];
+        }
+        *reinterpret_cast<double2*>(&Rg[(tri_off(k, m) + (l - m)) * C + c]) = sum;
+      }
+    }
+  };
 
   for (int im = 0; im < nm; ++im) {
     const int m = im == 0 ? pair : k - 1 - pair;
     const double* __restrict__ am = alpha + tri_off(Lt, m);
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Hm = HM + (size_t)m * k * C;
-    // operands: ap = H(s) + H(k-1-s) (even l+m), an = H(s) - H(k-1-s) (odd l+m); the layout is
-    // column-pair major, Hm[(cp*k + node)*2 + re/im]
+    // operands of this wave's tile: H(s) + H(k-1-s) (p = 0) or H(s) - H(k-1-s) (p = 1) at the slice's
+    // nodes; the theta stage stores them at nodes [0, k/2) and [k/2, k), column-pair major
+    T a[NK];
+    {
+      // k/2 is a multiple of 32 and the slice starts on a multiple of 128, so whether node
+      // base + 4 kk + lq exists does not depend on lq: nkv k-steps of the slice are in range
+      const int base = grp * FS_TB + h * KS;
+      const int nkv = kh <= base ? 0 : ((kh - base) / 4 < NK ? (kh - base) / 4 : NK);
+      const int c = ct * 16 + li;
+      const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1) + (p ? (size_t)kh * 2 : 0) +
+                          (size_t)(base + lq) * 2;
+      if (nkv == NK) {
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) a[kk] = (T)col[(size_t)kk * 8];
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) a[kk] = (T)(kk < nkv ? col[(size_t)kk * 8] : 0.0);
+      }
+    }
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cf = chunk_coef<FS_LC>(am, bm, 0, k - m, lane);
+    int lprev = -1;   // the chunk whose partial tiles wait to be reduced
+
+    for (int l0 = m; l0 < k; l0 += FS_LC) {
+      // below the degree floor: no products, and no rows of R (the caller reads none of them)
+      const bool below = l0 + FS_LC <= lmin;   // block-uniform
+      stage_coef<FS_LC>(cfl, cf, lane);
+      cf = chunk_coef<FS_LC>(am, bm, l0 + FS_LC - m, k - m, lane);   // the next chunk's, in flight
+      wave_lds_sync();
+      const bool ngw = !tile_live || __all(!valid || negligible(z1, z2, e));
+      if (below) {
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e, [](int, double) {});
+        continue;
+      }
+      // phase A: this chunk's recursion into Z, the previous chunk's reduction
+      recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
+                             [&](int j, double v) { Z[(j & 1) * 16 + (j >> 1)][w * 64 + lane] = (T)v; });
+      if (lane == 0) negl[w] = ngw;
+      if (!ngw) retained += (unsigned long long)((k - l0) < FS_LC ? (k - l0) : FS_LC) * nt;
+      if (lprev >= 0) reduce(m, lprev);
+      __syncthreads();   // Z holds the chunk; the previous partial tiles are read
+      // phase B: the products of this wave's tile
+      typename Mma<T>::acc_t acc0 = Mma<T>::zero(), acc1 = Mma<T>::zero();
+#pragma unroll
+      for (int sw = 0; sw < SRC; ++sw) {
+        if (negl[h * SRC + sw]) continue;   // wave-uniform
+#pragma unroll
+        for (int q = 0; q < 16; q += 2) {
+          const int kk = sw * 16 + q;
+          const T b0 = Z[p * 16 + li][h * KS + 4 * kk + lq];
+          const T b1 = Z[p * 16 + li][h * KS + 4 * kk + 4 + lq];
+          acc0 = Mma<T>::mma(a[kk], b0, acc0);
+          acc1 = Mma<T>::mma(a[kk + 1], b1, acc1);
+        }
+      }
+      // partial tile: register v holds column row(lq, v) of the tile, degree row li
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[w][li][Mma<T>::row(lq, v)] = acc0[v] + acc1[v];
+      __syncthreads();   // partial tiles written; every wave is done reading Z
+      lprev = l0;
+    }
+    if (lprev >= 0) reduce(m, lprev);
+  }
+  if (counter != nullptr && lane == 0 && retained > 0) atomicAdd(counter, retained);
+}
+
+// The same analysis with the FP32 contraction, organised by node instead: each wave multiplies
+// its own 64 nodes' z tile (wave-private, no barrier between recursion and products) into partial
+// sums of all 32 x C outputs, which the waves write to a double-buffered area and add up after one
+// barrier per chunk.  (The block-wide tile of the FP64 kernel, with one chain of FP32 products over
+// 256 nodes per tile, measured slower here and rounds more: FP32 sums of 64 products per partial
+// keep the error of this mode at a quarter of its bound.)
+constexpr int FWW_ZS = 66;      // z-tile row stride (elements): conflict-free B reads
+template <int C>
+__global__ __launch_bounds__(512) void k_legendre_fwd_sym_f32(const double* __restrict__ HM, double* __restrict__ R,
+                                                              long long part_stride,
+                                                              const double* __restrict__ alpha,
+                                                              const double* __restrict__ beta,
+                                                              const double* __restrict__ cm,
+                                                              const double* __restrict__ ut,
+                                                              const double* __restrict__ st, int k, int Lt, int ng,
+                                                              int lmin, unsigned long long* __restrict__ counter) {
+  typedef float T;
+  constexpr int CT = C / 16;
+  constexpr int RS = 2 * ((C / 2) | 1);
+  __shared__ __align__(16) T Z[FS_NW][FS_LC][FWW_ZS];
+  __shared__ __align__(16) T P[2][FS_NW][FS_LC][RS];
+  __shared__ double2 coef[FS_NW][FS_LC];
+  unsigned long long retained = 0;
+  const int kh = k / 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  double2* cfl = coef[w];
+  const int pair = blockIdx.x / ng;
+  const int grp = blockIdx.x % ng;
+  const int tile = grp * FS_NW + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < kh;
+  const bool tile_live = tile * 64 < kh;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = 1.0;
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  double* __restrict__ Rg = R + (size_t)grp * part_stride;
+  int nred = 0;   // chunks reduced so far (selects the partial-sum buffer)
+
+  for (int im = 0; im < nm; ++im) {
+    const int m = im == 0 ? pair : k - 1 - pair;
+    const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
+    const double* __restrict__ Hm = HM + (size_t)m * k * C;
+    // operands: ap = H(s) + H(k-1-s) (even l+m), an = H(s) - H(k-1-s) (odd l+m)
     T ap[16][CT], an[16][CT];
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
@@ -478,24 +639,24 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
     int e;
     double z1, z2;
     recur_start(cm[m], s, sg, m, z1, z2, e);
-    double cf_next = chunk_coef<FWD_LC>(am, bm, 0, k - m, lane);
+    double cf = chunk_coef<FS_LC>(am, bm, 0, k - m, lane);
 
-    for (int l0 = m; l0 < k; l0 += FWD_LC) {
+    for (int l0 = m; l0 < k; l0 += FS_LC) {
       typename Mma<T>::acc_t acc[2][CT];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<T>::zero();
-      // below the degree floor: no products, and no rows of R (the caller reads none of them)
-      const bool below = l0 + FWD_LC <= lmin;
+      const bool below = l0 + FS_LC <= lmin;
       const bool skip = !tile_live || below || __all(!valid || negligible(z1, z2, e));
-      const double cf = cf_next;
-      cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
-      recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e,
-                          [&](int j, double v) { Z[w][(j & 1) * (FWD_LC / 2) + (j >> 1)][lane] = (T)v; });
+      stage_coef<FS_LC>(cfl, cf, lane);
+      cf = chunk_coef<FS_LC>(am, bm, l0 + FS_LC - m, k - m, lane);   // the next chunk's, in flight
+      wave_lds_sync();
+      recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
+                             [&](int j, double v) { Z[w][(j & 1) * (FS_LC / 2) + (j >> 1)][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
-        const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
+        const int nl = (k - l0) < FS_LC ? (k - l0) : FS_LC;
         const int nt = (kh - tile * 64) < 64 ? (kh - tile * 64) : 64;
         retained += (unsigned long long)nl * (unsigned long long)nt;
 #pragma unroll
@@ -510,33 +671,29 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
         }
       }
       if (below) continue;   // block-uniform
-      __syncthreads();
+      const int pb = nred & 1;
 #pragma unroll
       for (int lt2 = 0; lt2 < 2; ++lt2)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int c = ct * 16 + Mma<T>::row(lq, v);
-            red[((size_t)w * FWD_LC + lt2 * 16 + li) * RS + c] = (double)acc[lt2][ct][v];
-          }
+          for (int v = 0; v < 4; ++v) P[pb][w][lt2 * 16 + li][ct * 16 + Mma<T>::row(lq, v)] = acc[lt2][ct][v];
       __syncthreads();
-      // one column pair per thread and step: 16-byte LDS reads and global stores
-      for (int idx = threadIdx.x; idx < FWD_LC * C / 2; idx += FWD_NW * 64) {
+      for (int idx = threadIdx.x; idx < FS_LC * C / 2; idx += FS_NW * 64) {
         const int lloc = idx / (C / 2), c = 2 * (idx % (C / 2));
         const int l = l0 + 2 * (lloc & 15) + (lloc >> 4);
         if (l < k) {
           double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int ww = 0; ww < FWD_NW; ++ww) {
-            const double2 v = *reinterpret_cast<const double2*>(&red[(ww * FWD_LC + lloc) * RS + c]);
-            sum.x += v.x;
-            sum.y += v.y;
+          for (int ww = 0; ww < FS_NW; ++ww) {
+            const float2 v = *reinterpret_cast<const float2*>(&P[pb][ww][lloc][c]);
+            sum.x += (double)v.x;
+            sum.y += (double)v.y;
           }
           *reinterpret_cast<double2*>(&Rg[(tri_off(k, m) + (l - m)) * C + c]) = sum;
         }
       }
-      __syncthreads();
+      ++nred;
     }
   }
   if (counter != nullptr && lane == 0 && retained > 0) atomicAdd(counter, retained);
@@ -627,6 +784,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
         for (int i = 0; i < PER; ++i)
           pre[i] = (l0 + INVM_LC + tr < k) ? Sm[(size_t)(l0 + INVM_LC - m + tr) * C + tc + i] : 0.0;
       }
+      // (coefficients by lane broadcasts: staging them in LDS, as the analysis does, measured slower
+      // here, where the z tile and the coefficient rows already load the LDS every chunk)
       const double cf = cf_next;
       cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
       recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e,
@@ -722,14 +881,14 @@ hipError_t launch_legendre_forward_sym(const ShtTables& T, const LegTables& G, c
   const dim3 grid(((k + 1) / 2) * ng), block(FWD_NW * 64);
   const bool f32 = precision == S2LET_MIXED_FP32;
   if (b.C == 32 && f32)
-    k_legendre_fwd_sym<32, float><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
-                                                         T.st_s, k, G.Lt, ng, lmin, counter);
+    k_legendre_fwd_sym_f32<32><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k,
+                                                      G.Lt, ng, lmin, counter);
   else if (b.C == 32)
     k_legendre_fwd_sym<32, double><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
                                                           T.st_s, k, G.Lt, ng, lmin, counter);
   else if (b.C == 16 && f32)
-    k_legendre_fwd_sym<16, float><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
-                                                         T.st_s, k, G.Lt, ng, lmin, counter);
+    k_legendre_fwd_sym_f32<16><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k,
+                                                      G.Lt, ng, lmin, counter);
   else if (b.C == 16)
     k_legendre_fwd_sym<16, double><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s,
                                                           T.st_s, k, G.Lt, ng, lmin, counter);

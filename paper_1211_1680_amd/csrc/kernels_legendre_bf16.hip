@@ -18,10 +18,30 @@ namespace s2let {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
+// x -> FP32 (round to nearest) -> bf16 hi and lo parts.  The empty asm statement keeps the FP32
+// value opaque, so the compiler rounds hi from it with one v_cvt_pk_bf16_f32 rather than fusing the
+// two conversions into a correctly rounded double -> bf16 sequence (nine more instructions).
+__device__ __forceinline__ float opaque_f32(float f) {
+  __asm__("" : "+v"(f));
+  return f;
+}
+
 __device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
-  const float f = (float)x;
+  const float f = opaque_f32((float)x);
   hi = (__bf16)f;
   lo = (__bf16)(f - (float)hi);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two values at once: hi = bf16(a, b) with one packed conversion, widened back by a shift and a
+// mask, lo = bf16 of the two exact FP32 residuals with a second packed conversion.
+__device__ __forceinline__ void split_bf16_pair(float a, float b, bf16x2& hi, bf16x2& lo) {
+  hi = __builtin_convertvector(f32x2{a, b}, bf16x2);
+  const unsigned hb = __builtin_bit_cast(unsigned, hi);
+  const float ha = __uint_as_float(hb << 16), hbf = __uint_as_float(hb & 0xffff0000u);
+  lo = __builtin_convertvector(f32x2{a - ha, b - hbf}, bf16x2);
 }
 
 __device__ __forceinline__ v4f mma_bf16(bf16x8 a, bf16x8 b, v4f c) {
@@ -308,9 +328,14 @@ __global__ __launch_bounds__(256) void k_legendre_inv_bf16(const double* __restr
 // The same two contractions on the northern half of the symmetric grid (see the FP64 kernels
 // k_legendre_fwd_sym / k_legendre_inv_sym): even l+m meets the north/south sums of the theta
 // stage, odd l+m the differences.
-// Analysis: as k_legendre_fwd_bf16 with two operand sets; z tile rows 0..15 hold the even steps
-// of the 32-degree chunk, rows 16..31 the odd steps.
+// Analysis: the block-wide, double-buffered z tile of k_legendre_fwd_sym_f32, in bf16 hi and lo
+// parts.  Each wave runs the recursion for 64 nodes (steps 2i and 2i+1 split together) into
+// Z[buf][hi/lo][row][node]; wave w owns the output tile (column block ct, parity p) over one node
+// slice, its operands split once per m; one barrier per chunk, FP32 partial tiles added in FP64.
 // ------------------------------------------------------------------------------------------
+constexpr int FBS_ZR = 520;   // Z row (bf16): 512 nodes + 8; the 16 rows a quarter-wave reads sit
+                              // 4 banks apart
+
 template <int C>
 __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __restrict__ HM,
                                                                double* __restrict__ R, long long part_stride,
@@ -321,139 +346,184 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
                                                                const double* __restrict__ st, int k, int Lt, int ng,
                                                                int lmin,
                                                                unsigned long long* __restrict__ counter) {
+  constexpr int NW = 8, LC = 32, TB = NW * 64, PS = 18;
   constexpr int CT = C / 16;
-  constexpr int RS = 2 * ((C / 2) | 1);
-  constexpr int ZBYTES = FB_NW * 2 * FB_LC * FB_ZR * 2;
-  constexpr int RBYTES = FB_NW * FB_LC * RS * (int)sizeof(double);
-  __shared__ __align__(16) char smem[ZBYTES > RBYTES ? ZBYTES : RBYTES];
-  __bf16 (*Zt)[2][FB_LC][FB_ZR] = reinterpret_cast<__bf16 (*)[2][FB_LC][FB_ZR]>(smem);
-  double* red = reinterpret_cast<double*>(smem);
+  constexpr int NKS = NW / (2 * CT);   // node slices per output tile
+  constexpr int KS = TB / NKS;         // nodes per slice
+  constexpr int NB = KS / 32;          // 32-node k-blocks per slice
+  constexpr int SRC = KS / 64;         // recursion waves per slice (2 k-blocks each)
+  __shared__ __align__(16) __bf16 Z[2][2][LC][FBS_ZR];
+  __shared__ __align__(16) float P[2][NW][16][PS];
+  __shared__ double2 coef[NW][LC];
+  __shared__ int negl[2][NW];
   unsigned long long retained = 0;
   const int kh = k / 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
   const int pair = blockIdx.x / ng;
   const int grp = blockIdx.x % ng;
-  const int tile = grp * FB_NW + w;
+  const int tile = grp * NW + w;
   const int t = tile * 64 + lane;
   const bool valid = t < kh;
   const bool tile_live = tile * 64 < kh;
+  const int nt = tile_live ? ((kh - tile * 64) < 64 ? (kh - tile * 64) : 64) : 0;
   const double u = valid ? ut[t] : -1.0;
   const double sg = 1.0;
   const double s = valid ? st[t] : 1.0;
+  const int ct = w % CT, p = (w / CT) & 1, h = w / (2 * CT);
   const int nm = (k - 1 - pair > pair) ? 2 : 1;
   double* __restrict__ Rg = R + (size_t)grp * part_stride;
+  double2* cfl = coef[w];
+
+  auto reduce = [&](int pb, int m, int l0) {
+    for (int idx = threadIdx.x; idx < LC * C / 2; idx += NW * 64) {
+      const int cp = idx % (C / 2), rest = idx / (C / 2);
+      const int r = rest & 15, pr = rest >> 4;
+      const int c = 2 * cp, ctt = c >> 4, cl = c & 15;
+      const int l = l0 + 2 * r + pr;
+      if (l < k) {
+        double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int hh = 0; hh < NKS; ++hh) {
+          const float2 v = *reinterpret_cast<const float2*>(&P[pb][(hh * 2 + pr) * CT + ctt][r][cl]);
+          sum.x += (double)v.x;
+          sum.y += (double)v.y;
+        }
+        *reinterpret_cast<double2*>(&Rg[(tri_off(k, m) + (l - m)) * C + c]) = sum;
+      }
+    }
+  };
 
   for (int im = 0; im < nm; ++im) {
     const int m = im == 0 ? pair : k - 1 - pair;
     const double* __restrict__ am = alpha + tri_off(Lt, m);
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Hm = HM + (size_t)m * k * C;
-    // element e of a*[kb][ct]: node tile*64 + 32 kb + 8 lq + e, column ct*16 + li (column-pair major)
-    bf16x8 aph[2][CT], apl[2][CT], anh[2][CT], anl[2][CT];
+    // operands: element e of ah/al[kb] = node base + 32 kb + 8 lq + e, column ct*16 + li, the sums
+    // (p = 0) or differences (p = 1) the theta stage stores at nodes [0, k/2) / [k/2, k)
+    bf16x8 ah[NB], al[NB];
+    {
+      const int base = grp * TB + h * KS;
+      const int c = ct * 16 + li;
+      const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1) + (p ? (size_t)kh * 2 : 0);
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
+      for (int kb = 0; kb < NB; ++kb) {
+        // k/2 is a multiple of 32: a k-block is in range or not as a whole
+        const bool in = base + 32 * kb < kh;
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int tg = tile * 64 + 32 * kb + 8 * lq + e;
-          const int c = ct * 16 + li;
-          const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1);
-          const double hp = tg < kh ? col[(size_t)tg * 2] : 0.0;
-          const double hn = tg < kh ? col[(size_t)(kh + tg) * 2] : 0.0;
-          __bf16 hi, lo;
-          split_bf16(hp, hi, lo);
-          aph[kb][ct][e] = hi;
-          apl[kb][ct][e] = lo;
-          split_bf16(hn, hi, lo);
-          anh[kb][ct][e] = hi;
-          anl[kb][ct][e] = lo;
+        for (int e2 = 0; e2 < 8; e2 += 2) {
+          const size_t tg = (size_t)(base + 32 * kb + 8 * lq + e2);
+          const float f0 = opaque_f32((float)(in ? col[tg * 2] : 0.0));
+          const float f1 = opaque_f32((float)(in ? col[(tg + 1) * 2] : 0.0));
+          bf16x2 hi, lo;
+          split_bf16_pair(f0, f1, hi, lo);
+          ah[kb][e2] = hi.x;
+          ah[kb][e2 + 1] = hi.y;
+          al[kb][e2] = lo.x;
+          al[kb][e2 + 1] = lo.y;
         }
+      }
+    }
     int e;
     double z1, z2;
     recur_start(cm[m], s, sg, m, z1, z2, e);
-    double cf_next = chunk_coef<FB_LC>(am, bm, 0, k - m, lane);
+    // chunk c of this m starts at degree m + 32 c; its z values go to Z[c & 1]
+    auto recur_into = [&](int c, int l0c) {
+      const bool fill = l0c + LC > lmin;
+      const bool ngw = !tile_live || __all(!valid || negligible(z1, z2, e));
+      if (fill) {
+        const int zb = c & 1;
+        float fe = 0.f;
+        recur_chunk_lds<LC>(cfl, u, sg, z1, z2, e, [&](int j, double v) {
+          const float f = opaque_f32((float)v);
+          if ((j & 1) == 0) {
+            fe = f;
+            return;
+          }
+          bf16x2 hi, lo;
+          split_bf16_pair(fe, f, hi, lo);
+          const int i = j >> 1;
+          Z[zb][0][i][w * 64 + lane] = hi.x;
+          Z[zb][0][16 + i][w * 64 + lane] = hi.y;
+          Z[zb][1][i][w * 64 + lane] = lo.x;
+          Z[zb][1][16 + i][w * 64 + lane] = lo.y;
+        });
+        if (lane == 0) negl[zb][w] = ngw;
+        if (!ngw) retained += (unsigned long long)((k - l0c) < LC ? (k - l0c) : LC) * nt;
+      } else {
+        recur_chunk_lds<LC>(cfl, u, sg, z1, z2, e, [](int, double) {});
+      }
+    };
+    double cf = chunk_coef<LC>(am, bm, 0, k - m, lane);
+    stage_coef<LC>(cfl, cf, lane);
+    cf = chunk_coef<LC>(am, bm, LC, k - m, lane);
+    wave_lds_sync();
+    recur_into(0, m);
+    wave_lds_sync();
+    stage_coef<LC>(cfl, cf, lane);   // chunk 1
+    cf = chunk_coef<LC>(am, bm, 2 * LC, k - m, lane);
+    if (m + LC > lmin) __syncthreads();
 
-    for (int l0 = m; l0 < k; l0 += FB_LC) {
-      v4f acc[2][CT];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = v4f{0.f, 0.f, 0.f, 0.f};
-      // below the degree floor: no products, and no rows of R (the caller reads none of them)
-      const bool below = l0 + FB_LC <= lmin;
-      const bool skip = !tile_live || below || __all(!valid || negligible(z1, z2, e));
-      const double cf = cf_next;
-      cf_next = chunk_coef<FB_LC>(am, bm, l0 + FB_LC - m, k - m, lane);
-      recur_chunk<FB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
-        __bf16 hi, lo;
-        split_bf16(v, hi, lo);
-        const int row = (j & 1) * (FB_LC / 2) + (j >> 1);
-        Zt[w][0][row][lane] = hi;
-        Zt[w][1][row][lane] = lo;
-      });
-      if (!skip) {
+    int ci = 0;
+    for (int l0 = m; l0 < k; l0 += LC, ++ci) {
+      const bool below = l0 + LC <= lmin;   // block-uniform
+      const int l1 = l0 + LC;
+      const bool has_next = l1 < k;
+      const bool fill_next = has_next && l1 + LC > lmin;
+      if (has_next) {
         wave_lds_sync();
-        const int nl = (k - l0) < FB_LC ? (k - l0) : FB_LC;
-        const int nt = (kh - tile * 64) < 64 ? (kh - tile * 64) : 64;
-        retained += (unsigned long long)nl * (unsigned long long)nt;
+        recur_into(ci + 1, l1);
+      }
+      if (!below) {
+        v4f acc0 = v4f{0.f, 0.f, 0.f, 0.f}, acc1 = v4f{0.f, 0.f, 0.f, 0.f};
+        const int zb = ci & 1;
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-          const bf16x8 b0h = *reinterpret_cast<const bf16x8*>(&Zt[w][0][li][32 * kb + 8 * lq]);
-          const bf16x8 b0l = *reinterpret_cast<const bf16x8*>(&Zt[w][1][li][32 * kb + 8 * lq]);
-          const bf16x8 b1h = *reinterpret_cast<const bf16x8*>(&Zt[w][0][16 + li][32 * kb + 8 * lq]);
-          const bf16x8 b1l = *reinterpret_cast<const bf16x8*>(&Zt[w][1][16 + li][32 * kb + 8 * lq]);
+        for (int sw = 0; sw < SRC; ++sw) {
+          if (negl[zb][h * SRC + sw]) continue;   // wave-uniform
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            acc[0][ct] = mma3(aph[kb][ct], apl[kb][ct], b0h, b0l, acc[0][ct]);
-            acc[1][ct] = mma3(anh[kb][ct], anl[kb][ct], b1h, b1l, acc[1][ct]);
+          for (int q = 0; q < 2; ++q) {
+            const int kb = 2 * sw + q;
+            const int col = h * KS + 32 * kb + 8 * lq;
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Z[zb][0][p * 16 + li][col]);
+            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Z[zb][1][p * 16 + li][col]);
+            if (q == 0)
+              acc0 = mma3(ah[kb], al[kb], bh, bl, acc0);
+            else
+              acc1 = mma3(ah[kb], al[kb], bh, bl, acc1);
           }
         }
+        if (l0 - LC >= m && l0 > lmin) reduce((ci - 1) & 1, m, l0 - LC);
+        // register v holds column 4 lq + v of the tile, degree row li
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[zb][w][li][4 * lq + v] = acc0[v] + acc1[v];
       }
-      if (below) continue;   // block-uniform
-      __syncthreads();
-#pragma unroll
-      for (int lt = 0; lt < 2; ++lt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int c = ct * 16 + 4 * lq + v;
-            red[((size_t)w * FB_LC + lt * 16 + li) * RS + c] = (double)acc[lt][ct][v];
-          }
-      __syncthreads();
-      // one column pair per thread and step: 16-byte LDS reads and global stores
-      for (int idx = threadIdx.x; idx < FB_LC * C / 2; idx += FB_NW * 64) {
-        const int lloc = idx / (C / 2), c = 2 * (idx % (C / 2));
-        const int l = l0 + 2 * (lloc & 15) + (lloc >> 4);
-        if (l < k) {
-          double2 sum = make_double2(0.0, 0.0);
-#pragma unroll
-          for (int ww = 0; ww < FB_NW; ++ww) {
-            const double2 v = *reinterpret_cast<const double2*>(&red[(ww * FB_LC + lloc) * RS + c]);
-            sum.x += v.x;
-            sum.y += v.y;
-          }
-          *reinterpret_cast<double2*>(&Rg[(tri_off(k, m) + (l - m)) * C + c]) = sum;
-        }
+      if (has_next) {
+        wave_lds_sync();
+        stage_coef<LC>(cfl, cf, lane);   // chunk ci + 2
+        cf = chunk_coef<LC>(am, bm, l1 + 2 * LC - m, k - m, lane);
       }
-      __syncthreads();
+      if (!below || fill_next) __syncthreads();
     }
+    {
+      const int nch = (k - m + LC - 1) / LC;
+      const int llast = m + (nch - 1) * LC;
+      if (llast + LC > lmin) reduce((nch - 1) & 1, m, llast);
+    }
+    __syncthreads();   // the next m overwrites Z, P and the flags
   }
   if (counter != nullptr && lane == 0 && retained > 0) atomicAdd(counter, retained);
 }
 
 // Synthesis: 64-degree chunks, so that one v_mfma_f32_16x16x32_bf16 contracts the 32 even or the
-// 32 odd degrees; z tile row per node [even hi 32 | odd hi 32 | even lo 32 | odd lo 32 | 8 pad];
-// FP32 partial sums (32 terms per chunk and parity) carried into the FP64 north and south sums
-// every IBS_FLUSH chunks.
+// 32 odd degrees; z tile row per node [even hi 32 | odd hi 32 | even lo 32 | odd lo 32 | 8 pad].
+// The even and odd sums accumulate in FP32 over the whole column m: the split products carry a
+// relative error near 2^-16 each, which FP32 accumulation (2^-24 per addition) does not change,
+// and without FP64 running sums the kernel fits two blocks per CU.
 constexpr int IBS_LC = 64;
 constexpr int IBS_ZR = 136;
-constexpr int IBS_FLUSH = 2;
 
 template <int C>
-__global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* __restrict__ S,
+__global__ __launch_bounds__(256, 2) void k_legendre_inv_bf16_sym(const double* __restrict__ S,
                                                                   double* __restrict__ FS,
                                                                   const double* __restrict__ alpha,
                                                                   const double* __restrict__ beta,
@@ -464,6 +534,7 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
                                                                   unsigned long long* __restrict__ counter) {
   constexpr int CT = C / 16;
   __shared__ __align__(16) __bf16 Z[4][64][IBS_ZR];
+  __shared__ double2 coef[4][IBS_LC];   // each wave's copy of the chunk's recursion coefficients
   const int kh = k / 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
@@ -484,22 +555,18 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
     const double* __restrict__ bm = beta + tri_off(Lt, m);
     const double* __restrict__ Sm = S + tri_off(k, m) * C;
     v4f accE[4][CT], accO[4][CT];
-    double accN[4][CT][4], accS[4][CT][4];
 #pragma unroll
     for (int g = 0; g < 4; ++g)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         accE[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
         accO[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) accN[g][ct][v] = accS[g][ct][v] = 0.0;
       }
-    int since_flush = 0;
     int e;
     double z1, z2;
     recur_start(cm[m], s, sg, m, z1, z2, e);
-    double cfa_next = chunk_coef<32>(am, bm, 0, k - m, lane);
-    double cfb_next = chunk_coef<32>(am, bm, 32, k - m, lane);
+    double cfa = chunk_coef<32>(am, bm, 0, k - m, lane);
+    double cfb = chunk_coef<32>(am, bm, 32, k - m, lane);
     // coefficient rows of the chunk: even degree l0 + 2 (8 lq + q), odd l0 + 2 (8 lq + q) + 1
     double bn[2][CT][8];
 #pragma unroll
@@ -536,24 +603,30 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
               bn[par][ct][q] = l < k ? Sm[(size_t)(l - m) * C + ct * 16 + li] : 0.0;
             }
       }
-      const double cfa = cfa_next, cfb = cfb_next;
-      cfa_next = chunk_coef<32>(am, bm, l0 + IBS_LC - m, k - m, lane);
-      cfb_next = chunk_coef<32>(am, bm, l0 + IBS_LC + 32 - m, k - m, lane);
-      // z values: 4 consecutive even (odd) steps per 8-byte store of hi and lo parts
+      stage_coef<32>(coef[w], cfa, lane);
+      stage_coef<32>(coef[w] + 32, cfb, lane);
+      cfa = chunk_coef<32>(am, bm, l0 + IBS_LC - m, k - m, lane);   // the next chunk's, in flight
+      cfb = chunk_coef<32>(am, bm, l0 + IBS_LC + 32 - m, k - m, lane);
+      wave_lds_sync();
+      // z values: steps 2i and 2i+1 split together; 4 consecutive even (odd) steps per 8-byte store
+      // of hi and lo parts
       bf16x4 peh, pel, poh, pol;
+      float fe = 0.f;
       auto sink = [&](int base) {
         return [&, base](int j, double v) {
           const int jj = base + j;
-          __bf16 hi, lo;
-          split_bf16(v, hi, lo);
-          const int i = jj >> 1;   // position within the parity half
-          if (jj & 1) {
-            poh[i & 3] = hi;
-            pol[i & 3] = lo;
-          } else {
-            peh[i & 3] = hi;
-            pel[i & 3] = lo;
+          const float f = opaque_f32((float)v);
+          if ((jj & 1) == 0) {
+            fe = f;
+            return;
           }
+          bf16x2 hi, lo;
+          split_bf16_pair(fe, f, hi, lo);
+          const int i = jj >> 1;   // position within the parity half
+          peh[i & 3] = hi.x;
+          poh[i & 3] = hi.y;
+          pel[i & 3] = lo.x;
+          pol[i & 3] = lo.y;
           if ((jj & 7) == 7) {
             *reinterpret_cast<bf16x4*>(&Z[w][lane][i - 3]) = peh;
             *reinterpret_cast<bf16x4*>(&Z[w][lane][32 + i - 3]) = poh;
@@ -562,8 +635,8 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
           }
         };
       };
-      recur_chunk<32>(cfa, u, sg, z1, z2, e, sink(0));
-      recur_chunk<32>(cfb, u, sg, z1, z2, e, sink(32));
+      recur_chunk_lds<32>(coef[w], u, sg, z1, z2, e, sink(0));
+      recur_chunk_lds<32>(coef[w] + 32, u, sg, z1, z2, e, sink(32));
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < IBS_LC ? (k - l0) : IBS_LC;
@@ -581,22 +654,6 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
             accO[g][ct] = mma3(zoh, zol, bh[1][ct], bl[1][ct], accO[g][ct]);
           }
         }
-        if (++since_flush == IBS_FLUSH) {
-          since_flush = 0;
-#pragma unroll
-          for (int g = 0; g < 4; ++g)
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const double E = (double)accE[g][ct][v], O = (double)accO[g][ct][v];
-                accN[g][ct][v] += E + O;
-                accS[g][ct][v] += E - O;
-              }
-              accE[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
-              accO[g][ct] = v4f{0.f, 0.f, 0.f, 0.f};
-            }
-        }
       }
       wave_lds_sync();
     }
@@ -612,8 +669,8 @@ __global__ __launch_bounds__(256, 1) void k_legendre_inv_bf16_sym(const double* 
             const int c = ct * 16 + li;
             double* col = FS + ((size_t)m * C + (c & ~1)) * k + (c & 1);
             const double E = (double)accE[g][ct][v], O = (double)accO[g][ct][v];
-            col[(size_t)tt * 2] = accN[g][ct][v] + (E + O);
-            col[(size_t)(k - 1 - tt) * 2] = accS[g][ct][v] + (E - O);
+            col[(size_t)tt * 2] = E + O;
+            col[(size_t)(k - 1 - tt) * 2] = E - O;
           }
         }
       }

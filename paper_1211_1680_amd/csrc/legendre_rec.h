@@ -76,16 +76,41 @@ __device__ __forceinline__ double chunk_coef(const double* __restrict__ am, cons
   return (lane < 2 * LC && i < len) ? p[i] : 0.0;
 }
 
+// Where a step's recursion coefficients (alpha_l, beta_l) come from.  RegCoef: one register per
+// lane (lane j < LC holds alpha, lane LC + j beta, as chunk_coef loads them), broadcast with
+// v_readlane (four per step, plus two moves to put beta in a vector register).  LdsCoef: a
+// wave-private LDS copy of the chunk as (alpha, beta) pairs, one broadcast 16-byte LDS load per
+// step (every lane the same address) and no further vector instructions.
+template <int LC>
+struct RegCoef {
+  double cf;
+  __device__ __forceinline__ double2 operator()(int j) const {
+    return make_double2(readlane_d(cf, j), readlane_d(cf, LC + j));
+  }
+};
+struct LdsCoef {
+  const double2* cfl;
+  __device__ __forceinline__ double2 operator()(int j) const { return cfl[j]; }
+};
+
+// Writes one chunk's coefficients, as chunk_coef loaded them, to a wave-private LDS buffer of
+// LC (alpha, beta) pairs; the caller orders it before the reads with wave_lds_sync().
+template <int LC>
+__device__ __forceinline__ void stage_coef(double2* cfl, double cf, int lane) {
+  if (lane < 2 * LC) reinterpret_cast<double*>(cfl)[2 * (lane % LC) + (lane >= LC ? 1 : 0)] = cf;
+}
+
 // One chunk of the difference recursion: degrees l0 .. l0 + LC - 1; the z value of step j
 // (scaled by 2^e) goes to sink(j, value).  The state enters as (z_{l0-1}, E_{l0-1}).  SIGN = +1 / -1: every lane of the
 // wave is in the northern / southern hemisphere (s uniform, folded into the operations);
 // SIGN = 0: mixed.  SCALED = false: every lane has e = 0 (no scaling, no renormalisation).
-template <int LC, int SIGN, bool SCALED, typename Sink>
-__device__ __forceinline__ void recur_steps(double cf, double u, double sg, double& z1, double& z2, int& e,
+template <int LC, int SIGN, bool SCALED, typename Coef, typename Sink>
+__device__ __forceinline__ void recur_steps(const Coef& coef, double u, double sg, double& z1, double& z2, int& e,
                                             Sink& sink) {
 #pragma unroll
   for (int j = 0; j < LC; ++j) {
-    const double g = fma(readlane_d(cf, j), u, readlane_d(cf, LC + j));
+    const double2 ab = coef(j);
+    const double g = fma(ab.x, u, ab.y);
     if (SIGN > 0) {
       z2 = fma(g, z1, z2);
       z1 = z1 + z2;
@@ -101,23 +126,36 @@ __device__ __forceinline__ void recur_steps(double cf, double u, double sg, doub
   }
 }
 
-template <int LC, typename Sink>
-__device__ __forceinline__ void recur_chunk(double cf, double u, double sg, double& z1, double& z2, int& e,
-                                            Sink&& sink) {
+template <int LC, typename Coef, typename Sink>
+__device__ __forceinline__ void recur_chunk_with(const Coef& coef, double u, double sg, double& z1, double& z2,
+                                                 int& e, Sink&& sink) {
   const bool scaled = !__all(e == 0);
   if (__all(sg > 0.0)) {
     if (scaled)
-      recur_steps<LC, 1, true>(cf, u, sg, z1, z2, e, sink);
+      recur_steps<LC, 1, true>(coef, u, sg, z1, z2, e, sink);
     else
-      recur_steps<LC, 1, false>(cf, u, sg, z1, z2, e, sink);
+      recur_steps<LC, 1, false>(coef, u, sg, z1, z2, e, sink);
   } else if (__all(sg < 0.0)) {
     if (scaled)
-      recur_steps<LC, -1, true>(cf, u, sg, z1, z2, e, sink);
+      recur_steps<LC, -1, true>(coef, u, sg, z1, z2, e, sink);
     else
-      recur_steps<LC, -1, false>(cf, u, sg, z1, z2, e, sink);
+      recur_steps<LC, -1, false>(coef, u, sg, z1, z2, e, sink);
   } else {
-    recur_steps<LC, 0, true>(cf, u, sg, z1, z2, e, sink);
+    recur_steps<LC, 0, true>(coef, u, sg, z1, z2, e, sink);
   }
+}
+
+template <int LC, typename Sink>
+__device__ __forceinline__ void recur_chunk(double cf, double u, double sg, double& z1, double& z2, int& e,
+                                            Sink&& sink) {
+  recur_chunk_with<LC>(RegCoef<LC>{cf}, u, sg, z1, z2, e, sink);
+}
+
+// The same with the chunk's coefficients staged in LDS (see LdsCoef).
+template <int LC, typename Sink>
+__device__ __forceinline__ void recur_chunk_lds(const double2* cfl, double u, double sg, double& z1, double& z2,
+                                                int& e, Sink&& sink) {
+  recur_chunk_with<LC>(LdsCoef{cfl}, u, sg, z1, z2, e, sink);
 }
 
 // Start of the recursion one degree early: z_{m-1} = 0 and E = s z_m, so that the first step

@@ -227,6 +227,17 @@ int s2let_hard_threshold(void* f_wav, const double* thresholds, int L, int B, in
  *   The graph stays bound to the buffers given at capture; changing the configuration
  *   (autotune) discards it. */
 typedef struct s2let_batch s2let_batch;
+/* Execution modes of a batch plan.  S2LET_BATCH_STREAMS: every (L, B) group runs the batched drivers
+ * on a worker stream.  S2LET_BATCH_PERSISTENT (FP64 only): the job runs level by level over every map
+ * and scale; the Legendre steps of a level (analysis at L, the inverse transforms of all scales, the
+ * forward transforms of all scales, synthesis at L) are work items (batch of up to 32 columns,
+ * scale, m pair, node group) sorted by decreasing cost and taken by one persistent launch per tile
+ * shape.  Tile shape: waves (64 northern nodes each) per block, 1, 2 or 4, chosen per band-limit
+ * bucket k = 64, 128, ..., 2048 (index log2(k) - 6) separately for the analysis and the synthesis
+ * kernels; a shape must not exceed the bucket's nodes (64 w <= k/2 rounded up to 64) nor give more
+ * than 4 node groups (k/2 <= 256 w).  Band-limits outside the buckets (the scales below 64 and
+ * those that are not powers of two) run per transform on the worker streams. */
+enum { S2LET_BATCH_STREAMS = 0, S2LET_BATCH_PERSISTENT = 1 };
 int s2let_batch_create(s2let_batch** plan, int nmaps, const int* L, const int* B, int J_min, int multires,
                        int reality, int precision);
 int s2let_batch_destroy(s2let_batch* plan);
@@ -243,6 +254,16 @@ int s2let_batch_autotune(s2let_batch* plan, void* f_wav, void* f_scal, void* rec
 int s2let_batch_graph_capture(s2let_batch* plan, void* f_wav, void* f_scal, void* rec, const void* f,
                               void* ws, size_t ws_bytes, void* stream);
 int s2let_batch_graph_launch(s2let_batch* plan, void* stream);
+/* s2let_batch_set_execution: selects the mode; nw_analysis / nw_synthesis (6 entries each, or NULL
+ *   to keep the current ones) are the persistent mode's tile shapes.  EUNSUPPORTED for the persistent
+ *   mode with a mixed precision, EINVAL for a shape outside the rules above.  Discards a captured graph.
+ * s2let_batch_get_execution: the current mode, worker streams, maps per batch and tile shapes (any
+ *   pointer may be NULL; the shape arrays take 6 entries).  s2let_batch_autotune also tries the
+ *   persistent mode (FP64), choosing each used bucket's shapes by timing, and keeps whichever mode
+ *   is faster. */
+int s2let_batch_set_execution(s2let_batch* plan, int mode, const int* nw_analysis, const int* nw_synthesis);
+int s2let_batch_get_execution(const s2let_batch* plan, int* mode, int* nstreams, int* maps_per_batch,
+                              int* nw_analysis, int* nw_synthesis);
 
 /* Measurement support.  s2let_profile_enable(1) clears previous records and, until
  * s2let_profile_enable(0), brackets every kernel launch of the calls above with a pair of HIP

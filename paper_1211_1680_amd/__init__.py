@@ -17,7 +17,7 @@ __all__ = [
     "REAL", "COMPLEX", "FP64", "MIXED_FP32", "MIXED_BF16X3", "MAX_L", "S2letError", "lib",
     "j_max", "bandlimit_wav", "bandlimit_scal", "mw_size", "wav_size", "tiling_axisym",
     "workspace_size", "mw_forward", "mw_inverse", "analysis", "synthesis", "split_wav", "sync",
-    "analysis_noalloc", "NOALLOC_SCRATCH_BYTES",
+    "analysis_noalloc", "NOALLOC_SCRATCH_BYTES", "BATCH_STREAMS", "BATCH_PERSISTENT",
     "mw_forward_adjoint", "mw_inverse_adjoint", "analysis_adjoint", "synthesis_adjoint",
     "BatchPlan", "profile_enable", "profile_query", "STAGES",
     "KERNEL_SD", "KERNEL_BSPLINE", "KERNEL_NEEDLET", "noise_std", "hard_threshold", "denoise",
@@ -28,6 +28,7 @@ FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
 KERNEL_SD, KERNEL_BSPLINE, KERNEL_NEEDLET = 0, 1, 2
 MAX_L = 2048
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENOTREADY, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
+BATCH_STREAMS, BATCH_PERSISTENT = 0, 1
 NOALLOC_SCRATCH_BYTES = 64 << 20   # S2LET_NOALLOC_SCRATCH_BYTES
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -82,6 +83,8 @@ def _load():
                                      ctypes.POINTER(ctypes.c_float)]),
         "s2let_batch_graph_capture": (i, [vp, vp, vp, vp, vp, vp, sz, vp]),
         "s2let_batch_graph_launch": (i, [vp, vp]),
+        "s2let_batch_set_execution": (i, [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "s2let_batch_get_execution": (i, [vp] + [ctypes.POINTER(i)] * 5),
         "s2let_bandlimit_wav_kernel": (i, [i, i, i, i, i]),
         "s2let_bandlimit_scal_kernel": (i, [i, i, i, i, i]),
         "s2let_wav_size_kernel": (i64, [i, i, i, i, i]),
@@ -528,6 +531,29 @@ class BatchPlan:
                                          f.data_ptr(), *self._ws(), _stream(self.device), ctypes.byref(s_),
                                          ctypes.byref(c_), ctypes.byref(ms)), "s2let_batch_autotune")
         return s_.value, c_.value, ms.value
+
+    def set_execution(self, mode: int, nw_analysis=None, nw_synthesis=None):
+        """Streams or persistent mode; tile shapes (waves per block) for the band-limit buckets
+        64, 128, ..., 2048 (6 entries each, None keeps the current ones)."""
+        def arr(v):
+            if v is None:
+                return None
+            v = [int(x) for x in v]
+            if len(v) != 6:
+                raise ValueError("one tile shape per band-limit bucket (6) is needed")
+            return (ctypes.c_int * 6)(*v)
+        self._captured = None
+        _check(_lib.s2let_batch_set_execution(self._h, int(mode), arr(nw_analysis), arr(nw_synthesis)),
+               "s2let_batch_set_execution")
+
+    def execution(self):
+        """{'mode', 'streams', 'maps_per_batch', 'nw_analysis', 'nw_synthesis'} of the current plan."""
+        mo, ns, mp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        fa, sy = (ctypes.c_int * 6)(), (ctypes.c_int * 6)()
+        _check(_lib.s2let_batch_get_execution(self._h, ctypes.byref(mo), ctypes.byref(ns), ctypes.byref(mp), fa, sy),
+               "s2let_batch_get_execution")
+        return {"mode": "persistent" if mo.value == BATCH_PERSISTENT else "streams", "streams": ns.value,
+                "maps_per_batch": mp.value, "nw_analysis": list(fa), "nw_synthesis": list(sy)}
 
     def capture(self, f, out):
         """Capture run(f, out) into a HIP graph on the current (non-default) stream.  The graph

@@ -414,6 +414,43 @@ int64_t wav_size_int(int L, int B, int J_min, int multires, int kernel = S2LET_K
 }
 
 }  // namespace
+
+// Plan tables of the current device for the uneven-batch executor (built on first use; the cache
+// keeps them at stable addresses until s2let_finalize).
+int cached_leg(const LegTables** G) {
+  int dev, st;
+  if ((st = get_device(&dev)) != S2LET_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevCache& dc = g_cache[dev];
+  if ((st = ensure_leg(dc)) != S2LET_OK) return st;
+  *G = &dc.leg;
+  return S2LET_OK;
+}
+
+int cached_sht(int k, const ShtTables** T) {
+  int dev, st;
+  if ((st = get_device(&dev)) != S2LET_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevCache& dc = g_cache[dev];
+  ShtTables* t;
+  if ((st = ensure_sht(dc, k, &t)) != S2LET_OK) return st;
+  *T = t;
+  return S2LET_OK;
+}
+
+int cached_wav(int L, int B, int J_min, const double** kappa, const double** eta, std::vector<int>* lmin) {
+  int dev, st;
+  if ((st = get_device(&dev)) != S2LET_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevCache& dc = g_cache[dev];
+  WavTables* W;
+  if ((st = ensure_wav(dc, L, B, J_min, S2LET_KERNEL_SD, &W)) != S2LET_OK) return st;
+  *kappa = W->kappa;
+  *eta = W->eta;
+  *lmin = W->lmin;
+  return S2LET_OK;
+}
+
 }  // namespace s2let
 
 using namespace s2let;

@@ -170,6 +170,31 @@ hipError_t launch_legendre_forward_bf16(const ShtTables& T, const LegTables& G, 
 hipError_t launch_legendre_inverse_bf16(const ShtTables& T, const LegTables& G, const Batch& b,
                                         const double* S, double* FT, unsigned long long* counter,
                                         hipStream_t s);
+// ---- persistent Legendre launches over the work items of many transforms (uneven batches) ----
+// One task is one symmetric-grid Legendre step of one batch of 32 columns at band-limit k; one item is
+// one (m pair, node group) of a task.  A launch's blocks take items in the order given (the caller
+// sorts them by decreasing cost) from a device counter until none is left.
+struct LegTask {
+  const double* in;       // HM (analysis) or S (synthesis), layouts as launch_legendre_*_sym
+  double* out;            // R (analysis: node group g's partial sums at out + g * part_stride) or FS
+  const double* ut;       // the symmetric-grid tables of band-limit k
+  const double* st;
+  long long part_stride;
+  int k, lmin;
+};
+struct LegItem {
+  int task, pair, sub;    // sub: node group of nw x 64 northern nodes
+};
+// Tile shapes: nw waves (64 northern nodes each) per block, 1, 2 or 4; a task at band-limit k has
+// legendre_persist_groups(k, nw) node groups per m pair.
+int legendre_persist_groups(int k, int nw);
+bool legendre_persist_shape_ok(bool analysis, int nw);
+// Resident blocks per CU of the persistent kernel (for the grid size), 0 if unknown.
+int legendre_persist_blocks_per_cu(bool analysis, int nw);
+// FP64, 32 columns.  next: one device counter, reset by the launch (a kernel, no memset).
+hipError_t launch_legendre_persist(bool analysis, int nw, const LegTask* tasks, const LegItem* items, int nitems,
+                                   unsigned* next, const LegTables& G, int nblocks, hipStream_t s);
+
 // Records e as the HIP error behind the status and returns S2LET_EHIP (defined with the C ABI).
 int hip_fail(hipError_t e);
 int to_status(hipError_t e);

@@ -702,37 +702,31 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym_f32(const double* __re
 // Synthesis: E(s) = sum over even l+m, O(s) = sum over odd l+m of z_l(psi_s) S[l][c] on the
 // northern nodes; F(psi_s) = E + O and F(psi_{k-1-s}) = E - O, written column-pair major,
 // FS[((m*(C/2) + c/2)*k + s)*2 + c%2], s < k (read by the resampling to the MW nodes).
-template <int C, typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sym(const double* __restrict__ S, double* __restrict__ FS,
-                                                          const double* __restrict__ alpha,
-                                                          const double* __restrict__ beta,
-                                                          const double* __restrict__ cm,
-                                                          const double* __restrict__ ut,
-                                                          const double* __restrict__ sx,
-                                                          const double* __restrict__ st, int k, int Lt, int ntb,
-                                                          int lmin, unsigned long long* __restrict__ counter) {
+template <int C, int NW, typename T>
+__device__ __forceinline__ void inv_sym_body(const double* __restrict__ S, double* __restrict__ FS,
+                                             const double* __restrict__ alpha, const double* __restrict__ beta,
+                                             const double* __restrict__ cm, const double* __restrict__ ut,
+                                             const double* __restrict__ st, int k, int Lt, int pair, int tb,
+                                             int lmin, unsigned long long& retained) {
   constexpr int CT = C / 16;
   constexpr bool F64 = sizeof(T) == sizeof(double);
   // the coefficient rows of a chunk, loaded once per block (the four waves share them) into a
   // double-buffered tile; row stride 40 doubles puts the rows a half wave reads (2 apart) 16
   // banks apart
   constexpr int SBS = 40;
-  constexpr int PER = INVM_LC * C / 256;   // doubles per thread per chunk (2 for C = 32)
-  __shared__ T Z[4][INVM_LC][INVM_ZS];
+  constexpr int PER = INVM_LC * C / (NW * 64);   // doubles per thread per chunk (2 for C = 32, NW = 4)
+  __shared__ T Z[NW][INVM_LC][INVM_ZS];
   __shared__ double Sb[2][INVM_LC][SBS];
   const int kh = k / 2;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
-  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int pair = spread_pairs(blk / ntb, (k + 1) / 2);
-  const int tile = (blk % ntb) * 4 + w;
+  const int tile = tb * NW + w;
   const int t = tile * 64 + lane;
   const bool valid = t < kh;
   const double u = valid ? ut[t] : -1.0;
   const double sg = 1.0;
   const double s = valid ? st[t] : 1.0;
   const int nm = (k - 1 - pair > pair) ? 2 : 1;
-  unsigned long long retained = 0;
 
   for (int im = 0; im < nm; ++im) {
     const int m = im == 0 ? pair : k - 1 - pair;
@@ -862,9 +856,25 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sy
         }
       }
   }
+}
+
+
+template <int C, typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 1) void k_legendre_inv_sym(const double* __restrict__ S, double* __restrict__ FS,
+                                                          const double* __restrict__ alpha,
+                                                          const double* __restrict__ beta,
+                                                          const double* __restrict__ cm,
+                                                          const double* __restrict__ ut,
+                                                          const double* __restrict__ sx,
+                                                          const double* __restrict__ st, int k, int Lt, int ntb,
+                                                          int lmin, unsigned long long* __restrict__ counter) {
+  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+  unsigned long long retained = 0;
+  inv_sym_body<C, 4, T>(S, FS, alpha, beta, cm, ut, st, k, Lt, spread_pairs(blk / ntb, (k + 1) / 2), blk % ntb, lmin,
+                        retained);
   if (counter != nullptr) {
     for (int off = 32; off > 0; off >>= 1) retained += __shfl_down(retained, off);
-    if (lane == 0 && retained > 0) atomicAdd(counter, retained);
+    if ((threadIdx.x & 63) == 0 && retained > 0) atomicAdd(counter, retained);
   }
 }
 
@@ -920,6 +930,206 @@ hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, c
                                                           G.Lt, ntb, lmin, counter);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Persistent launches for uneven batches: the items of many transforms (band-limits 64 to 2048)
+// in one launch.  The analysis body is the node-organised form (each wave multiplies its own 64
+// nodes' z tile into partial sums of all 32 x C outputs; the partial sums of the block's nw
+// waves overwrite their z tiles and are added in order), which works for any number of waves per
+// block; the synthesis body is inv_sym_body.  Blocks take items from a device counter.
+// ------------------------------------------------------------------------------------------
+template <int C, int NW>
+__device__ __forceinline__ void fwd_sym_wave_body(const double* __restrict__ HM, double* __restrict__ R,
+                                                  long long part_stride, const double* __restrict__ alpha,
+                                                  const double* __restrict__ beta, const double* __restrict__ cm,
+                                                  const double* __restrict__ ut, const double* __restrict__ st,
+                                                  int k, int Lt, int pair, int grp, int lmin,
+                                                  unsigned long long& retained) {
+  typedef double T;
+  constexpr int CT = C / 16;
+  constexpr int RS = 2 * ((C / 2) | 1);
+  static_assert(RS <= FWW_ZS, "a wave's partial sums must fit in its z tile");
+  __shared__ __align__(16) T Z[NW][FS_LC][FWW_ZS];
+  __shared__ double2 coef[NW][FS_LC];
+  const int kh = k / 2;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  double2* cfl = coef[w];
+  const int tile = grp * NW + w;
+  const int t = tile * 64 + lane;
+  const bool valid = t < kh;
+  const bool tile_live = tile * 64 < kh;
+  const double u = valid ? ut[t] : -1.0;
+  const double sg = 1.0;
+  const double s = valid ? st[t] : 1.0;
+  const int nm = (k - 1 - pair > pair) ? 2 : 1;
+  double* __restrict__ Rg = R + (size_t)grp * part_stride;
+
+  for (int im = 0; im < nm; ++im) {
+    const int m = im == 0 ? pair : k - 1 - pair;
+    const double* __restrict__ am = alpha + tri_off(Lt, m);
+    const double* __restrict__ bm = beta + tri_off(Lt, m);
+    const double* __restrict__ Hm = HM + (size_t)m * k * C;
+    T ap[16][CT], an[16][CT];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int tg = tile * 64 + 4 * kk + lq;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int c = ct * 16 + li;
+        const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1);
+        ap[kk][ct] = tg < kh ? col[(size_t)tg * 2] : 0.0;
+        an[kk][ct] = tg < kh ? col[(size_t)(kh + tg) * 2] : 0.0;
+      }
+    }
+    int e;
+    double z1, z2;
+    recur_start(cm[m], s, sg, m, z1, z2, e);
+    double cf = chunk_coef<FS_LC>(am, bm, 0, k - m, lane);
+
+    for (int l0 = m; l0 < k; l0 += FS_LC) {
+      typename Mma<T>::acc_t acc[2][CT];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[x][ct] = Mma<T>::zero();
+      const bool below = l0 + FS_LC <= lmin;
+      const bool skip = !tile_live || below || __all(!valid || negligible(z1, z2, e));
+      stage_coef<FS_LC>(cfl, cf, lane);
+      cf = chunk_coef<FS_LC>(am, bm, l0 + FS_LC - m, k - m, lane);
+      wave_lds_sync();
+      recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
+                             [&](int j, double v) { Z[w][(j & 1) * (FS_LC / 2) + (j >> 1)][lane] = v; });
+      if (!skip) {
+        wave_lds_sync();
+        const int nl = (k - l0) < FS_LC ? (k - l0) : FS_LC;
+        const int nt = (kh - tile * 64) < 64 ? (kh - tile * 64) : 64;
+        retained += (unsigned long long)nl * (unsigned long long)nt;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          const int tl = 4 * kk + lq;
+          const T b0 = Z[w][li][tl], b1 = Z[w][16 + li][tl];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) {
+            acc[0][ct] = Mma<T>::mma(ap[kk][ct], b0, acc[0][ct]);
+            acc[1][ct] = Mma<T>::mma(an[kk][ct], b1, acc[1][ct]);
+          }
+        }
+      }
+      if (below) continue;   // block-uniform
+      wave_lds_sync();       // this wave's reads of its z tile are done
+      T* Pw = &Z[w][0][0];
+#pragma unroll
+      for (int lt2 = 0; lt2 < 2; ++lt2)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Pw[(lt2 * 16 + li) * RS + ct * 16 + Mma<T>::row(lq, v)] = acc[lt2][ct][v];
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < FS_LC * C / 2; idx += NW * 64) {
+        const int lloc = idx / (C / 2), c = 2 * (idx % (C / 2));
+        const int l = l0 + 2 * (lloc & 15) + (lloc >> 4);
+        if (l < k) {
+          double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int ww = 0; ww < NW; ++ww) {
+            const double2 v = *reinterpret_cast<const double2*>(&Z[ww][0][0] + lloc * RS + c);
+            sum.x += v.x;
+            sum.y += v.y;
+          }
+          *reinterpret_cast<double2*>(&Rg[(tri_off(k, m) + (l - m)) * C + c]) = sum;
+        }
+      }
+      __syncthreads();   // the next chunk's recursion overwrites the partial sums
+    }
+  }
+}
+
+__global__ void k_reset_u32(unsigned* __restrict__ p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// Takes the next item index for the whole block (thread 0 draws it, the barriers publish it and
+// keep it until every thread has read it).
+__device__ __forceinline__ int next_item(unsigned* __restrict__ next) {
+  __shared__ int s_item;
+  __syncthreads();
+  if (threadIdx.x == 0) s_item = (int)atomicAdd(next, 1u);
+  __syncthreads();
+  return s_item;
+}
+
+// (two waves per SIMD: at most 256 registers, whatever the block size)
+template <int C, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_fwd_persist(const LegTask* __restrict__ tasks,
+                                                                  const LegItem* __restrict__ items, int nitems,
+                                                                  unsigned* __restrict__ next,
+                                                                  const double* __restrict__ alpha,
+                                                                  const double* __restrict__ beta,
+                                                                  const double* __restrict__ cm, int Lt) {
+  unsigned long long retained = 0;
+  for (int it = next_item(next); it < nitems; it = next_item(next)) {
+    const LegItem I = items[it];
+    const LegTask T = tasks[I.task];
+    fwd_sym_wave_body<C, NW>(T.in, T.out, T.part_stride, alpha, beta, cm, T.ut, T.st, T.k, Lt, I.pair, I.sub, T.lmin,
+                             retained);
+  }
+}
+
+template <int C, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_legendre_inv_persist(const LegTask* __restrict__ tasks,
+                                                                  const LegItem* __restrict__ items, int nitems,
+                                                                  unsigned* __restrict__ next,
+                                                                  const double* __restrict__ alpha,
+                                                                  const double* __restrict__ beta,
+                                                                  const double* __restrict__ cm, int Lt) {
+  unsigned long long retained = 0;
+  for (int it = next_item(next); it < nitems; it = next_item(next)) {
+    const LegItem I = items[it];
+    const LegTask T = tasks[I.task];
+    inv_sym_body<C, NW, double>(T.in, T.out, alpha, beta, cm, T.ut, T.st, T.k, Lt, I.pair, I.sub, T.lmin, retained);
+  }
+}
+
+int legendre_persist_groups(int k, int nw) { return (k / 2 + nw * 64 - 1) / (nw * 64); }
+
+bool legendre_persist_shape_ok(bool, int nw) { return nw == 1 || nw == 2 || nw == 4; }
+
+int legendre_persist_blocks_per_cu(bool analysis, int nw) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define S2LET_OCC(NWV)                                                                                       \
+  if (nw == NWV)                                                                                             \
+    e = analysis ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_legendre_fwd_persist<32, NWV>, NWV * 64, 0) \
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_legendre_inv_persist<32, NWV>, NWV * 64, 0);
+  S2LET_OCC(1)
+  S2LET_OCC(2)
+  S2LET_OCC(4)
+#undef S2LET_OCC
+  return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_legendre_persist(bool analysis, int nw, const LegTask* tasks, const LegItem* items, int nitems,
+                                   unsigned* next, const LegTables& G, int nblocks, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (!legendre_persist_shape_ok(analysis, nw) || nblocks < 1) return hipErrorInvalidValue;
+  k_reset_u32<<<1, 64, 0, s>>>(next, 1);
+  const dim3 grid(nblocks), block(nw * 64);
+  if (analysis) {
+    switch (nw) {
+      case 1: k_legendre_fwd_persist<32, 1><<<grid, block, 0, s>>>(tasks, items, nitems, next, G.alpha, G.beta, G.cm, G.Lt); break;
+      case 2: k_legendre_fwd_persist<32, 2><<<grid, block, 0, s>>>(tasks, items, nitems, next, G.alpha, G.beta, G.cm, G.Lt); break;
+      default: k_legendre_fwd_persist<32, 4><<<grid, block, 0, s>>>(tasks, items, nitems, next, G.alpha, G.beta, G.cm, G.Lt); break;
+    }
+  } else {
+    switch (nw) {
+      case 1: k_legendre_inv_persist<32, 1><<<grid, block, 0, s>>>(tasks, items, nitems, next, G.alpha, G.beta, G.cm, G.Lt); break;
+      case 2: k_legendre_inv_persist<32, 2><<<grid, block, 0, s>>>(tasks, items, nitems, next, G.alpha, G.beta, G.cm, G.Lt); break;
+      default: k_legendre_inv_persist<32, 4><<<grid, block, 0, s>>>(tasks, items, nitems, next, G.alpha, G.beta, G.cm, G.Lt); break;
+    }
+  }
   return hipGetLastError();
 }
 

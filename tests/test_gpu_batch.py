@@ -140,3 +140,130 @@ def test_uneven_batching_workload(dev):
         assert _rel(plan.map_view(f_scal, i, "scal").cpu().numpy(), scal_ref[0], floor) < 1e-10
         assert _rel(plan.map_view(rec, i).cpu().numpy(), oin[i]) < 1e-10
     plan.close()
+
+
+# ------------------------------------------------------------------ persistent (level) execution
+def _run_both(plan, f):
+    """(streams outputs, persistent outputs) of one plan on the same input."""
+    plan.set_execution(s2.BATCH_STREAMS)
+    ref = [t.clone() for t in plan.run(f)]
+    plan.set_execution(s2.BATCH_PERSISTENT)
+    got = plan.run(f)
+    torch.cuda.synchronize()
+    return ref, got
+
+
+@pytest.mark.parametrize("shapes", [None, (1, 1, 1, 1, 2, 4), (1, 1, 2, 4, 4, 4)])
+def test_persistent_matches_streams_and_oracle(dev, shapes):
+    """Band-limits on the symmetric grid (64, 128, 256: persistent items) and off it (16, 48, 96;
+    scales 2..32 and the B = 3 scales 9, 27, 81: per-transform kernels), real maps, in the
+    persistent mode with the default and forced tile shapes: every output equals the streams mode
+    (1e-12) and sampled maps the oracle (1e-10)."""
+    rng = np.random.default_rng(7)
+    params = [(int(rng.choice([16, 48, 64, 96, 128, 256])), int(rng.choice([2, 3])), 2.0) for _ in range(22)]
+    params[0] = (64, 2, 2.0)
+    params[1] = (128, 3, 2.0)
+    J_min = 1
+    plan = s2.BatchPlan([p[0] for p in params], [p[1] for p in params], J_min)
+    f, oin = _maps(params, 300, False, dev, oracle_idx={0, 1, 2})
+    if shapes is not None:
+        plan.set_execution(s2.BATCH_PERSISTENT, shapes, [min(x, 4) for x in shapes])
+        cfg = plan.execution()
+        assert cfg["nw_analysis"] == list(shapes)
+    ref, got = _run_both(plan, f)
+    _log("  execution: %s" % plan.execution())
+    for a, b in zip(got, ref):
+        assert _rel(a.cpu().numpy(), b.cpu().numpy(), 1e-300) < 1e-12
+    for i in (0, 1, 2):
+        L, B, _ = params[i]
+        wav_ref, scal_ref = oracle.analysis(oin[i], L, B, J_min, True, True)
+        floor = 1e-6 * float(np.max(np.abs(oin[i])))
+        for g, r in zip(plan.map_view(got[0], i, "wav"), wav_ref):
+            assert _rel(g.cpu().numpy(), r[0], floor) < 1e-10
+        assert _rel(plan.map_view(got[1], i, "scal").cpu().numpy(), scal_ref[0], floor) < 1e-10
+        assert _rel(plan.map_view(got[2], i).cpu().numpy(), oin[i]) < 1e-10
+    plan.close()
+
+
+def test_persistent_complex_maps(dev):
+    params = [(64, 2), (128, 2), (33, 3), (64, 3), (128, 2)]
+    J_min = 1
+    plan = s2.BatchPlan([p[0] for p in params], [p[1] for p in params], J_min, reality=s2.COMPLEX)
+    flat, oin = [], {}
+    for i, (L, B) in enumerate(params):
+        flm = si.random_flm(L, 1, reality=False, seed=500 + i)
+        fi = oracle.inverse_sht(flm, L, reality=False)[0]
+        oin[i] = fi
+        flat.append(torch.from_numpy(fi.reshape(-1)).to(dev))
+    f = torch.cat(flat)
+    ref, got = _run_both(plan, f)
+    for a, b in zip(got, ref):
+        assert _rel(a.cpu().numpy(), b.cpu().numpy(), 1e-300) < 1e-12
+    L, B = params[1]
+    wav_ref, _ = oracle.analysis(oin[1], L, B, J_min, True, False)
+    for g, r in zip(plan.map_view(got[0], 1, "wav"), wav_ref):
+        assert _rel(g.cpu().numpy(), r[0]) < 1e-10
+    plan.close()
+
+
+def test_persistent_graph_replay_and_errors(dev):
+    rng = np.random.default_rng(8)
+    params = [(int(rng.choice([32, 64, 128])), int(rng.choice([2, 3])), 1.5) for _ in range(12)]
+    plan = s2.BatchPlan([p[0] for p in params], [p[1] for p in params], 1)
+    f, _ = _maps(params, 90, False, dev)
+    # invalid tile shapes: 4 waves at band-limit 64 (k/2 = 32 nodes), 3 waves anywhere
+    with pytest.raises(s2.S2letError):
+        plan.set_execution(s2.BATCH_PERSISTENT, [4, 1, 1, 1, 1, 1], None)
+    with pytest.raises(s2.S2letError):
+        plan.set_execution(s2.BATCH_PERSISTENT, None, [1, 1, 3, 1, 1, 1])
+    plan.set_execution(s2.BATCH_PERSISTENT)
+    out = plan.outputs()
+    eager = [t.clone() for t in plan.run(f, out)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(f, out)
+        for rep in range(3):
+            for t in out:
+                t.zero_()
+            plan.replay()
+            s.synchronize()
+            for a, b in zip(out, eager):
+                assert torch.equal(a, b), "graph replay %d differs from the eager run" % rep
+            _ = s2.mw_forward(plan.map_view(f, 0).unsqueeze(0).contiguous(), params[0][0], s2.REAL)
+            s.synchronize()
+    plan.close()
+    # the persistent mode is FP64 only
+    mixed = s2.BatchPlan([64, 64], [2, 2], 1, precision=s2.MIXED_FP32)
+    with pytest.raises(s2.S2letError):
+        mixed.set_execution(s2.BATCH_PERSISTENT)
+    mixed.close()
+
+
+def test_uneven_batching_workload_persistent(dev):
+    """The uneven-batching workload in the persistent mode (autotuned tile shapes): every map
+    reconstructed; one map per (L, B) group against the oracle on every ring."""
+    params = si.uniform_batch_params(seed=2, nmaps=256)
+    J_min = 1
+    firsts = {}
+    for i, (L, B, _) in enumerate(params):
+        firsts.setdefault((L, B), i)
+    plan = s2.BatchPlan([p[0] for p in params], [p[1] for p in params], J_min)
+    f, oin = _maps(params, 1000, True, dev, oracle_idx=set(firsts.values()))
+    out = plan.outputs()
+    plan.autotune(f, out)
+    plan.set_execution(s2.BATCH_PERSISTENT)   # keeps the tuned shapes
+    _log("  execution: %s" % plan.execution())
+    f_wav, f_scal, rec = plan.run(f, out)
+    torch.cuda.synchronize()
+    for i, (L, B, _) in enumerate(params):
+        e = _rel(plan.map_view(rec, i).cpu().numpy(), plan.map_view(f, i).cpu().numpy())
+        assert e < 1e-12, (i, L, B, e)
+    for (L, B), i in sorted(firsts.items()):
+        _log("  map %d (L=%d, B=%d): oracle analysis" % (i, L, B))
+        wav_ref, scal_ref = oracle.analysis(oin[i], L, B, J_min, True, True)
+        floor = 1e-6 * float(np.max(np.abs(oin[i])))
+        for g, r in zip(plan.map_view(f_wav, i, "wav"), wav_ref):
+            assert _rel(g.cpu().numpy(), r[0], floor) < 1e-10
+        assert _rel(plan.map_view(f_scal, i, "scal").cpu().numpy(), scal_ref[0], floor) < 1e-10
+        assert _rel(plan.map_view(rec, i).cpu().numpy(), oin[i]) < 1e-10
+    plan.close()

@@ -440,7 +440,7 @@ constexpr int FS_PS = 18;                // partial-tile row stride (elements)
 // row stride of Z: (stride x row + k) mod (banks / element) distinct for the 16 rows x 4 nodes a
 // half-wave (FP64) or wave (FP32) reads per k-step
 template <typename T> struct FsZStride;
-template <> struct FsZStride<double> { static constexpr int v = FS_TB + 2; };
+template <> struct FsZStride<double> { static constexpr int v = FS_TB + 3; };
 template <> struct FsZStride<float> { static constexpr int v = FS_TB + 4; };
 
 template <int C, typename T>

@@ -41,10 +41,10 @@ PEAK_HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {
     # the Legendre kernels' sources; the counters are reported only while these files are unchanged
     "sources": ["paper_1211_1680_amd/csrc/kernels_legendre.hip", "paper_1211_1680_amd/csrc/legendre_rec.h"],
-    "sha256": "259d3fd468e21cd8db1592a37485bddd196d04c1fa4e3c78a909c707a90bc7d0",
+    "sha256": "0fbbadce0bfd450630a7de260d6d7c805626734ae1e91ff9ee51098c84655b28",
     # k = 2048 launches of k_legendre_fwd_sym<32, double> / k_legendre_inv_sym<32, double>:
     # FETCH_SIZE + WRITE_SIZE, copy-calibrated (profiles/wavelet_L2048_16maps_fp64_hbm_traffic.txt)
-    "bytes_per_launch": {"legendre_analysis": 2.2557e+09, "legendre_synthesis": 1.8185e+09},
+    "bytes_per_launch": {"legendre_analysis": 2.1101e+09, "legendre_synthesis": 1.8008e+09},
 }
 
 

@@ -12,6 +12,12 @@ namespace s2let {
 
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
 constexpr int lds_padded(int n) { return n + (n >> 3) + 1; }
+// LDS slot of element i of a transform: padded for the power-of-two FFTs, whose strided writes
+// would otherwise share banks; plain for the odd-length DFT, whose strides (its radices) are odd
+// and whose sub-transform counts are not multiples of 8, so that pad slots would split groups of 8
+// consecutive lanes across two LDS cycles
+template <bool PAD>
+__device__ __forceinline__ int lds_at(int i) { return PAD ? lds_pad(i) : i; }
 
 // Input of the theta stage for an even order mE and the odd order mE + 1 of one column pair:
 // ring r < K of both orders, r = lt + i T.  Every gather is issued before the first one is
@@ -20,7 +26,7 @@ constexpr int lds_padded(int n) { return n + (n >> 3) + 1; }
 // Ring t of one phi problem into LDS slots q < N: REAL packs map ma (real part) and map ma + 1
 // (imaginary part, zero without it); otherwise map ma is complex.  Every load is issued before
 // the first store.
-template <int N, int T, int REAL>
+template <int N, int T, int REAL, bool PAD = true>
 __device__ __forceinline__ void load_ring(const double* __restrict__ f, long long map_stride, int ma, bool hasb,
                                           int t, bool valid, double2* buf, int lt) {
   constexpr int PER = (N + T - 1) / T;
@@ -39,7 +45,7 @@ __device__ __forceinline__ void load_ring(const double* __restrict__ f, long lon
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int q = lt + i * T;
-    if (q < N) buf[lds_pad(q)] = valid ? z[i] : make_double2(0.0, 0.0);
+    if (q < N) buf[lds_at<PAD>(q)] = valid ? z[i] : make_double2(0.0, 0.0);
   }
 }
 
@@ -47,7 +53,7 @@ __device__ __forceinline__ void load_ring(const double* __restrict__ f, long lon
 // slot N - m (0 < m < K) order -m.  REAL: the unit packs maps ma and ma + 1 as a + i b, with the
 // negative orders their conjugates; otherwise columns 4 ma .. 4 ma + 3 hold orders +m and -m of
 // map ma.  Each row is read once for both slots, and every load is issued before the first store.
-template <int K, int T, int REAL>
+template <int K, int T, int REAL, bool PAD = true>
 __device__ __forceinline__ void load_orders(const double* __restrict__ FT, int C, int ma, bool hasb, int t,
                                             bool valid, double2* buf, int lt) {
   constexpr int N = 2 * K - 1;
@@ -71,11 +77,11 @@ __device__ __forceinline__ void load_orders(const double* __restrict__ FT, int C
     const double2 a = valid ? ra[i] : make_double2(0.0, 0.0);
     const double2 b = valid ? rb[i] : make_double2(0.0, 0.0);
     if (REAL) {
-      buf[lds_pad(m)] = make_double2(a.x - b.y, a.y + b.x);
-      if (m > 0) buf[lds_pad(N - m)] = make_double2(a.x + b.y, b.x - a.y);
+      buf[lds_at<PAD>(m)] = make_double2(a.x - b.y, a.y + b.x);
+      if (m > 0) buf[lds_at<PAD>(N - m)] = make_double2(a.x + b.y, b.x - a.y);
     } else {
-      buf[lds_pad(m)] = a;
-      if (m > 0) buf[lds_pad(N - m)] = b;
+      buf[lds_at<PAD>(m)] = a;
+      if (m > 0) buf[lds_at<PAD>(N - m)] = b;
     }
   }
 }
@@ -106,15 +112,15 @@ __device__ __forceinline__ void dft_small(double2* v) {
 // One pass: N points, radix R, NS = product of the radices of the earlier passes, T threads.
 // The twiddle tables hold W_{N TS}^p (TS > 1: a shorter transform with the tables of a longer one).
 // LM / SM: bit r clear = input r of every butterfly is known to be zero (not loaded) / output r is
-// not needed (not stored).
+// not needed (not stored).  PAD: the slot layout (lds_at).
 // inputs j + r N/R of butterfly j of a pass, with the pass's twiddles applied
-template <int N, int R, int NS, bool INV, int TS, unsigned LM>
+template <int N, int R, int NS, bool INV, int TS, unsigned LM, bool PAD = true>
 __device__ __forceinline__ void ct_gather(const double2* buf, int j, double2* v, const double2* wlo,
                                           const double2* whi) {
   constexpr int NB = N / R;
   constexpr int STRIDE = N / (NS * R);
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = ((LM >> r) & 1u) ? buf[lds_pad(j + r * NB)] : make_double2(0.0, 0.0);
+  for (int r = 0; r < R; ++r) v[r] = ((LM >> r) & 1u) ? buf[lds_at<PAD>(j + r * NB)] : make_double2(0.0, 0.0);
   if constexpr (NS > 1) {
     const int p = (j % NS) * STRIDE * TS;
     double2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
@@ -128,7 +134,8 @@ __device__ __forceinline__ void ct_gather(const double2* buf, int j, double2* v,
   }
 }
 
-template <int N, int R, int NS, bool INV, int T, int TS = 1, unsigned LM = 0xFFFFu, unsigned SM = 0xFFFFu>
+template <int N, int R, int NS, bool INV, int T, int TS = 1, unsigned LM = 0xFFFFu, unsigned SM = 0xFFFFu,
+          bool PAD = true>
 __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo, const double2* whi) {
   constexpr int NB = N / R;
   constexpr int PER = (NB + T - 1) / T;
@@ -137,7 +144,7 @@ __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = lt + i * T;
-    if (j < NB) ct_gather<N, R, NS, INV, TS, LM>(buf, j, v[i], wlo, whi);
+    if (j < NB) ct_gather<N, R, NS, INV, TS, LM, PAD>(buf, j, v[i], wlo, whi);
   }
   __syncthreads();
 #pragma unroll
@@ -149,7 +156,7 @@ __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo
       const int base = (j - kk) * R + kk;
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if ((SM >> r) & 1u) buf[lds_pad(base + r * NS)] = v[i][r];
+        if ((SM >> r) & 1u) buf[lds_at<PAD>(base + r * NS)] = v[i][r];
     }
   }
   __syncthreads();
@@ -486,13 +493,14 @@ __device__ __forceinline__ void dft_bluestein(double2* buf, int n, int lt, const
   bluestein_conv<NL, INV, T>(buf, n, lt, wlo, whi, chirp, bhat);
 }
 
-// 4095 = 13 * 9 * 7 * 5
+// 4095 = 13 * 9 * 7 * 5, in the plain slot layout (element i in slot i, see lds_at)
 template <bool INV, int T>
 __device__ __forceinline__ void dft4095(double2* buf, int lt, const double2* wlo, const double2* whi) {
-  ct_pass<4095, 13, 1, INV, T>(buf, lt, wlo, whi);
-  ct_pass<4095, 9, 13, INV, T>(buf, lt, wlo, whi);
-  ct_pass<4095, 7, 117, INV, T>(buf, lt, wlo, whi);
-  ct_pass<4095, 5, 819, INV, T>(buf, lt, wlo, whi);
+  constexpr unsigned A = 0xFFFFu;
+  ct_pass<4095, 13, 1, INV, T, 1, A, A, false>(buf, lt, wlo, whi);
+  ct_pass<4095, 9, 13, INV, T, 1, A, A, false>(buf, lt, wlo, whi);
+  ct_pass<4095, 7, 117, INV, T, 1, A, A, false>(buf, lt, wlo, whi);
+  ct_pass<4095, 5, 819, INV, T, 1, A, A, false>(buf, lt, wlo, whi);
 }
 
 }  // namespace s2let

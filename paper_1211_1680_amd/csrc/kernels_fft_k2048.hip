@@ -32,8 +32,9 @@ struct K2048Args {
 
 // First radix-13 pass of the inverse 4095-point DFT, straight from the 4096-point FFT's output:
 // DFT input i is bin j = i (i < K) or j = i - 4095 (i >= K), held in FFT slot j mod 4096, i.e. slot
-// i or i + 1, and is taken times the phase ph[j + K - 1].  Replaces a gather into registers, a
-// barrier, a scatter to the DFT's order and another barrier.
+// i or i + 1 (padded layout), and is taken times the phase ph[j + K - 1]; the outputs go to the
+// DFT's plain layout.  Replaces a gather into registers, a barrier, a scatter to the DFT's order
+// and another barrier.
 template <int T>
 __device__ __forceinline__ void dft4095_inv_first_from_fft(double2* buf, int lt, const double2* __restrict__ ph) {
   constexpr int R = 13, NB = N / R;
@@ -58,7 +59,7 @@ __device__ __forceinline__ void dft4095_inv_first_from_fft(double2* buf, int lt,
     if (j < NB) {
       dft_small<R, true>(v[i]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_pad(j * R + r)] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[j * R + r] = v[i][r];
     }
   }
   __syncthreads();
@@ -93,15 +94,15 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const d
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  load_ring<N, TT, REAL>(f, map_stride, ma, hasb, t, valid, buf, lt);
+  load_ring<N, TT, REAL, false>(f, map_stride, ma, hasb, t, valid, buf, lt);
   __syncthreads();
   dft4095<false, TT>(buf, lt, w5lo, w5hi);
 
   const double wphi = 2.0 * M_PI / (double)N;
   if (valid) {
     for (int m = lt; m < K; m += TT) {
-      const double2 zp = buf[lds_pad(m)];
-      const double2 zn = buf[lds_pad(m == 0 ? 0 : N - m)];
+      const double2 zp = buf[m];
+      const double2 zn = buf[m == 0 ? 0 : N - m];
       double* row = GT + ((size_t)t * K + m) * C;
       if (REAL) {
         row[2 * ma] = wphi * 0.5 * (zp.x + zn.x);
@@ -157,14 +158,14 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       const double2 ge = valid ? x.ge[i] : make_double2(0.0, 0.0);
       const double2 go = valid ? x.go[i] : make_double2(0.0, 0.0);
       if (r < K - 1) {
-        buf[lds_pad(r)] = cadd(ge, go);
-        buf[lds_pad(N - 1 - r)] = csub(ge, go);
+        buf[r] = cadd(ge, go);
+        buf[N - 1 - r] = csub(ge, go);
         if (!SYM) {
           racc.x = fma(A.pole[r], go.x, racc.x);
           racc.y = fma(A.pole[r], go.y, racc.y);
         }
       } else {
-        buf[lds_pad(r)] = ge;
+        buf[r] = ge;
       }
     }
   }
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
     const int idx = lt + i * TT;
     if (idx < NJ) {
       const int j = idx - (K - 1);
-      keep[i] = cmul(A.hphase[idx], buf[lds_pad(j < 0 ? j + N : j)]);
+      keep[i] = cmul(A.hphase[idx], buf[j < 0 ? j + N : j]);
     }
   }
 #pragma unroll
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
     const int idx = lt + i * TT;
     if (idx < NJ) {
       const int jp = idx - (K - 1);
-      buf[lds_pad(jp < 0 ? jp + N : jp)] = keep[i];
+      buf[jp < 0 ? jp + N : jp] = keep[i];
     }
   }
   __syncthreads();
@@ -268,10 +269,10 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
     const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
     const double2 pO = make_double2(rP[0], rP[1]);
     for (int t = lt; t < K; t += TT) {
-      const double2 h1 = buf[lds_pad(t)];
+      const double2 h1 = buf[t];
       double2 he = h1, ho;
       if (t < K - 1) {
-        const double2 h2 = buf[lds_pad(N - 1 - t)];
+        const double2 h2 = buf[N - 1 - t];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
         ho.x = fma(A.pole[t], pO.x, ho.x);
@@ -335,9 +336,10 @@ __global__ __launch_bounds__(2 * TT) void k_resample_2048(K2048Args A, const dou
   fft4096<false, TT>(buf, lt, w6lo, w6hi);
   // bins |j| <= K-1 times the phase, inverse 4095-point DFT onto the MW nodes
   dft4095_inv_first_from_fft<TT>(buf, lt, A.rsph);
-  ct_pass<4095, 9, 13, true, TT>(buf, lt, w5lo, w5hi);
-  ct_pass<4095, 7, 117, true, TT>(buf, lt, w5lo, w5hi);
-  ct_pass<4095, 5, 819, true, TT>(buf, lt, w5lo, w5hi);
+  constexpr unsigned A8 = 0xFFFFu;
+  ct_pass<4095, 9, 13, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
+  ct_pass<4095, 7, 117, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
+  ct_pass<4095, 5, 819, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
   // thread T writes problem 2 p2 + (T & 1) at rings T / 2 + 512 i
   const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
   const int ph = 2 * p2 + h;
@@ -347,10 +349,10 @@ __global__ __launch_bounds__(2 * TT) void k_resample_2048(K2048Args A, const dou
 #pragma unroll
     for (int i = 0; i < K / TT; ++i) {
       const int t = rr + i * TT;
-      const double2 h1 = bh[lds_pad(t)];
+      const double2 h1 = bh[t];
       double2 he, ho;
       if (t < K - 1) {
-        const double2 h2 = bh[lds_pad(N - 1 - t)];
+        const double2 h2 = bh[N - 1 - t];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
       } else {
@@ -380,13 +382,13 @@ __global__ __launch_bounds__(TT, 4) void k_phi_inverse_2048(K2048Args A, const d
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  load_orders<K, TT, REAL>(FT, C, ma, hasb, t, valid, buf, lt);
+  load_orders<K, TT, REAL, false>(FT, C, ma, hasb, t, valid, buf, lt);
   __syncthreads();
   dft4095<true, TT>(buf, lt, w5lo, w5hi);
 
   if (valid) {
     for (int q = lt; q < N; q += TT) {
-      const double2 v = buf[lds_pad(q)];
+      const double2 v = buf[q];
       if (REAL) {
         f[(size_t)ma * map_stride + (size_t)t * N + q] = v.x;
         if (hasb) f[(size_t)(ma + 1) * map_stride + (size_t)t * N + q] = v.y;

@@ -48,6 +48,30 @@ MEASURED_TRAFFIC = {
 }
 
 
+# Pipe utilisation of the Legendre kernels' band-limit-2048 launches in this workload, from the SQ
+# counters of profiles/wavelet_L2048_16maps_counters.txt: MFMA busy and VALU active per SIMD, LDS
+# active per CU, as fractions of the launch.  Valid only for the kernel sources they were taken on
+# (sha256 below); otherwise not reported.
+MEASURED_PIPES = {
+    "sources": ["paper_1211_1680_amd/csrc/kernels_legendre.hip", "paper_1211_1680_amd/csrc/kernels_legendre_bf16.hip",
+                "paper_1211_1680_amd/csrc/legendre_rec.h"],
+    "sha256": "675be48c735ac956de84d0f27e6e0078a96666955e07c2bd1ee44456a4746ea0",
+    "fp64": {"legendre_analysis": {"mfma": 0.554, "valu": 0.168, "lds": 0.340},
+             "legendre_synthesis": {"mfma": 0.543, "valu": 0.304, "lds": 0.193}},
+    "fp32": {"legendre_analysis": {"mfma": 0.393, "valu": 0.286, "lds": 0.291},
+             "legendre_synthesis": {"mfma": 0.221, "valu": 0.337, "lds": 0.097}},
+    "bf16x3": {"legendre_analysis": {"mfma": 0.084, "valu": 0.360, "lds": 0.412},
+               "legendre_synthesis": {"mfma": 0.101, "valu": 0.636, "lds": 0.407}},
+}
+
+
+def measured_pipes(mode, stage):
+    """The counter-measured pipe utilisation of a Legendre stage (None once its sources changed)."""
+    if sources_sha256(MEASURED_PIPES["sources"]) != MEASURED_PIPES["sha256"]:
+        return None
+    return MEASURED_PIPES[mode][stage]
+
+
 # the kernel each stage launches at band-limit 2048 for 16 real maps in FP64 (32 columns)
 KERNEL_AT_L = {"phi_forward": "k_phi_forward_2048<1>", "theta": "k_theta_2048<true>",
                "legendre_analysis": "k_legendre_fwd_sym<32>", "legendre_synthesis": "k_legendre_inv_sym<32>",
@@ -198,10 +222,13 @@ PEAK_BF16_TFLOPS = 2500.0
 MIXED_PEAK = {"fp32": PEAK_FP32_TFLOPS, "bf16x3": PEAK_BF16_TFLOPS / 3.0}
 
 
-def mixed_roofline(st, mode, C):
+def mixed_roofline(st, mode, C, stage):
     """Both rooflines of a mixed-precision Legendre stage at the top band-limit: the contraction's
     algorithmic flops (2 C per retained pair) against the matrix-core peak of its type, and the
-    FP64 recursion's (3 per (l, m, theta) triple) against the FP64 vector peak."""
+    FP64 recursion's (3 per (l, m, theta) triple) against the FP64 vector peak.  The binding pipe
+    is the busiest one in the counter profile (the recursion's algorithmic flops leave out the
+    operand splitting, conversions and scaling that the vector units also do); without a valid
+    profile, the larger of the two algorithmic fractions."""
     if st["ms"] <= 0:
         return None
     sec = st["ms"] * 1e-3
@@ -209,7 +236,9 @@ def mixed_roofline(st, mode, C):
     rec_tf = 3.0 * triples / sec / 1e12
     con_tf = (st["flops_retained"] - 3.0 * triples) / sec / 1e12
     mfma, valu = con_tf / MIXED_PEAK[mode], rec_tf / PEAK_FP64_TFLOPS
-    return {"bound": "mfma" if mfma >= valu else "fp64-valu",
+    pipes = measured_pipes(mode, stage)
+    bound = max(pipes, key=pipes.get) if pipes else ("mfma" if mfma >= valu else "valu")
+    return {"bound": bound, "pipes_measured": pipes,
             "contraction_tflops": round(con_tf, 2), "contraction_peak": round(MIXED_PEAK[mode], 1),
             "mfma_frac": round(mfma, 4), "recursion_tflops": round(rec_tf, 2),
             "recursion_peak": PEAK_FP64_TFLOPS, "valu_frac": round(valu, 4),
@@ -374,7 +403,8 @@ def main():
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": measured_traffic(dom), "kernel": "%s, k=%d (%s)" % (dom, L, kname),
                 "launches": st["launches"], "avg_launch_ms": st["ms"] / max(st["launches"], 1),
-                "flops_per_launch": st["flops_retained"] / max(st["launches"], 1)}
+                "flops_per_launch": st["flops_retained"] / max(st["launches"], 1),
+                "pipes_measured": measured_pipes("fp64", dom)}
     else:
         achieved = st["bytes"] / (st["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -424,7 +454,7 @@ def main():
             "ms_per_step": 1e3 * r["dt"] / args.steps,
             "speedup_vs_fp64": dt / r["dt"],
             "stage_ms_per_step": {n: round(v["ms"] / args.steps, 3) for n, v in lst.items()},
-            "roofline": {n: mixed_roofline(r["at_L"][n], name, C) for n in ("legendre_analysis", "legendre_synthesis")},
+            "roofline": {n: mixed_roofline(r["at_L"][n], name, C, n) for n in ("legendre_analysis", "legendre_synthesis")},
             "error_vs_fp64_per_scale": per_scale,
             "reconstruction_rel_max_err_vs_fp64": (r["rec"] - r64["rec"]).abs().max().item() /
                                                    r64["rec"].abs().max().item(),

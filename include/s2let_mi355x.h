@@ -50,8 +50,13 @@ enum {
 };
 
 enum { S2LET_REAL = 0, S2LET_COMPLEX = 1 };                       /* reality */
-enum { S2LET_FP64 = 0, S2LET_MIXED_FP32 = 1, S2LET_MIXED_BF16X3 = 2 };  /* precision of the
-                                                                     Legendre contraction */
+/* Precision of the Legendre contraction (the recursion, the phi/theta stages and the tiling are FP64
+ * in every mode).  S2LET_MIXED_FP32: FP32 matrix-core products with FP32 partial sums carried into
+ * FP64; where that is not faster than FP64 (the symmetric-grid synthesis of 32-column batches,
+ * whose FP64 running sums leave it one wave per SIMD), the FP64 contraction runs instead.
+ * S2LET_MIXED_BF16X3: both operands split into two bfloat16 parts, three products.  The stated
+ * bounds (relative to the largest output) are 2e-6 and 1e-4. */
+enum { S2LET_FP64 = 0, S2LET_MIXED_FP32 = 1, S2LET_MIXED_BF16X3 = 2 };
 #define S2LET_MAX_L 2048
 
 /* Generating functions of the axisymmetric wavelets (Sect. 2.2).  S2LET_KERNEL_SD: the

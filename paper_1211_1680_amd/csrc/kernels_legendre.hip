@@ -916,10 +916,9 @@ hipError_t launch_legendre_inverse_sym(const ShtTables& T, const LegTables& G, c
   const int ntb = (k / 2 + 255) / 256;
   const dim3 grid(((k + 1) / 2) * ntb), block(256);
   const bool f32 = precision == S2LET_MIXED_FP32;
-  if (b.C == 32 && f32)
-    k_legendre_inv_sym<32, float><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
-                                                         G.Lt, ntb, lmin, counter);
-  else if (b.C == 32)
+  // 32 columns in FP32 would need 310 registers (FP64 north/south running sums beside the FP32
+  // partial sums): one wave per SIMD, slower than the FP64 kernel at two.  The FP64 kernel serves.
+  if (b.C == 32)
     k_legendre_inv_sym<32, double><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.sx_s, T.st_s, k,
                                                           G.Lt, ntb, lmin, counter);
   else if (b.C == 16 && f32)

@@ -224,7 +224,11 @@ __global__ __launch_bounds__(512) void k_legendre_fwd(const double* __restrict__
       // that meet zero operands)
       const double cf = cf_next;
       cf_next = chunk_coef<FWD_LC>(am, bm, l0 + FWD_LC - m, k - m, lane);
-      recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) { Z[w][j][lane] = (T)v; });
+      // (a skipped chunk's z values are read by no product: the recursion stores none)
+      if (skip)
+        recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e, [](int, double) {});
+      else
+        recur_chunk<FWD_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) { Z[w][j][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < FWD_LC ? (k - l0) : FWD_LC;
@@ -360,7 +364,10 @@ __global__ __launch_bounds__(256) void k_legendre_inv_mfma(const double* __restr
       const double cf = cf_next;
       cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
       // degrees past k meet zero coefficient rows; thetas past k are not stored
-      recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) { Z[w][j][lane] = (T)v; });
+      if (skip)
+        recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e, [](int, double) {});
+      else
+        recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) { Z[w][j][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < INVM_LC ? (k - l0) : INVM_LC;
@@ -542,13 +549,18 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym(const double* __restri
       cf = chunk_coef<FS_LC>(am, bm, l0 + FS_LC - m, k - m, lane);   // the next chunk's, in flight
       wave_lds_sync();
       const bool ngw = !tile_live || __all(!valid || negligible(z1, z2, e));
+      auto nosink = [](int, double) {};
       if (below) {
-        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e, [](int, double) {});
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e, nosink);
         continue;
       }
-      // phase A: this chunk's recursion into Z, the previous chunk's reduction
-      recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
-                             [&](int j, double v) { Z[(j & 1) * 16 + (j >> 1)][w * 64 + lane] = (T)v; });
+      // phase A: this chunk's recursion into Z (none when the products skip this wave's nodes), the
+      // previous chunk's reduction
+      if (ngw)
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e, nosink);
+      else
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
+                               [&](int j, double v) { Z[(j & 1) * 16 + (j >> 1)][w * 64 + lane] = (T)v; });
       if (lane == 0) negl[w] = ngw;
       if (!ngw) retained += (unsigned long long)((k - l0) < FS_LC ? (k - l0) : FS_LC) * nt;
       if (lprev >= 0) reduce(m, lprev);
@@ -652,8 +664,11 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_sym_f32(const double* __re
       stage_coef<FS_LC>(cfl, cf, lane);
       cf = chunk_coef<FS_LC>(am, bm, l0 + FS_LC - m, k - m, lane);   // the next chunk's, in flight
       wave_lds_sync();
-      recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
-                             [&](int j, double v) { Z[w][(j & 1) * (FS_LC / 2) + (j >> 1)][lane] = (T)v; });
+      if (skip)
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e, [](int, double) {});
+      else
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
+                               [&](int j, double v) { Z[w][(j & 1) * (FS_LC / 2) + (j >> 1)][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < FS_LC ? (k - l0) : FS_LC;
@@ -782,8 +797,11 @@ __device__ __forceinline__ void inv_sym_body(const double* __restrict__ S, doubl
       // here, where the z tile and the coefficient rows already load the LDS every chunk)
       const double cf = cf_next;
       cf_next = chunk_coef<INVM_LC>(am, bm, l0 + INVM_LC - m, k - m, lane);
-      recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e,
-                           [&](int j, double v) { Z[w][(j & 1) * (INVM_LC / 2) + (j >> 1)][lane] = (T)v; });
+      if (skip)
+        recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e, [](int, double) {});
+      else
+        recur_chunk<INVM_LC>(cf, u, sg, z1, z2, e,
+                             [&](int j, double v) { Z[w][(j & 1) * (INVM_LC / 2) + (j >> 1)][lane] = (T)v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < INVM_LC ? (k - l0) : INVM_LC;
@@ -999,8 +1017,11 @@ __device__ __forceinline__ void fwd_sym_wave_body(const double* __restrict__ HM,
       stage_coef<FS_LC>(cfl, cf, lane);
       cf = chunk_coef<FS_LC>(am, bm, l0 + FS_LC - m, k - m, lane);
       wave_lds_sync();
-      recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
-                             [&](int j, double v) { Z[w][(j & 1) * (FS_LC / 2) + (j >> 1)][lane] = v; });
+      if (skip)
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e, [](int, double) {});
+      else
+        recur_chunk_lds<FS_LC>(cfl, u, sg, z1, z2, e,
+                               [&](int j, double v) { Z[w][(j & 1) * (FS_LC / 2) + (j >> 1)][lane] = v; });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < FS_LC ? (k - l0) : FS_LC;

@@ -133,12 +133,16 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16(const double* __restr
       const bool skip = !tile_live || __all(!valid || negligible(z1, z2, e));
       const double cf = cf_next;
       cf_next = chunk_coef<FB_LC>(am, bm, l0 + FB_LC - m, k - m, lane);
-      recur_chunk<FB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
-        __bf16 hi, lo;
-        split_bf16(v, hi, lo);
-        Zt[w][0][j][lane] = hi;
-        Zt[w][1][j][lane] = lo;
-      });
+      // (a skipped chunk's z values are read by no product: neither split nor stored)
+      if (skip)
+        recur_chunk<FB_LC>(cf, u, sg, z1, z2, e, [](int, double) {});
+      else
+        recur_chunk<FB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
+          __bf16 hi, lo;
+          split_bf16(v, hi, lo);
+          Zt[w][0][j][lane] = hi;
+          Zt[w][1][j][lane] = lo;
+        });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < FB_LC ? (k - l0) : FB_LC;
@@ -270,16 +274,19 @@ __global__ __launch_bounds__(256) void k_legendre_inv_bf16(const double* __restr
       cf_next = chunk_coef<IB_LC>(am, bm, l0 + IB_LC - m, k - m, lane);
       // z values: 4 consecutive degrees per 8-byte store (hi and lo parts)
       bf16x4 ph, pl;
-      recur_chunk<IB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
-        __bf16 hi, lo;
-        split_bf16(v, hi, lo);
-        ph[j & 3] = hi;
-        pl[j & 3] = lo;
-        if ((j & 3) == 3) {
-          *reinterpret_cast<bf16x4*>(&Z[w][lane][j - 3]) = ph;
-          *reinterpret_cast<bf16x4*>(&Z[w][lane][32 + j - 3]) = pl;
-        }
-      });
+      if (skip)
+        recur_chunk<IB_LC>(cf, u, sg, z1, z2, e, [](int, double) {});
+      else
+        recur_chunk<IB_LC>(cf, u, sg, z1, z2, e, [&](int j, double v) {
+          __bf16 hi, lo;
+          split_bf16(v, hi, lo);
+          ph[j & 3] = hi;
+          pl[j & 3] = lo;
+          if ((j & 3) == 3) {
+            *reinterpret_cast<bf16x4*>(&Z[w][lane][j - 3]) = ph;
+            *reinterpret_cast<bf16x4*>(&Z[w][lane][32 + j - 3]) = pl;
+          }
+        });
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < IB_LC ? (k - l0) : IB_LC;
@@ -431,8 +438,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
     auto recur_into = [&](int c, int l0c) {
       const bool fill = l0c + LC > lmin;
       const bool ngw = !tile_live || __all(!valid || negligible(z1, z2, e));
-      if (fill) {
-        const int zb = c & 1;
+      const int zb = c & 1;
+      if (fill && !ngw) {
         float fe = 0.f;
         recur_chunk_lds<LC>(cfl, u, sg, z1, z2, e, [&](int j, double v) {
           const float f = opaque_f32((float)v);
@@ -448,11 +455,12 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
           Z[zb][1][i][w * 64 + lane] = lo.x;
           Z[zb][1][16 + i][w * 64 + lane] = lo.y;
         });
-        if (lane == 0) negl[zb][w] = ngw;
-        if (!ngw) retained += (unsigned long long)((k - l0c) < LC ? (k - l0c) : LC) * nt;
+        retained += (unsigned long long)((k - l0c) < LC ? (k - l0c) : LC) * nt;
       } else {
+        // below the floor, or products that skip this wave's nodes: no z values stored
         recur_chunk_lds<LC>(cfl, u, sg, z1, z2, e, [](int, double) {});
       }
+      if (fill && lane == 0) negl[zb][w] = ngw;
     };
     double cf = chunk_coef<LC>(am, bm, 0, k - m, lane);
     stage_coef<LC>(cfl, cf, lane);
@@ -635,8 +643,15 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_bf16_sym(const double* 
           }
         };
       };
-      recur_chunk_lds<32>(coef[w], u, sg, z1, z2, e, sink(0));
-      recur_chunk_lds<32>(coef[w] + 32, u, sg, z1, z2, e, sink(32));
+      if (skip) {
+        // a skipped chunk's z values are read by no product: neither split nor stored
+        auto nosink = [](int, double) {};
+        recur_chunk_lds<32>(coef[w], u, sg, z1, z2, e, nosink);
+        recur_chunk_lds<32>(coef[w] + 32, u, sg, z1, z2, e, nosink);
+      } else {
+        recur_chunk_lds<32>(coef[w], u, sg, z1, z2, e, sink(0));
+        recur_chunk_lds<32>(coef[w] + 32, u, sg, z1, z2, e, sink(32));
+      }
       if (!skip) {
         wave_lds_sync();
         const int nl = (k - l0) < IBS_LC ? (k - l0) : IBS_LC;

@@ -8,6 +8,8 @@
 #pragma once
 #include "fft_lds.h"
 
+#include <type_traits>
+
 namespace s2let {
 
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 3); }
@@ -26,9 +28,9 @@ __device__ __forceinline__ int lds_at(int i) { return PAD ? lds_pad(i) : i; }
 // Ring t of one phi problem into LDS slots q < N: REAL packs map ma (real part) and map ma + 1
 // (imaginary part, zero without it); otherwise map ma is complex.  Every load is issued before
 // the first store.
-template <int N, int T, int REAL, bool PAD = true>
+template <int N, int T, int REAL, bool PAD = true, typename C2 = double2>
 __device__ __forceinline__ void load_ring(const double* __restrict__ f, long long map_stride, int ma, bool hasb,
-                                          int t, bool valid, double2* buf, int lt) {
+                                          int t, bool valid, C2* buf, int lt) {
   constexpr int PER = (N + T - 1) / T;
   double2 z[PER];
 #pragma unroll
@@ -45,7 +47,7 @@ __device__ __forceinline__ void load_ring(const double* __restrict__ f, long lon
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int q = lt + i * T;
-    if (q < N) buf[lds_at<PAD>(q)] = valid ? z[i] : make_double2(0.0, 0.0);
+    if (q < N) buf[lds_at<PAD>(q)] = valid ? cplx<C2>(z[i]) : czero<C2>();
   }
 }
 
@@ -53,60 +55,64 @@ __device__ __forceinline__ void load_ring(const double* __restrict__ f, long lon
 // slot N - m (0 < m < K) order -m.  REAL: the unit packs maps ma and ma + 1 as a + i b, with the
 // negative orders their conjugates; otherwise columns 4 ma .. 4 ma + 3 hold orders +m and -m of
 // map ma.  Each row is read once for both slots, and every load is issued before the first store.
-template <int K, int T, int REAL, bool PAD = true>
-__device__ __forceinline__ void load_orders(const double* __restrict__ FT, int C, int ma, bool hasb, int t,
-                                            bool valid, double2* buf, int lt) {
+// (TF: the element type of FT, double or float; C2: the complex type of the LDS buffer)
+template <int K, int T, int REAL, bool PAD = true, typename TF = double, typename C2 = double2>
+__device__ __forceinline__ void load_orders(const TF* __restrict__ FT, int C, int ma, bool hasb, int t,
+                                            bool valid, C2* buf, int lt) {
+  typedef decltype(C2::x) S;
   constexpr int N = 2 * K - 1;
   constexpr int PER = K / T;
   static_assert(K % T == 0, "orders per thread");
-  double2 ra[PER], rb[PER];
+  typedef typename std::conditional<sizeof(TF) == 8, double2, float2>::type V2;
+  V2 ra[PER], rb[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const double* row = FT + ((size_t)t * K + lt + i * T) * C;
+    const TF* row = FT + ((size_t)t * K + lt + i * T) * C;
     if (REAL) {
-      ra[i] = *reinterpret_cast<const double2*>(row + 2 * ma);
-      rb[i] = hasb ? *reinterpret_cast<const double2*>(row + 2 * ma + 2) : make_double2(0.0, 0.0);
+      ra[i] = *reinterpret_cast<const V2*>(row + 2 * ma);
+      rb[i] = hasb ? *reinterpret_cast<const V2*>(row + 2 * ma + 2) : V2{};
     } else {
-      ra[i] = *reinterpret_cast<const double2*>(row + 4 * ma);
-      rb[i] = *reinterpret_cast<const double2*>(row + 4 * ma + 2);
+      ra[i] = *reinterpret_cast<const V2*>(row + 4 * ma);
+      rb[i] = *reinterpret_cast<const V2*>(row + 4 * ma + 2);
     }
   }
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int m = lt + i * T;
-    const double2 a = valid ? ra[i] : make_double2(0.0, 0.0);
-    const double2 b = valid ? rb[i] : make_double2(0.0, 0.0);
+    const S ax = valid ? (S)ra[i].x : S(0), ay = valid ? (S)ra[i].y : S(0);
+    const S bx = valid ? (S)rb[i].x : S(0), by = valid ? (S)rb[i].y : S(0);
     if (REAL) {
-      buf[lds_at<PAD>(m)] = make_double2(a.x - b.y, a.y + b.x);
-      if (m > 0) buf[lds_at<PAD>(N - m)] = make_double2(a.x + b.y, b.x - a.y);
+      buf[lds_at<PAD>(m)] = CplxTraits<C2>::make(ax - by, ay + bx);
+      if (m > 0) buf[lds_at<PAD>(N - m)] = CplxTraits<C2>::make(ax + by, bx - ay);
     } else {
-      buf[lds_at<PAD>(m)] = a;
-      if (m > 0) buf[lds_at<PAD>(N - m)] = b;
+      buf[lds_at<PAD>(m)] = CplxTraits<C2>::make(ax, ay);
+      if (m > 0) buf[lds_at<PAD>(N - m)] = CplxTraits<C2>::make(bx, by);
     }
   }
 }
 
-template <int K, int T>
+template <int K, int T, typename TG = double>
 struct RingGather {
+  typedef typename std::conditional<sizeof(TG) == 8, double2, float2>::type V2;
   static constexpr int PER = K / T;
   static_assert(K % T == 0, "rings per thread");
-  double2 ge[PER], go[PER];
-  __device__ __forceinline__ void load(const double* __restrict__ GT, int C, int mE, int s, int lt) {
+  V2 ge[PER], go[PER];
+  __device__ __forceinline__ void load(const TG* __restrict__ GT, int C, int mE, int s, int lt) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const double* row = GT + ((size_t)(lt + i * T) * K + mE) * C + 2 * s;
-      ge[i] = *reinterpret_cast<const double2*>(row);
-      go[i] = *reinterpret_cast<const double2*>(row + C);
+      const TG* row = GT + ((size_t)(lt + i * T) * K + mE) * C + 2 * s;
+      ge[i] = *reinterpret_cast<const V2*>(row);
+      go[i] = *reinterpret_cast<const V2*>(row + C);
     }
   }
 };
 
-template <int R, bool INV>
-__device__ __forceinline__ void dft_small(double2* v) {
+template <int R, bool INV, typename C2>
+__device__ __forceinline__ void dft_small(C2* v) {
   if constexpr (R == 2 || R == 4 || R == 8 || R == 16)
-    SmallDft<R, INV>::run(v);
+    SmallDft<R, INV, C2>::run(v);
   else
-    OddDft<R, INV>::run(v);
+    OddDft<R, INV, C2>::run(v);
 }
 
 // One pass: N points, radix R, NS = product of the radices of the earlier passes, T threads.
@@ -114,18 +120,17 @@ __device__ __forceinline__ void dft_small(double2* v) {
 // LM / SM: bit r clear = input r of every butterfly is known to be zero (not loaded) / output r is
 // not needed (not stored).  PAD: the slot layout (lds_at).
 // inputs j + r N/R of butterfly j of a pass, with the pass's twiddles applied
-template <int N, int R, int NS, bool INV, int TS, unsigned LM, bool PAD = true>
-__device__ __forceinline__ void ct_gather(const double2* buf, int j, double2* v, const double2* wlo,
-                                          const double2* whi) {
+template <int N, int R, int NS, bool INV, int TS, unsigned LM, bool PAD = true, typename C2>
+__device__ __forceinline__ void ct_gather(const C2* buf, int j, C2* v, const C2* wlo, const C2* whi) {
   constexpr int NB = N / R;
   constexpr int STRIDE = N / (NS * R);
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = ((LM >> r) & 1u) ? buf[lds_at<PAD>(j + r * NB)] : make_double2(0.0, 0.0);
+  for (int r = 0; r < R; ++r) v[r] = ((LM >> r) & 1u) ? buf[lds_at<PAD>(j + r * NB)] : czero<C2>();
   if constexpr (NS > 1) {
     const int p = (j % NS) * STRIDE * TS;
-    double2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
+    C2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
     if (INV) w1 = conjd(w1);
-    double2 w = w1;
+    C2 w = w1;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
       v[r] = cmul(v[r], w);
@@ -135,12 +140,12 @@ __device__ __forceinline__ void ct_gather(const double2* buf, int j, double2* v,
 }
 
 template <int N, int R, int NS, bool INV, int T, int TS = 1, unsigned LM = 0xFFFFu, unsigned SM = 0xFFFFu,
-          bool PAD = true>
-__device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo, const double2* whi) {
+          bool PAD = true, typename C2>
+__device__ __forceinline__ void ct_pass(C2* buf, int lt, const C2* wlo, const C2* whi) {
   constexpr int NB = N / R;
   constexpr int PER = (NB + T - 1) / T;
   static_assert(N % (NS * R) == 0, "radix plan does not divide the length");
-  double2 v[PER][R];
+  C2 v[PER][R];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = lt + i * T;
@@ -164,8 +169,8 @@ __device__ __forceinline__ void ct_pass(double2* buf, int lt, const double2* wlo
 
 // 4096 = 8^4 with every thread active: fewer registers than the radix-16 plan below, for kernels
 // that keep other values live across their transforms
-template <bool INV, int T>
-__device__ __forceinline__ void fft4096_r8(double2* buf, int lt, const double2* wlo, const double2* whi) {
+template <bool INV, int T, typename C2>
+__device__ __forceinline__ void fft4096_r8(C2* buf, int lt, const C2* wlo, const C2* whi) {
   ct_pass<4096, 8, 1, INV, T>(buf, lt, wlo, whi);
   ct_pass<4096, 8, 8, INV, T>(buf, lt, wlo, whi);
   ct_pass<4096, 8, 64, INV, T>(buf, lt, wlo, whi);
@@ -180,12 +185,13 @@ __device__ __forceinline__ void fft4096_r8(double2* buf, int lt, const double2* 
 // the same slots j + r NL/8 (j < NL/8), and one pass does both with the spectrum scaling in
 // between, in registers (one LDS round trip and two barriers fewer than transform, scale,
 // transform).
-template <int NL, int T, int TS>
-__device__ __forceinline__ void corr_conv_mid(double2* buf, int lt, const double2* wlo, const double2* whi,
+template <int NL, int T, int TS, typename C2>
+__device__ __forceinline__ void corr_conv_mid(C2* buf, int lt, const C2* wlo, const C2* whi,
                                               const double* __restrict__ kr) {
+  typedef typename CplxTraits<C2>::S S;
   constexpr int NB = NL / 8;
   constexpr int PER = (NB + T - 1) / T;
-  double2 v[PER][8];
+  C2 v[PER][8];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = lt + i * T;
@@ -196,12 +202,12 @@ __device__ __forceinline__ void corr_conv_mid(double2* buf, int lt, const double
   for (int i = 0; i < PER; ++i) {
     const int j = lt + i * T;
     if (j < NB) {
-      double k[8];
+      S k[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) k[r] = kr[j + r * NB];
+      for (int r = 0; r < 8; ++r) k[r] = (S)kr[j + r * NB];
       dft_small<8, false>(v[i]);   // bin j + NB r in v[i][r]
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[i][r] = make_double2(v[i][r].x * k[r], v[i][r].y * k[r]);
+      for (int r = 0; r < 8; ++r) v[i][r] = CplxTraits<C2>::make(v[i][r].x * k[r], v[i][r].y * k[r]);
       dft_small<8, true>(v[i]);    // first inverse pass (no twiddles), outputs 8 j + r
 #pragma unroll
       for (int r = 0; r < 8; ++r) buf[lds_pad(8 * j + r)] = v[i][r];
@@ -210,8 +216,8 @@ __device__ __forceinline__ void corr_conv_mid(double2* buf, int lt, const double
   __syncthreads();
 }
 
-template <int NL, int T, int TS>
-__device__ __forceinline__ void corr_conv(double2* buf, int lt, const double2* wlo, const double2* whi,
+template <int NL, int T, int TS, typename C2>
+__device__ __forceinline__ void corr_conv(C2* buf, int lt, const C2* wlo, const C2* whi,
                                           const double* __restrict__ kr) {
   // a radix-8 first (last) pass keeps inputs (outputs) 0, 1, 6, 7; a radix-4 one keeps 0 and 3
   constexpr unsigned M8 = 0xC3u, M4 = 0x9u;
@@ -264,8 +270,8 @@ __device__ __forceinline__ void corr_conv(double2* buf, int lt, const double2* w
 // 4096 = 16^3 (unnormalised, sign -1 or +1 with INV): three passes, half of 512 threads active
 // in each; 10 % faster than four radix-8 passes with every thread active (fewer LDS round trips
 // and barriers)
-template <bool INV, int T, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu>
-__device__ __forceinline__ void fft4096(double2* buf, int lt, const double2* wlo, const double2* whi) {
+template <bool INV, int T, unsigned LM0 = 0xFFFFu, unsigned SML = 0xFFFFu, typename C2>
+__device__ __forceinline__ void fft4096(C2* buf, int lt, const C2* wlo, const C2* whi) {
   ct_pass<4096, 16, 1, INV, T, 1, LM0>(buf, lt, wlo, whi);
   ct_pass<4096, 16, 16, INV, T>(buf, lt, wlo, whi);
   ct_pass<4096, 16, 256, INV, T, 1, 0xFFFFu, SML>(buf, lt, wlo, whi);
@@ -494,8 +500,8 @@ __device__ __forceinline__ void dft_bluestein(double2* buf, int n, int lt, const
 }
 
 // 4095 = 13 * 9 * 7 * 5, in the plain slot layout (element i in slot i, see lds_at)
-template <bool INV, int T>
-__device__ __forceinline__ void dft4095(double2* buf, int lt, const double2* wlo, const double2* whi) {
+template <bool INV, int T, typename C2>
+__device__ __forceinline__ void dft4095(C2* buf, int lt, const C2* wlo, const C2* whi) {
   constexpr unsigned A = 0xFFFFu;
   ct_pass<4095, 13, 1, INV, T, 1, A, A, false>(buf, lt, wlo, whi);
   ct_pass<4095, 9, 13, INV, T, 1, A, A, false>(buf, lt, wlo, whi);

@@ -19,10 +19,38 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
+// The same for single-precision complex values (the transforms' FP32 instantiations)
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 conjd(float2 a) { return make_float2(a.x, -a.y); }
+
+// Scalar type of a complex type, a complex value from two scalars, and a double2 constant or
+// table entry taken to the working precision
+template <typename C2> struct CplxTraits;
+template <> struct CplxTraits<double2> {
+  typedef double S;
+  __device__ __forceinline__ static double2 make(double x, double y) { return make_double2(x, y); }
+};
+template <> struct CplxTraits<float2> {
+  typedef float S;
+  __device__ __forceinline__ static float2 make(float x, float y) { return make_float2(x, y); }
+};
+template <typename C2>
+__device__ __forceinline__ C2 cplx(double2 a) {
+  return CplxTraits<C2>::make((typename CplxTraits<C2>::S)a.x, (typename CplxTraits<C2>::S)a.y);
+}
+template <typename C2>
+__device__ __forceinline__ C2 czero() {
+  return CplxTraits<C2>::make(0, 0);
+}
+
 // multiply by exp(-i pi/2) = -i (forward) or +i (inverse)
-template <bool INV>
-__device__ __forceinline__ double2 mul_quarter(double2 a) {
-  return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+template <bool INV, typename C2>
+__device__ __forceinline__ C2 mul_quarter(C2 a) {
+  return INV ? CplxTraits<C2>::make(-a.y, a.x) : CplxTraits<C2>::make(a.y, -a.x);
 }
 
 // cos / sin of 2 pi q / 16, q = 0..7
@@ -54,62 +82,63 @@ __device__ __forceinline__ double2 w16(int q) {
   return make_double2(cos16(q), INV ? sin16(q) : -sin16(q));
 }
 
-// In-register DFT of size R (R = 1, 2, 4, 8, 16) on v[0..R-1], sign -1 (forward) or +1.
-template <int R, bool INV>
+// In-register DFT of size R (R = 1, 2, 4, 8, 16) on v[0..R-1], sign -1 (forward) or +1, in the
+// precision of the complex type C2.
+template <int R, bool INV, typename C2 = double2>
 struct SmallDft;
 
-template <bool INV>
-struct SmallDft<1, INV> {
-  __device__ __forceinline__ static void run(double2*) {}
+template <bool INV, typename C2>
+struct SmallDft<1, INV, C2> {
+  __device__ __forceinline__ static void run(C2*) {}
 };
-template <bool INV>
-struct SmallDft<2, INV> {
-  __device__ __forceinline__ static void run(double2* v) {
-    double2 a = v[0], b = v[1];
+template <bool INV, typename C2>
+struct SmallDft<2, INV, C2> {
+  __device__ __forceinline__ static void run(C2* v) {
+    C2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
   }
 };
-template <bool INV>
-struct SmallDft<4, INV> {
-  __device__ __forceinline__ static void run(double2* v) {
-    double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    double2 t2 = cadd(v[1], v[3]), t3 = mul_quarter<INV>(csub(v[1], v[3]));
+template <bool INV, typename C2>
+struct SmallDft<4, INV, C2> {
+  __device__ __forceinline__ static void run(C2* v) {
+    C2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    C2 t2 = cadd(v[1], v[3]), t3 = mul_quarter<INV>(csub(v[1], v[3]));
     v[0] = cadd(t0, t2);
     v[2] = csub(t0, t2);
     v[1] = cadd(t1, t3);
     v[3] = csub(t1, t3);
   }
 };
-template <bool INV>
-struct SmallDft<8, INV> {
-  __device__ __forceinline__ static void run(double2* v) {
-    double2 e[4] = {v[0], v[2], v[4], v[6]};
-    double2 o[4] = {v[1], v[3], v[5], v[7]};
-    SmallDft<4, INV>::run(e);
-    SmallDft<4, INV>::run(o);
+template <bool INV, typename C2>
+struct SmallDft<8, INV, C2> {
+  __device__ __forceinline__ static void run(C2* v) {
+    C2 e[4] = {v[0], v[2], v[4], v[6]};
+    C2 o[4] = {v[1], v[3], v[5], v[7]};
+    SmallDft<4, INV, C2>::run(e);
+    SmallDft<4, INV, C2>::run(o);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      double2 t = cmul(o[q], w16<INV>(2 * q));
+      C2 t = cmul(o[q], cplx<C2>(w16<INV>(2 * q)));
       v[q] = cadd(e[q], t);
       v[q + 4] = csub(e[q], t);
     }
   }
 };
-template <bool INV>
-struct SmallDft<16, INV> {
-  __device__ __forceinline__ static void run(double2* v) {
-    double2 e[8], o[8];
+template <bool INV, typename C2>
+struct SmallDft<16, INV, C2> {
+  __device__ __forceinline__ static void run(C2* v) {
+    C2 e[8], o[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       e[q] = v[2 * q];
       o[q] = v[2 * q + 1];
     }
-    SmallDft<8, INV>::run(e);
-    SmallDft<8, INV>::run(o);
+    SmallDft<8, INV, C2>::run(e);
+    SmallDft<8, INV, C2>::run(o);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      double2 t = cmul(o[q], w16<INV>(q));
+      C2 t = cmul(o[q], cplx<C2>(w16<INV>(q)));
       v[q] = cadd(e[q], t);
       v[q + 8] = csub(e[q], t);
     }
@@ -238,38 +267,39 @@ S2LET_TRIG(13)
 // DFT of odd size R on v[0..R-1] using the symmetric pairs (j, R-j):
 // X_q = A_q -+ i B_q, X_{R-q} = A_q +- i B_q with A_q = v_0 + sum_j (v_j + v_{R-j}) cos(2 pi j q/R),
 // B_q = sum_j (v_j - v_{R-j}) sin(2 pi j q/R).
-template <int R, bool INV>
+template <int R, bool INV, typename C2 = double2>
 struct OddDft {
-  __device__ __forceinline__ static void run(double2* v) {
+  __device__ __forceinline__ static void run(C2* v) {
+    typedef typename CplxTraits<C2>::S S;
     constexpr int h = (R - 1) / 2;
-    double2 a[h], b[h];
+    C2 a[h], b[h];
 #pragma unroll
     for (int j = 1; j <= h; ++j) {
       a[j - 1] = cadd(v[j], v[R - j]);
       b[j - 1] = csub(v[j], v[R - j]);
     }
-    const double2 x0 = v[0];
-    double2 sum = x0;
+    const C2 x0 = v[0];
+    C2 sum = x0;
 #pragma unroll
     for (int j = 0; j < h; ++j) sum = cadd(sum, a[j]);
     v[0] = sum;
 #pragma unroll
     for (int q = 1; q <= h; ++q) {
-      double ax = x0.x, ay = x0.y, bx = 0.0, by = 0.0;
+      S ax = x0.x, ay = x0.y, bx = 0, by = 0;
 #pragma unroll
       for (int j = 1; j <= h; ++j) {
-        const double c = cosR<R>((j * q) % R), sn = sinR<R>((j * q) % R);
+        const S c = (S)cosR<R>((j * q) % R), sn = (S)sinR<R>((j * q) % R);
         ax = fma(a[j - 1].x, c, ax);
         ay = fma(a[j - 1].y, c, ay);
         bx = fma(b[j - 1].x, sn, bx);
         by = fma(b[j - 1].y, sn, by);
       }
       if (INV) {   // A + i B, A - i B
-        v[q] = make_double2(ax - by, ay + bx);
-        v[R - q] = make_double2(ax + by, ay - bx);
+        v[q] = CplxTraits<C2>::make(ax - by, ay + bx);
+        v[R - q] = CplxTraits<C2>::make(ax + by, ay - bx);
       } else {     // A - i B, A + i B
-        v[q] = make_double2(ax + by, ay - bx);
-        v[R - q] = make_double2(ax - by, ay + bx);
+        v[q] = CplxTraits<C2>::make(ax + by, ay - bx);
+        v[R - q] = CplxTraits<C2>::make(ax - by, ay + bx);
       }
     }
   }

@@ -4,6 +4,14 @@
 // MW sampling), the theta stage (extension, DFT, parity-split correlation with the even part of
 // the sin(theta) weight, DFT back, fold), and the inverse phi DFT.  One problem per 512-thread
 // block; 74-76 KiB of LDS and at most 128 VGPRs (4 waves per SIMD), so two blocks share a CU.
+// Each kernel is a template over its working precision Rt: double, or float for the BF16x3
+// contraction mode (whose stated bound, 1e-4, leaves room for FP32 transforms, about 1e-6), in
+// which the stage buffers between these kernels and the Legendre steps hold floats too.  The FP32
+// instantiations take 37-39 KiB of LDS and at most 64 VGPRs (the theta stage 80), so four
+// problems (three for the theta stage) share a CU.  Non-packed FP32 arithmetic issues at the FP64
+// rate, so the gain is in LDS traffic and occupancy: the theta and resampling stages, heavy in
+// radix-8 passes, gain about a third; the phi stages, bound by the odd-radix 4095-point arithmetic,
+// little.
 #include "common.h"
 #include "fft_ct.h"
 #include "../../include/s2let_mi355x.h"
@@ -16,6 +24,9 @@ constexpr int N = 2 * K - 1;    // 4095
 constexpr int NC = 4096;
 constexpr int TT = 512;         // threads per problem
 constexpr int NBUF = lds_padded(NC);
+// complex type of a working precision, and the waves per SIMD its kernels are built for
+template <typename Rt>
+using Cx = typename std::conditional<sizeof(Rt) == 8, double2, float2>::type;
 
 struct K2048Args {
   const double2* tw4096_lo;   // W_4096^p, p < 64
@@ -35,11 +46,11 @@ struct K2048Args {
 // i or i + 1 (padded layout), and is taken times the phase ph[j + K - 1]; the outputs go to the
 // DFT's plain layout.  Replaces a gather into registers, a barrier, a scatter to the DFT's order
 // and another barrier.
-template <int T>
-__device__ __forceinline__ void dft4095_inv_first_from_fft(double2* buf, int lt, const double2* __restrict__ ph) {
+template <int T, typename C2>
+__device__ __forceinline__ void dft4095_inv_first_from_fft(C2* buf, int lt, const double2* __restrict__ ph) {
   constexpr int R = 13, NB = N / R;
   constexpr int PER = (NB + T - 1) / T;
-  double2 v[PER][R];
+  C2 v[PER][R];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int j = lt + i * T;
@@ -48,7 +59,7 @@ __device__ __forceinline__ void dft4095_inv_first_from_fft(double2* buf, int lt,
       for (int r = 0; r < R; ++r) {
         const int x = j + r * NB;
         const bool lo = x < K;
-        v[i][r] = cmul(ph[lo ? x + K - 1 : x - K], buf[lds_pad(lo ? x : x + 1)]);
+        v[i][r] = cmul(cplx<C2>(ph[lo ? x + K - 1 : x - K]), buf[lds_pad(lo ? x : x + 1)]);
       }
     }
   }
@@ -65,25 +76,26 @@ __device__ __forceinline__ void dft4095_inv_first_from_fft(double2* buf, int lt,
   __syncthreads();
 }
 
-__device__ __forceinline__ void stage_tables(const K2048Args& A, double2* w6lo, double2* w6hi, double2* w5lo,
-                                             double2* w5hi) {
+template <typename C2>
+__device__ __forceinline__ void stage_tables(const K2048Args& A, C2* w6lo, C2* w6hi, C2* w5lo, C2* w5hi) {
   const int lt = threadIdx.x;
   if (lt < 64) {
-    w6lo[lt] = A.tw4096_lo[lt];
-    w6hi[lt] = A.tw4096_hi[lt];
-    w5lo[lt] = A.tw4095_lo[lt];
-    w5hi[lt] = A.tw4095_hi[lt];
+    w6lo[lt] = cplx<C2>(A.tw4096_lo[lt]);
+    w6hi[lt] = cplx<C2>(A.tw4096_hi[lt]);
+    w5lo[lt] = cplx<C2>(A.tw4095_lo[lt]);
+    w5hi[lt] = cplx<C2>(A.tw4095_hi[lt]);
   }
 }
 }  // namespace
 
 // phi stage, forward (see k_phi_forward): GT[(t*k + m)*C + c] for m < k.
-template <int REAL>
-__global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const double* __restrict__ f,
-                                                            long long map_stride, double* __restrict__ GT,
+template <int REAL, typename Rt>
+__global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_2048(K2048Args A, const double* __restrict__ f,
+                                                            long long map_stride, Rt* __restrict__ GT,
                                                             int C, int nb, int used, int nprob) {
-  __shared__ double2 buf[NBUF];
-  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  typedef Cx<Rt> C2;
+  __shared__ C2 buf[NBUF];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
@@ -98,27 +110,27 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const d
   __syncthreads();
   dft4095<false, TT>(buf, lt, w5lo, w5hi);
 
-  const double wphi = 2.0 * M_PI / (double)N;
+  const Rt wphi = (Rt)(2.0 * M_PI / (double)N), half = (Rt)0.5;
   if (valid) {
     for (int m = lt; m < K; m += TT) {
-      const double2 zp = buf[m];
-      const double2 zn = buf[m == 0 ? 0 : N - m];
-      double* row = GT + ((size_t)t * K + m) * C;
+      const C2 zp = buf[m];
+      const C2 zn = buf[m == 0 ? 0 : N - m];
+      Rt* row = GT + ((size_t)t * K + m) * C;
       if (REAL) {
-        row[2 * ma] = wphi * 0.5 * (zp.x + zn.x);
-        row[2 * ma + 1] = wphi * 0.5 * (zp.y - zn.y);
+        row[2 * ma] = wphi * half * (zp.x + zn.x);
+        row[2 * ma + 1] = wphi * half * (zp.y - zn.y);
         if (hasb) {
-          row[2 * ma + 2] = wphi * 0.5 * (zp.y + zn.y);
-          row[2 * ma + 3] = -wphi * 0.5 * (zp.x - zn.x);
+          row[2 * ma + 2] = wphi * half * (zp.y + zn.y);
+          row[2 * ma + 3] = -wphi * half * (zp.x - zn.x);
         }
       } else {
         row[4 * ma] = wphi * zp.x;
         row[4 * ma + 1] = wphi * zp.y;
-        row[4 * ma + 2] = (m == 0) ? 0.0 : wphi * zn.x;
-        row[4 * ma + 3] = (m == 0) ? 0.0 : wphi * zn.y;
+        row[4 * ma + 2] = (m == 0) ? Rt(0) : wphi * zn.x;
+        row[4 * ma + 3] = (m == 0) ? Rt(0) : wphi * zn.y;
       }
       if (u == 0)
-        for (int c = used; c < C; ++c) row[c] = 0.0;
+        for (int c = used; c < C; ++c) row[c] = Rt(0);
     }
   }
 }
@@ -130,11 +142,14 @@ __global__ __launch_bounds__(TT, 4) void k_phi_forward_2048(K2048Args A, const d
 // 2k-1-s, and writes the north/south sums and differences for the Legendre analysis on s < k/2,
 // column-pair major: row (m*(C/2) + cp)*k of double2, entry s = H(s) + H(k-1-s) and entry
 // k/2 + s = H(s) - H(k-1-s).
-template <bool SYM>
-__global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double* __restrict__ GT,
-                                                      double* __restrict__ HM, int C, int nprob) {
-  __shared__ double2 buf[NBUF];
-  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+// (FP32: 6 waves per SIMD, three problems per CU; at 8 the kernel spills and is slower)
+template <bool SYM, typename Rt>
+__global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K2048Args A, const Rt* __restrict__ GT,
+                                                      Rt* __restrict__ HM, int C, int nprob) {
+  typedef Cx<Rt> C2;
+  static_assert(SYM || sizeof(Rt) == 8, "the MW-node output is FP64 only");
+  __shared__ C2 buf[NBUF];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
   __shared__ double2 red_scratch[8];
   __shared__ double2 prow_s;   // pole row sum, kept in LDS through the transforms
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
@@ -149,18 +164,18 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
   // packed extension without the odd pole value (applied by the pole correction, see k_theta)
   double2 racc = make_double2(0.0, 0.0);
   {
-    RingGather<K, TT> x;
+    RingGather<K, TT, Rt> x;
     x.load(GT, C, mE, s, lt);
     // node r: even + odd order; node 2K-2-r (r < K-1): even - odd, the reflection's parity
 #pragma unroll
     for (int i = 0; i < x.PER; ++i) {
       const int r = lt + i * TT;
-      const double2 ge = valid ? x.ge[i] : make_double2(0.0, 0.0);
-      const double2 go = valid ? x.go[i] : make_double2(0.0, 0.0);
+      const C2 ge = valid ? x.ge[i] : czero<C2>();
+      const C2 go = valid ? x.go[i] : czero<C2>();
       if (r < K - 1) {
         buf[r] = cadd(ge, go);
         buf[N - 1 - r] = csub(ge, go);
-        if (!SYM) {
+        if constexpr (!SYM) {
           racc.x = fma(A.pole[r], go.x, racc.x);
           racc.y = fma(A.pole[r], go.y, racc.y);
         }
@@ -169,7 +184,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       }
     }
   }
-  if (!SYM) {
+  if constexpr (!SYM) {
     const double2 prow = problem_sum(racc, TT, red_scratch);
     if (lt == 0) prow_s = prow;
   }
@@ -178,13 +193,13 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
 
   constexpr int MAXV = NC / TT;   // 8 >= ceil((2K-1) / TT)
   constexpr int NJ = 2 * K - 1;
-  double2 keep[MAXV];
+  C2 keep[MAXV];
 #pragma unroll
   for (int i = 0; i < MAXV; ++i) {
     const int idx = lt + i * TT;
     if (idx < NJ) {
       const int j = idx - (K - 1);
-      keep[i] = cmul(A.hphase[idx], buf[j < 0 ? j + N : j]);
+      keep[i] = cmul(cplx<C2>(A.hphase[idx]), buf[j < 0 ? j + N : j]);
     }
   }
 #pragma unroll
@@ -192,7 +207,7 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
     __syncthreads();
     // the class fills slots [0, 1024) and [3072, 4096) except slot 3072 for P = 0; the middle half
     // is never read (the first FFT pass skips it), so only that slot needs a zero
-    if (P == 0 && lt == 0) buf[lds_pad(3 * K / 2)] = make_double2(0.0, 0.0);
+    if (P == 0 && lt == 0) buf[lds_pad(3 * K / 2)] = czero<C2>();
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
@@ -215,14 +230,14 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
       if (idx < NJ) {
         const int jp = idx - (K - 1);
         if (((jp - P) & 1) == 0)
-          keep[i] = cmul(SYM ? A.psph[idx] : A.hphase[idx], buf[lds_pad((-(jp - P) / 2 - P) & (NC - 1))]);
+          keep[i] = cmul(cplx<C2>(SYM ? A.psph[idx] : A.hphase[idx]), buf[lds_pad((-(jp - P) / 2 - P) & (NC - 1))]);
       }
     }
   }
   __syncthreads();
   if constexpr (SYM) {
     // I(j') at j' mod 4096 (slot 2048 stays empty), FFT onto the psi grid
-    if (lt == 0) buf[lds_pad(K)] = make_double2(0.0, 0.0);
+    if (lt == 0) buf[lds_pad(K)] = czero<C2>();
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       const int idx = lt + i * TT;
@@ -231,61 +246,62 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
     __syncthreads();
     fft4096_r8<false, TT>(buf, lt, w6lo, w6hi);
     if (valid) {
-      const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
-      const double2 pO = make_double2(rP[0], rP[1]);
+      const Rt* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
+      const C2 pO = CplxTraits<C2>::make(rP[0], rP[1]);
       for (int q = lt; q < K / 2; q += TT) {
         const int qs = K - 1 - q;   // the southern mirror of node q
-        const double2 a1 = buf[lds_pad(q)], a2 = buf[lds_pad(NC - 1 - q)];
-        const double2 b1 = buf[lds_pad(qs)], b2 = buf[lds_pad(NC - 1 - qs)];
-        const double2 hea = cadd(a1, a2), heb = cadd(b1, b2);
-        double2 hoa = csub(a1, a2), hob = csub(b1, b2);
-        hoa.x = fma(A.pole_s[q], pO.x, hoa.x);
-        hoa.y = fma(A.pole_s[q], pO.y, hoa.y);
-        hob.x = fma(A.pole_s[qs], pO.x, hob.x);
-        hob.y = fma(A.pole_s[qs], pO.y, hob.y);
-        double2* colE = reinterpret_cast<double2*>(HM) + ((size_t)mE * ns + s) * K;
-        double2* colO = reinterpret_cast<double2*>(HM) + ((size_t)mO * ns + s) * K;
+        const C2 a1 = buf[lds_pad(q)], a2 = buf[lds_pad(NC - 1 - q)];
+        const C2 b1 = buf[lds_pad(qs)], b2 = buf[lds_pad(NC - 1 - qs)];
+        const C2 hea = cadd(a1, a2), heb = cadd(b1, b2);
+        C2 hoa = csub(a1, a2), hob = csub(b1, b2);
+        const Rt ps = (Rt)A.pole_s[q], pss = (Rt)A.pole_s[qs];
+        hoa.x = fma(ps, pO.x, hoa.x);
+        hoa.y = fma(ps, pO.y, hoa.y);
+        hob.x = fma(pss, pO.x, hob.x);
+        hob.y = fma(pss, pO.y, hob.y);
+        C2* colE = reinterpret_cast<C2*>(HM) + ((size_t)mE * ns + s) * K;
+        C2* colO = reinterpret_cast<C2*>(HM) + ((size_t)mO * ns + s) * K;
         colE[q] = cadd(hea, heb);
         colE[K / 2 + q] = csub(hea, heb);
         colO[q] = cadd(hoa, hob);
         colO[K / 2 + q] = csub(hoa, hob);
       }
     }
-    return;
-  }
-  __syncthreads();
+  } else {
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    const int idx = lt + i * TT;
-    if (idx < NJ) {
-      const int jp = idx - (K - 1);
-      buf[jp < 0 ? jp + N : jp] = keep[i];
-    }
-  }
-  __syncthreads();
-  dft4095<false, TT>(buf, lt, w5lo, w5hi);
-
-  if (valid) {
-    const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
-    const double2 pO = make_double2(rP[0], rP[1]);
-    for (int t = lt; t < K; t += TT) {
-      const double2 h1 = buf[t];
-      double2 he = h1, ho;
-      if (t < K - 1) {
-        const double2 h2 = buf[N - 1 - t];
-        he = cadd(h1, h2);
-        ho = csub(h1, h2);
-        ho.x = fma(A.pole[t], pO.x, ho.x);
-        ho.y = fma(A.pole[t], pO.y, ho.y);
-      } else {
-        ho = make_double2(fma(A.pole[t], pO.x, prow_s.x), fma(A.pole[t], pO.y, prow_s.y));
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = lt + i * TT;
+      if (idx < NJ) {
+        const int jp = idx - (K - 1);
+        buf[jp < 0 ? jp + N : jp] = keep[i];
       }
-      double* wE = HM + ((size_t)mE * K + t) * C + 2 * s;
-      double* wO = HM + ((size_t)mO * K + t) * C + 2 * s;
-      wE[0] = he.x;
-      wE[1] = he.y;
-      wO[0] = ho.x;
-      wO[1] = ho.y;
+    }
+    __syncthreads();
+    dft4095<false, TT>(buf, lt, w5lo, w5hi);
+
+    if (valid) {
+      const double* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
+      const double2 pO = make_double2(rP[0], rP[1]);
+      for (int t = lt; t < K; t += TT) {
+        const double2 h1 = buf[t];
+        double2 he = h1, ho;
+        if (t < K - 1) {
+          const double2 h2 = buf[N - 1 - t];
+          he = cadd(h1, h2);
+          ho = csub(h1, h2);
+          ho.x = fma(A.pole[t], pO.x, ho.x);
+          ho.y = fma(A.pole[t], pO.y, ho.y);
+        } else {
+          ho = make_double2(fma(A.pole[t], pO.x, prow_s.x), fma(A.pole[t], pO.y, prow_s.y));
+        }
+        double* wE = HM + ((size_t)mE * K + t) * C + 2 * s;
+        double* wO = HM + ((size_t)mO * K + t) * C + 2 * s;
+        wE[0] = he.x;
+        wE[1] = he.y;
+        wO[0] = ho.x;
+        wO[1] = ho.y;
+      }
     }
   }
 }
@@ -300,12 +316,14 @@ __global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const double*
 // Output FT[(t*k + m)*C + c], t < k.  Two problems (adjacent column pairs) per 1024-thread
 // block, so that the output rows are written in 32-byte pieces by neighbouring lanes (16-byte
 // pieces from separate blocks reach HBM as partial writes, about 2.8 times the bytes).
-__global__ __launch_bounds__(2 * TT) void k_resample_2048(K2048Args A, const double* __restrict__ FS,
-                                                          double* __restrict__ FT, int C, int nprob) {
-  __shared__ double2 bufs[2][NBUF];
-  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+template <typename Rt>
+__global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_2048(K2048Args A, const Rt* __restrict__ FS,
+                                                          Rt* __restrict__ FT, int C, int nprob) {
+  typedef Cx<Rt> C2;
+  __shared__ C2 bufs[2][NBUF];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
-  double2* buf = bufs[threadIdx.x / TT];
+  C2* buf = bufs[threadIdx.x / TT];
   const int p2 = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x % TT;
   const int p = 2 * p2 + (int)(threadIdx.x / TT);
@@ -315,15 +333,15 @@ __global__ __launch_bounds__(2 * TT) void k_resample_2048(K2048Args A, const dou
   const int s = valid ? p % ns : 0;
   const int mE = 2 * mu, mO = 2 * mu + 1;
   constexpr int NL = K / TT;   // 4
-  double2 fe[NL], fo[NL];
+  C2 fe[NL], fo[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
     const int q = lt + i * TT;
-    fe[i] = make_double2(0.0, 0.0);
-    fo[i] = make_double2(0.0, 0.0);
+    fe[i] = czero<C2>();
+    fo[i] = czero<C2>();
     if (valid) {
-      fe[i] = reinterpret_cast<const double2*>(FS)[((size_t)mE * ns + s) * K + q];
-      fo[i] = reinterpret_cast<const double2*>(FS)[((size_t)mO * ns + s) * K + q];
+      fe[i] = reinterpret_cast<const C2*>(FS)[((size_t)mE * ns + s) * K + q];
+      fo[i] = reinterpret_cast<const C2*>(FS)[((size_t)mO * ns + s) * K + q];
     }
   }
 #pragma unroll
@@ -345,33 +363,34 @@ __global__ __launch_bounds__(2 * TT) void k_resample_2048(K2048Args A, const dou
   const int ph = 2 * p2 + h;
   if (ph < nprob) {
     const int muh = ph / ns, sh = ph % ns;
-    const double2* bh = bufs[h];
+    const C2* bh = bufs[h];
 #pragma unroll
     for (int i = 0; i < K / TT; ++i) {
       const int t = rr + i * TT;
-      const double2 h1 = bh[t];
-      double2 he, ho;
+      const C2 h1 = bh[t];
+      C2 he, ho;
       if (t < K - 1) {
-        const double2 h2 = bh[N - 1 - t];
+        const C2 h2 = bh[N - 1 - t];
         he = cadd(h1, h2);
         ho = csub(h1, h2);
       } else {
         he = cadd(h1, h1);
-        ho = make_double2(0.0, 0.0);
+        ho = czero<C2>();
       }
-      *reinterpret_cast<double2*>(FT + ((size_t)t * K + 2 * muh) * C + 2 * sh) = he;
-      *reinterpret_cast<double2*>(FT + ((size_t)t * K + 2 * muh + 1) * C + 2 * sh) = ho;
+      *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh) * C + 2 * sh) = he;
+      *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh + 1) * C + 2 * sh) = ho;
     }
   }
 }
 
 // phi stage, inverse (see k_phi_inverse): FT[(t*k + m)*C + c] -> maps.
-template <int REAL>
-__global__ __launch_bounds__(TT, 4) void k_phi_inverse_2048(K2048Args A, const double* __restrict__ FT,
+template <int REAL, typename Rt>
+__global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_inverse_2048(K2048Args A, const Rt* __restrict__ FT,
                                                             double* __restrict__ f, long long map_stride, int C,
                                                             int nb, int nprob) {
-  __shared__ double2 buf[NBUF];
-  __shared__ double2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  typedef Cx<Rt> C2;
+  __shared__ C2 buf[NBUF];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
@@ -388,12 +407,12 @@ __global__ __launch_bounds__(TT, 4) void k_phi_inverse_2048(K2048Args A, const d
 
   if (valid) {
     for (int q = lt; q < N; q += TT) {
-      const double2 v = buf[q];
+      const C2 v = buf[q];
       if (REAL) {
         f[(size_t)ma * map_stride + (size_t)t * N + q] = v.x;
         if (hasb) f[(size_t)(ma + 1) * map_stride + (size_t)t * N + q] = v.y;
       } else {
-        reinterpret_cast<double2*>(f)[(size_t)ma * map_stride + (size_t)t * N + q] = v;
+        reinterpret_cast<double2*>(f)[(size_t)ma * map_stride + (size_t)t * N + q] = make_double2(v.x, v.y);
       }
     }
   }
@@ -422,16 +441,27 @@ static K2048Args k2048_args(const ShtTables& T) {
 
 bool fft_k2048_applies(const ShtTables& T) { return k2048_ok(T); }
 
-hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
-                                   double* GT, hipStream_t s) {
+template <typename Rt>
+static hipError_t phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride, Rt* GT,
+                                   hipStream_t s) {
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = K * nunits;
   const K2048Args a = k2048_args(T);
   if (b.reality == S2LET_REAL)
-    k_phi_forward_2048<1><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<1, Rt><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
   else
-    k_phi_forward_2048<0><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<0, Rt><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
   return hipGetLastError();
+}
+
+hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                   double* GT, hipStream_t s) {
+  return phi_forward_2048(T, b, f, map_stride, GT, s);
+}
+
+hipError_t launch_phi_forward_2048_f32(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                       float* GT, hipStream_t s) {
+  return phi_forward_2048(T, b, f, map_stride, GT, s);
 }
 
 hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s,
@@ -439,30 +469,58 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
   const int nprob = (K / 2) * (b.C / 2);
   if (sym) {
     if (!T.sym) return hipErrorInvalidValue;
-    k_theta_2048<true><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
+    k_theta_2048<true, double><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
   } else {
-    k_theta_2048<false><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
+    k_theta_2048<false, double><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
+hipError_t launch_theta_2048_f32(const ShtTables& T, const Batch& b, const float* GT, float* HM, hipStream_t s) {
+  if (!T.sym) return hipErrorInvalidValue;
+  const int nprob = (K / 2) * (b.C / 2);
+  k_theta_2048<true, float><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
+  return hipGetLastError();
+}
+
+template <typename Rt>
+static hipError_t resample_2048(const ShtTables& T, const Batch& b, const Rt* FS, Rt* FT, hipStream_t s) {
   if (!T.sym || !k2048_ok(T)) return hipErrorInvalidValue;
   const int nprob = (K / 2) * (b.C / 2);   // even: K / 2 is
-  k_resample_2048<<<nprob / 2, 2 * TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
+  k_resample_2048<Rt><<<nprob / 2, 2 * TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
+  return resample_2048(T, b, FS, FT, s);
+}
+
+hipError_t launch_resample_2048_f32(const ShtTables& T, const Batch& b, const float* FS, float* FT,
+                                    hipStream_t s) {
+  return resample_2048(T, b, FS, FT, s);
+}
+
+template <typename Rt>
+static hipError_t phi_inverse_2048(const ShtTables& T, const Batch& b, const Rt* FT, void* f, int64_t map_stride,
+                                   hipStream_t s) {
+  const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
+  const int nprob = K * nunits;
+  const K2048Args a = k2048_args(T);
+  if (b.reality == S2LET_REAL)
+    k_phi_inverse_2048<1, Rt><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+  else
+    k_phi_inverse_2048<0, Rt><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
                                    int64_t map_stride, hipStream_t s) {
-  const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
-  const int nprob = K * nunits;
-  const K2048Args a = k2048_args(T);
-  if (b.reality == S2LET_REAL)
-    k_phi_inverse_2048<1><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
-  else
-    k_phi_inverse_2048<0><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
-  return hipGetLastError();
+  return phi_inverse_2048(T, b, FT, f, map_stride, s);
+}
+
+hipError_t launch_phi_inverse_2048_f32(const ShtTables& T, const Batch& b, const float* FT, void* f,
+                                       int64_t map_stride, hipStream_t s) {
+  return phi_inverse_2048(T, b, FT, f, map_stride, s);
 }
 
 }  // namespace s2let

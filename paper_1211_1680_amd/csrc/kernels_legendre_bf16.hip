@@ -343,8 +343,9 @@ __global__ __launch_bounds__(256) void k_legendre_inv_bf16(const double* __restr
 constexpr int FBS_ZR = 520;   // Z row (bf16): 512 nodes + 8; the 16 rows a quarter-wave reads sit
                               // 4 banks apart
 
-template <int C>
-__global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __restrict__ HM,
+// HT: the element type of HM (double, or float when the theta stage runs in FP32)
+template <int C, typename HT>
+__global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const HT* __restrict__ HM,
                                                                double* __restrict__ R, long long part_stride,
                                                                const double* __restrict__ alpha,
                                                                const double* __restrict__ beta,
@@ -405,14 +406,14 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
     const int m = im == 0 ? pair : k - 1 - pair;
     const double* __restrict__ am = alpha + tri_off(Lt, m);
     const double* __restrict__ bm = beta + tri_off(Lt, m);
-    const double* __restrict__ Hm = HM + (size_t)m * k * C;
+    const HT* __restrict__ Hm = HM + (size_t)m * k * C;
     // operands: element e of ah/al[kb] = node base + 32 kb + 8 lq + e, column ct*16 + li, the sums
     // (p = 0) or differences (p = 1) the theta stage stores at nodes [0, k/2) / [k/2, k)
     bf16x8 ah[NB], al[NB];
     {
       const int base = grp * TB + h * KS;
       const int c = ct * 16 + li;
-      const double* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1) + (p ? (size_t)kh * 2 : 0);
+      const HT* col = Hm + (size_t)(c >> 1) * k * 2 + (c & 1) + (p ? (size_t)kh * 2 : 0);
 #pragma unroll
       for (int kb = 0; kb < NB; ++kb) {
         // k/2 is a multiple of 32: a k-block is in range or not as a whole
@@ -420,8 +421,8 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
 #pragma unroll
         for (int e2 = 0; e2 < 8; e2 += 2) {
           const size_t tg = (size_t)(base + 32 * kb + 8 * lq + e2);
-          const float f0 = opaque_f32((float)(in ? col[tg * 2] : 0.0));
-          const float f1 = opaque_f32((float)(in ? col[(tg + 1) * 2] : 0.0));
+          const float f0 = opaque_f32((float)(in ? col[tg * 2] : HT(0)));
+          const float f1 = opaque_f32((float)(in ? col[(tg + 1) * 2] : HT(0)));
           bf16x2 hi, lo;
           split_bf16_pair(f0, f1, hi, lo);
           ah[kb][e2] = hi.x;
@@ -530,9 +531,10 @@ __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const double* __r
 constexpr int IBS_LC = 64;
 constexpr int IBS_ZR = 136;
 
-template <int C>
+// FT_: the element type of FS (double, or float when the resampling runs in FP32)
+template <int C, typename FT_>
 __global__ __launch_bounds__(256, 2) void k_legendre_inv_bf16_sym(const double* __restrict__ S,
-                                                                  double* __restrict__ FS,
+                                                                  FT_* __restrict__ FS,
                                                                   const double* __restrict__ alpha,
                                                                   const double* __restrict__ beta,
                                                                   const double* __restrict__ cm,
@@ -682,10 +684,10 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_bf16_sym(const double* 
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) {
             const int c = ct * 16 + li;
-            double* col = FS + ((size_t)m * C + (c & ~1)) * k + (c & 1);
+            FT_* col = FS + ((size_t)m * C + (c & ~1)) * k + (c & 1);
             const double E = (double)accE[g][ct][v], O = (double)accO[g][ct][v];
-            col[(size_t)tt * 2] = E + O;
-            col[(size_t)(k - 1 - tt) * 2] = E - O;
+            col[(size_t)tt * 2] = (FT_)(E + O);
+            col[(size_t)(k - 1 - tt) * 2] = (FT_)(E - O);
           }
         }
       }
@@ -696,19 +698,49 @@ __global__ __launch_bounds__(256, 2) void k_legendre_inv_bf16_sym(const double* 
   }
 }
 
-hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
-                                            const double* HM, double* R, long long part_stride, int lmin,
-                                            unsigned long long* counter, hipStream_t s) {
+template <typename HT>
+static hipError_t fwd_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b, const HT* HM, double* R,
+                               long long part_stride, int lmin, unsigned long long* counter, hipStream_t s) {
   const int k = T.k;
   if (!T.sym || (k & 1)) return hipErrorInvalidValue;
   const int ng = legendre_forward_groups_sym(k);
   const dim3 grid(((k + 1) / 2) * ng), block(FB_NW * 64);
   if (b.C == 32)
-    k_legendre_fwd_bf16_sym<32><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s,
-                                                       k, G.Lt, ng, lmin, counter);
+    k_legendre_fwd_bf16_sym<32, HT><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s,
+                                                           T.st_s, k, G.Lt, ng, lmin, counter);
   else if (b.C == 16)
-    k_legendre_fwd_bf16_sym<16><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s, T.st_s,
-                                                       k, G.Lt, ng, lmin, counter);
+    k_legendre_fwd_bf16_sym<16, HT><<<grid, block, 0, s>>>(HM, R, part_stride, G.alpha, G.beta, G.cm, T.ut_s,
+                                                           T.st_s, k, G.Lt, ng, lmin, counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
+                                            const double* HM, double* R, long long part_stride, int lmin,
+                                            unsigned long long* counter, hipStream_t s) {
+  return fwd_bf16_sym(T, G, b, HM, R, part_stride, lmin, counter, s);
+}
+
+hipError_t launch_legendre_forward_bf16_sym_f32(const ShtTables& T, const LegTables& G, const Batch& b,
+                                                const float* HM, double* R, long long part_stride, int lmin,
+                                                unsigned long long* counter, hipStream_t s) {
+  return fwd_bf16_sym(T, G, b, HM, R, part_stride, lmin, counter, s);
+}
+
+template <typename FT_>
+static hipError_t inv_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b, const double* S, FT_* FS,
+                               int lmin, unsigned long long* counter, hipStream_t s) {
+  const int k = T.k;
+  if (!T.sym || (k & 1)) return hipErrorInvalidValue;
+  const int ntb = (k / 2 + 255) / 256;
+  const dim3 grid(((k + 1) / 2) * ntb), block(256);
+  if (b.C == 32)
+    k_legendre_inv_bf16_sym<32, FT_><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt,
+                                                            ntb, lmin, counter);
+  else if (b.C == 16)
+    k_legendre_inv_bf16_sym<16, FT_><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt,
+                                                            ntb, lmin, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -717,19 +749,13 @@ hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables&
 hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
                                             const double* S, double* FS, int lmin, unsigned long long* counter,
                                             hipStream_t s) {
-  const int k = T.k;
-  if (!T.sym || (k & 1)) return hipErrorInvalidValue;
-  const int ntb = (k / 2 + 255) / 256;
-  const dim3 grid(((k + 1) / 2) * ntb), block(256);
-  if (b.C == 32)
-    k_legendre_inv_bf16_sym<32><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt, ntb,
-                                                       lmin, counter);
-  else if (b.C == 16)
-    k_legendre_inv_bf16_sym<16><<<grid, block, 0, s>>>(S, FS, G.alpha, G.beta, G.cm, T.ut_s, T.st_s, k, G.Lt, ntb,
-                                                       lmin, counter);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  return inv_bf16_sym(T, G, b, S, FS, lmin, counter, s);
+}
+
+hipError_t launch_legendre_inverse_bf16_sym_f32(const ShtTables& T, const LegTables& G, const Batch& b,
+                                                const double* S, float* FS, int lmin, unsigned long long* counter,
+                                                hipStream_t s) {
+  return inv_bf16_sym(T, G, b, S, FS, lmin, counter, s);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -107,6 +107,15 @@ struct RingGather {
   }
 };
 
+// Twiddle tables: W^p = lo[p mod 64] hi[p / 64].  The low table of a power-of-two transform
+// leaves one spare slot after every eight entries (twlo_at): in the passes whose twiddle index steps
+// by 8 (NS = 64 at 4096 points, and the passes of the shorter transforms that use those tables),
+// the eight lanes an LDS cycle serves read entries 0, 8, ..., 56, which the plain layout puts in
+// the same four banks.  The 4095-point tables keep the plain layout, which is better for their
+// index patterns.
+constexpr int TWLO_SLOTS = 72;
+__host__ __device__ constexpr int twlo_at(int i) { return i + (i >> 3); }
+
 template <int R, bool INV, typename C2>
 __device__ __forceinline__ void dft_small(C2* v) {
   if constexpr (R == 2 || R == 4 || R == 8 || R == 16)
@@ -128,7 +137,8 @@ __device__ __forceinline__ void ct_gather(const C2* buf, int j, C2* v, const C2*
   for (int r = 0; r < R; ++r) v[r] = ((LM >> r) & 1u) ? buf[lds_at<PAD>(j + r * NB)] : czero<C2>();
   if constexpr (NS > 1) {
     const int p = (j % NS) * STRIDE * TS;
-    C2 w1 = cmul(wlo[p & 63], whi[p >> 6]);
+    constexpr bool P2 = (N & (N - 1)) == 0;
+    C2 w1 = cmul(wlo[P2 ? twlo_at(p & 63) : (p & 63)], whi[p >> 6]);
     if (INV) w1 = conjd(w1);
     C2 w = w1;
 #pragma unroll

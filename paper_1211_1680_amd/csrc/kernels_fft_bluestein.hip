@@ -44,7 +44,7 @@ struct BsArgs {
 template <int NB>
 __device__ __forceinline__ void stage_tw(const BsArgs& A, double2* wlo, double2* whi) {
   for (int i = threadIdx.x; i < 64; i += blockDim.x) {
-    wlo[i] = A.tw_lo[i];
+    wlo[twlo_at(i)] = A.tw_lo[i];
     if (i < NB / 64) whi[i] = A.tw_hi[i];
   }
 }
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_phi_forward_bs(BsArgs A, co
                                                                     int C, int nb, int used, int nprob) {
   S2LET_BS_CONSTANTS
   __shared__ double2 buf[NBUF];
-  __shared__ double2 wlo[64], whi[64];
+  __shared__ double2 wlo[TWLO_SLOTS], whi[64];
   stage_tw<NB>(A, wlo, whi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_theta_sym_bs(BsArgs A, cons
                                                                   double* __restrict__ HM, int C, int nprob) {
   S2LET_BS_CONSTANTS
   __shared__ double2 buf[NBUF];
-  __shared__ double2 wlo[64], whi[64];
+  __shared__ double2 wlo[TWLO_SLOTS], whi[64];
   stage_tw<NB>(A, wlo, whi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(2 * BsCfg<K>::TT) void k_resample_bs(BsArgs A, cons
                                                                   double* __restrict__ FT, int C, int nprob) {
   S2LET_BS_CONSTANTS
   __shared__ double2 bufs[2][NBUF];
-  __shared__ double2 wlo[64], whi[64];
+  __shared__ double2 wlo[TWLO_SLOTS], whi[64];
   stage_tw<NB>(A, wlo, whi);
   double2* buf = bufs[threadIdx.x / TT];
   const int p2 = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(BsCfg<K>::TT, 4) void k_phi_inverse_bs(BsArgs A, co
                                                                     int C, int nb, int nprob) {
   S2LET_BS_CONSTANTS
   __shared__ double2 buf[NBUF];
-  __shared__ double2 wlo[64], whi[64];
+  __shared__ double2 wlo[TWLO_SLOTS], whi[64];
   stage_tw<NB>(A, wlo, whi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;

@@ -80,7 +80,7 @@ template <typename C2>
 __device__ __forceinline__ void stage_tables(const K2048Args& A, C2* w6lo, C2* w6hi, C2* w5lo, C2* w5hi) {
   const int lt = threadIdx.x;
   if (lt < 64) {
-    w6lo[lt] = cplx<C2>(A.tw4096_lo[lt]);
+    w6lo[twlo_at(lt)] = cplx<C2>(A.tw4096_lo[lt]);
     w6hi[lt] = cplx<C2>(A.tw4096_hi[lt]);
     w5lo[lt] = cplx<C2>(A.tw4095_lo[lt]);
     w5hi[lt] = cplx<C2>(A.tw4095_hi[lt]);
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_204
                                                             int C, int nb, int used, int nprob) {
   typedef Cx<Rt> C2;
   __shared__ C2 buf[NBUF];
-  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[TWLO_SLOTS], w6hi[64];
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K204
   typedef Cx<Rt> C2;
   static_assert(SYM || sizeof(Rt) == 8, "the MW-node output is FP64 only");
   __shared__ C2 buf[NBUF];
-  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[TWLO_SLOTS], w6hi[64];
   __shared__ double2 red_scratch[8];
   __shared__ double2 prow_s;   // pole row sum, kept in LDS through the transforms
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_20
                                                           Rt* __restrict__ FT, int C, int nprob) {
   typedef Cx<Rt> C2;
   __shared__ C2 bufs[2][NBUF];
-  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[TWLO_SLOTS], w6hi[64];
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
   C2* buf = bufs[threadIdx.x / TT];
   const int p2 = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_inverse_204
                                                             int nb, int nprob) {
   typedef Cx<Rt> C2;
   __shared__ C2 buf[NBUF];
-  __shared__ C2 w5lo[64], w5hi[64], w6lo[64], w6hi[64];
+  __shared__ C2 w5lo[64], w5hi[64], w6lo[TWLO_SLOTS], w6hi[64];
   stage_tables(A, w6lo, w6hi, w5lo, w5hi);
   const int p = xcd_swizzle(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;

@@ -374,7 +374,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     if (f32)
       e = launch_resample_2048_f32(T, b, (const float*)w.HM, (float*)w.GT, s);
     else
-      e = T.k == 2048 ? launch_resample_2048(T, b, w.HM, w.GT, s) : launch_resample_bs(T, b, w.HM, w.GT, s);
+      e = T.k == 2048 ? launch_resample_2048(T, b, w.HM, w.GT, s, !adjoint) : launch_resample_bs(T, b, w.HM, w.GT, s);
     if (e != hipSuccess) return to_status(e);
     prof_end(r, s);
   }
@@ -388,7 +388,7 @@ int inverse_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   r = prof_begin(ST_PHI_INV, s, T.k);
   if (r) r->bytes = mapb + colb;
   e = f32 ? launch_phi_inverse_2048_f32(T, b, (const float*)w.GT, f, map_stride, s)
-          : launch_phi_inverse(T, b, w.GT, f, map_stride, s);
+          : launch_phi_inverse(T, b, w.GT, f, map_stride, s, sym && !adjoint);
   if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
   return S2LET_OK;

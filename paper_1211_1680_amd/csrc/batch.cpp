@@ -413,10 +413,11 @@ hipError_t lv_fwd_pre(const Slot& X, const s2let::Batch& bt, const double* f, in
 hipError_t lv_inv_post(const Slot& X, const s2let::Batch& bt, double* f, int64_t stride, hipStream_t s) {
   using namespace s2let;
   if (X.sym) {
-    hipError_t e = X.k == 2048 ? launch_resample_2048(*X.T, bt, X.HM, X.GT, s) : launch_resample_bs(*X.T, bt, X.HM, X.GT, s);
+    hipError_t e = X.k == 2048 ? launch_resample_2048(*X.T, bt, X.HM, X.GT, s, true)
+                               : launch_resample_bs(*X.T, bt, X.HM, X.GT, s);
     if (e != hipSuccess) return e;
   }
-  return launch_phi_inverse(*X.T, bt, X.GT, f, stride, s);
+  return launch_phi_inverse(*X.T, bt, X.GT, f, stride, s, X.sym);
 }
 
 int lv_persistent_level(s2let_batch* b, int level, bool analysis, int& rr) {

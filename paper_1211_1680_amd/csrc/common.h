@@ -113,8 +113,9 @@ hipError_t launch_phi_forward(const ShtTables& T, const Batch& b, const void* f,
 // theta stage: GT[t][m][c] -> HM[m][t][c]  (the quadrature-weighted values H'_m(theta_t)).
 hipError_t launch_theta(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s);
 // phi stage, inverse: FT[t][m][c] -> maps (ring stride n, map stride map_stride samples).
+// quad: at band-limit 2048, FT in the column-quad layout (as launch_resample_2048 writes it).
 hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
-                              int64_t map_stride, hipStream_t s);
+                              int64_t map_stride, hipStream_t s, bool quad = false);
 // The same three stages compiled for band-limit 2048 (n = 4095); used when applicable.
 bool fft_k2048_applies(const ShtTables& T);
 hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
@@ -124,7 +125,13 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
 // Symmetric-grid variants (T.sym; FP64, C in {16, 32}): theta stage onto the psi grid (HM holds
 // the north/south sums in rows s < k/2 and differences in rows k/2 + s), the Legendre steps on
 // the northern nodes (the synthesis writes FS[m][s][c], s < k), and the resampling FS -> FT[t][m][c].
-hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s);
+// At band-limit 2048 the resampling with quad writes FT in the column-quad layout: element
+// (t, m, c) at ((t (C/4) + c/4) k + m) 4 + c mod 4, so that the inverse phi stage reads 64 KiB
+// contiguous per problem; without quad it writes the row layout, for the general theta stage of
+// the adjoint transform.  (FP64 GT keeps the row layout: there the theta stage's loss in the
+// column-quad layout outweighs the phi stage's gain.)
+hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s,
+                                bool quad);
 // The same stages compiled for band-limit 1024 (n = 2047 by Bluestein over 4096 points).
 // band-limits 512 and 1024 (kernels_fft_bluestein.hip): compiled phi, symmetric-grid theta and
 // resampling kernels; fft_bs_applies says whether T is one of them
@@ -152,10 +159,10 @@ hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables&
                                             const double* S, double* FS, int lmin, unsigned long long* counter,
                                             hipStream_t s);
 hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
-                                   int64_t map_stride, hipStream_t s);
+                                   int64_t map_stride, hipStream_t s, bool quad);
 // FP32 variants of the band-limit 2048 stages and of the BF16x3 symmetric-grid Legendre steps'
 // ends that meet them (the BF16x3 mode on the symmetric grid): GT, HM, FS and FT hold floats in
-// the same layouts; maps, R and S stay FP64.
+// the same layouts, except that GT and FT are column-quad; maps, R and S stay FP64.
 hipError_t launch_phi_forward_2048_f32(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
                                        float* GT, hipStream_t s);
 hipError_t launch_theta_2048_f32(const ShtTables& T, const Batch& b, const float* GT, float* HM, hipStream_t s);

@@ -56,7 +56,9 @@ __device__ __forceinline__ void load_ring(const double* __restrict__ f, long lon
 // negative orders their conjugates; otherwise columns 4 ma .. 4 ma + 3 hold orders +m and -m of
 // map ma.  Each row is read once for both slots, and every load is issued before the first store.
 // (TF: the element type of FT, double or float; C2: the complex type of the LDS buffer)
-template <int K, int T, int REAL, bool PAD = true, typename TF = double, typename C2 = double2>
+// QUAD: FT in the column-quad layout, element (t, m, c) at ((t (C/4) + c/4) K + m) 4 + c mod 4 (the
+// unit's four columns are one quad).
+template <int K, int T, int REAL, bool PAD = true, typename TF = double, typename C2 = double2, bool QUAD = false>
 __device__ __forceinline__ void load_orders(const TF* __restrict__ FT, int C, int ma, bool hasb, int t,
                                             bool valid, C2* buf, int lt) {
   typedef decltype(C2::x) S;
@@ -67,6 +69,12 @@ __device__ __forceinline__ void load_orders(const TF* __restrict__ FT, int C, in
   V2 ra[PER], rb[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
+    if constexpr (QUAD) {
+      const TF* q = FT + (((size_t)t * (C >> 2) + (REAL ? ma >> 1 : ma)) * K + lt + i * T) * 4;
+      ra[i] = *reinterpret_cast<const V2*>(q);
+      rb[i] = (!REAL || hasb) ? *reinterpret_cast<const V2*>(q + 2) : V2{};
+      continue;
+    }
     const TF* row = FT + ((size_t)t * K + lt + i * T) * C;
     if (REAL) {
       ra[i] = *reinterpret_cast<const V2*>(row + 2 * ma);
@@ -91,7 +99,8 @@ __device__ __forceinline__ void load_orders(const TF* __restrict__ FT, int C, in
   }
 }
 
-template <int K, int T, typename TG = double>
+// (QUAD: GT in the column-quad layout, see load_orders)
+template <int K, int T, typename TG = double, bool QUAD = false>
 struct RingGather {
   typedef typename std::conditional<sizeof(TG) == 8, double2, float2>::type V2;
   static constexpr int PER = K / T;
@@ -100,9 +109,11 @@ struct RingGather {
   __device__ __forceinline__ void load(const TG* __restrict__ GT, int C, int mE, int s, int lt) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const TG* row = GT + ((size_t)(lt + i * T) * K + mE) * C + 2 * s;
+      const int r = lt + i * T;
+      const TG* row = QUAD ? GT + (((size_t)r * (C >> 2) + (s >> 1)) * K + mE) * 4 + 2 * (s & 1)
+                           : GT + ((size_t)r * K + mE) * C + 2 * s;
       ge[i] = *reinterpret_cast<const V2*>(row);
-      go[i] = *reinterpret_cast<const V2*>(row + C);
+      go[i] = *reinterpret_cast<const V2*>(row + (QUAD ? 4 : C));
     }
   }
 };

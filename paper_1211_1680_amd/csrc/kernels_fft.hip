@@ -520,8 +520,8 @@ static hipError_t phi_inv_v(const FftArgs& A, const double* FT, void* f, int64_t
 }
 
 hipError_t launch_phi_inverse(const ShtTables& T, const Batch& b, const double* FT, void* f,
-                              int64_t map_stride, hipStream_t s) {
-  if (fft_k2048_applies(T)) return launch_phi_inverse_2048(T, b, FT, f, map_stride, s);
+                              int64_t map_stride, hipStream_t s, bool quad) {
+  if (fft_k2048_applies(T)) return launch_phi_inverse_2048(T, b, FT, f, map_stride, s, quad);
   if (fft_bs_applies(T)) return launch_phi_inverse_bs(T, b, FT, f, map_stride, s);
   const FftArgs A = fft_args(T, false);
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;

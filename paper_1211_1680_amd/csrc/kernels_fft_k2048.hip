@@ -28,6 +28,37 @@ constexpr int NBUF = lds_padded(NC);
 template <typename Rt>
 using Cx = typename std::conditional<sizeof(Rt) == 8, double2, float2>::type;
 
+// The column-quad layout of a stage buffer: element (t, m, c) at ((t (C/4) + c/4) K + m) 4 + c mod 4.
+// A phi problem (ring t and one unit: a map, or a pair of real maps) owns one column quad, so it
+// writes (reads) 32 contiguous bytes per order and 64 KiB in all; in the row layout ((t K + m) C + c)
+// the same bytes lie in 32-byte pieces 8 C bytes apart, one L2 request per 16-byte access, and those
+// requests, not HBM bandwidth, bound the phi stages (their time hardly changes without the DFT).
+// The theta and resampling problems (orders 2 mu and 2 mu + 1 of one column pair, every ring) pay
+// for it: in the column-quad layout the theta stage fetches about four times its bytes from HBM.
+// FT (resampling -> inverse phi) is column-quad on the symmetric path; GT (forward phi -> theta) only
+// in FP32, where the phi stage's gain is the larger (in FP64 the theta stage's loss is).
+__device__ __forceinline__ size_t quad_at(int t, int m, int c, int C) {
+  return (((size_t)t * (C >> 2) + (c >> 2)) * K + m) * 4 + (c & 3);
+}
+
+// Problem p of a theta / resampling launch (order pair mu, column pair s; ns = C/2 column pairs).
+// Row layout: p = mu ns + s, so the problems that share a GT / FT line (one order, eight column
+// pairs) are consecutive.  Column-quad layout: a line holds orders 4j .. 4j+3 of one quad, shared
+// by the problems (mu, s) with mu in {2j, 2j+1} and s in {2c, 2c+1}; those four are consecutive
+// (p = 4 (j ns/2 + c) + 2 (mu mod 2) + s mod 2), and a resampling block (two consecutive problems)
+// writes a whole quad of its two orders, 64 contiguous bytes per ring.
+template <bool QUAD>
+__device__ __forceinline__ void theta_problem(int p, int ns, int& mu, int& s) {
+  if (QUAD) {
+    const int q = p >> 2, r = p & 3, nc = ns >> 1;
+    mu = 2 * (q / nc) + (r >> 1);
+    s = 2 * (q % nc) + (r & 1);
+  } else {
+    mu = p / ns;
+    s = p % ns;
+  }
+}
+
 struct K2048Args {
   const double2* tw4096_lo;   // W_4096^p, p < 64
   const double2* tw4096_hi;   // W_4096^(64 q), q < 64
@@ -89,7 +120,9 @@ __device__ __forceinline__ void stage_tables(const K2048Args& A, C2* w6lo, C2* w
 }  // namespace
 
 // phi stage, forward (see k_phi_forward): GT[(t*k + m)*C + c] for m < k.
-template <int REAL, typename Rt>
+// QUAD: GT in the column-quad layout (unit u's columns are quad u; the unit-0 problems zero the
+// quads past the last unit, a unit without a second real map zeroes its upper half).
+template <int REAL, typename Rt, bool QUAD>
 __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_2048(K2048Args A, const double* __restrict__ f,
                                                             long long map_stride, Rt* __restrict__ GT,
                                                             int C, int nb, int used, int nprob) {
@@ -115,6 +148,26 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_204
     for (int m = lt; m < K; m += TT) {
       const C2 zp = buf[m];
       const C2 zn = buf[m == 0 ? 0 : N - m];
+      if constexpr (QUAD) {
+        Rt* q = GT + quad_at(t, m, 4 * u, C);
+        if (REAL) {
+          q[0] = wphi * half * (zp.x + zn.x);
+          q[1] = wphi * half * (zp.y - zn.y);
+          q[2] = hasb ? wphi * half * (zp.y + zn.y) : Rt(0);
+          q[3] = hasb ? -wphi * half * (zp.x - zn.x) : Rt(0);
+        } else {
+          q[0] = wphi * zp.x;
+          q[1] = wphi * zp.y;
+          q[2] = (m == 0) ? Rt(0) : wphi * zn.x;
+          q[3] = (m == 0) ? Rt(0) : wphi * zn.y;
+        }
+        if (u == 0)
+          for (int cq = nunits; cq < (C >> 2); ++cq) {
+            Rt* z = GT + quad_at(t, m, 4 * cq, C);
+            z[0] = z[1] = z[2] = z[3] = Rt(0);
+          }
+        continue;
+      }
       Rt* row = GT + ((size_t)t * K + m) * C;
       if (REAL) {
         row[2 * ma] = wphi * half * (zp.x + zn.x);
@@ -143,10 +196,13 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_204
 // column-pair major: row (m*(C/2) + cp)*k of double2, entry s = H(s) + H(k-1-s) and entry
 // k/2 + s = H(s) - H(k-1-s).
 // (FP32: 6 waves per SIMD, three problems per CU; at 8 the kernel spills and is slower)
+// GT: the row layout, except in FP32 (the BF16x3 mode's stages), whose GT is column-quad: there the
+// phi stage's gain outweighs the theta stage's loss, in FP64 it does not.
 template <bool SYM, typename Rt>
 __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K2048Args A, const Rt* __restrict__ GT,
                                                       Rt* __restrict__ HM, int C, int nprob) {
   typedef Cx<Rt> C2;
+  constexpr bool QUAD = SYM && sizeof(Rt) == 4;
   static_assert(SYM || sizeof(Rt) == 8, "the MW-node output is FP64 only");
   __shared__ C2 buf[NBUF];
   __shared__ C2 w5lo[64], w5hi[64], w6lo[TWLO_SLOTS], w6hi[64];
@@ -157,14 +213,14 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K204
   const int lt = threadIdx.x;
   const bool valid = p < nprob;
   const int ns = C / 2;
-  const int mu = valid ? p / ns : 0;
-  const int s = valid ? p % ns : 0;
+  int mu = 0, s = 0;
+  if (valid) theta_problem<QUAD>(p, ns, mu, s);
   const int mE = 2 * mu, mO = 2 * mu + 1;   // mO < K always (K even)
 
   // packed extension without the odd pole value (applied by the pole correction, see k_theta)
   double2 racc = make_double2(0.0, 0.0);
   {
-    RingGather<K, TT, Rt> x;
+    RingGather<K, TT, Rt, QUAD> x;
     x.load(GT, C, mE, s, lt);
     // node r: even + odd order; node 2K-2-r (r < K-1): even - odd, the reflection's parity
 #pragma unroll
@@ -246,7 +302,7 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K204
     __syncthreads();
     fft4096_r8<false, TT>(buf, lt, w6lo, w6hi);
     if (valid) {
-      const Rt* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
+      const Rt* rP = QUAD ? GT + quad_at(K - 1, mO, 2 * s, C) : GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
       const C2 pO = CplxTraits<C2>::make(rP[0], rP[1]);
       for (int q = lt; q < K / 2; q += TT) {
         const int qs = K - 1 - q;   // the southern mirror of node q
@@ -316,7 +372,8 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K204
 // Output FT[(t*k + m)*C + c], t < k.  Two problems (adjacent column pairs) per 1024-thread
 // block, so that the output rows are written in 32-byte pieces by neighbouring lanes (16-byte
 // pieces from separate blocks reach HBM as partial writes, about 2.8 times the bytes).
-template <typename Rt>
+// QUAD: FT in the column-quad layout (else the row layout, for the general theta stage of the adjoint)
+template <typename Rt, bool QUAD>
 __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_2048(K2048Args A, const Rt* __restrict__ FS,
                                                           Rt* __restrict__ FT, int C, int nprob) {
   typedef Cx<Rt> C2;
@@ -329,8 +386,8 @@ __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_20
   const int p = 2 * p2 + (int)(threadIdx.x / TT);
   const bool valid = p < nprob;
   const int ns = C / 2;
-  const int mu = valid ? p / ns : 0;
-  const int s = valid ? p % ns : 0;
+  int mu = 0, s = 0;
+  if (valid) theta_problem<QUAD>(p, ns, mu, s);
   const int mE = 2 * mu, mO = 2 * mu + 1;
   constexpr int NL = K / TT;   // 4
   C2 fe[NL], fo[NL];
@@ -362,7 +419,8 @@ __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_20
   const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
   const int ph = 2 * p2 + h;
   if (ph < nprob) {
-    const int muh = ph / ns, sh = ph % ns;
+    int muh, sh;
+    theta_problem<QUAD>(ph, ns, muh, sh);
     const C2* bh = bufs[h];
 #pragma unroll
     for (int i = 0; i < K / TT; ++i) {
@@ -377,14 +435,20 @@ __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_20
         he = cadd(h1, h1);
         ho = czero<C2>();
       }
-      *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh) * C + 2 * sh) = he;
-      *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh + 1) * C + 2 * sh) = ho;
+      if (QUAD) {
+        *reinterpret_cast<C2*>(FT + quad_at(t, 2 * muh, 2 * sh, C)) = he;
+        *reinterpret_cast<C2*>(FT + quad_at(t, 2 * muh + 1, 2 * sh, C)) = ho;
+      } else {
+        *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh) * C + 2 * sh) = he;
+        *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh + 1) * C + 2 * sh) = ho;
+      }
     }
   }
 }
 
 // phi stage, inverse (see k_phi_inverse): FT[(t*k + m)*C + c] -> maps.
-template <int REAL, typename Rt>
+// QUAD: FT in the column-quad layout
+template <int REAL, typename Rt, bool QUAD>
 __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_inverse_2048(K2048Args A, const Rt* __restrict__ FT,
                                                             double* __restrict__ f, long long map_stride, int C,
                                                             int nb, int nprob) {
@@ -401,7 +465,7 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_inverse_204
   const int ma = REAL ? 2 * u : u;
   const bool hasb = REAL && (ma + 1 < nb);
 
-  load_orders<K, TT, REAL, false>(FT, C, ma, hasb, t, valid, buf, lt);
+  load_orders<K, TT, REAL, false, Rt, C2, QUAD>(FT, C, ma, hasb, t, valid, buf, lt);
   __syncthreads();
   dft4095<true, TT>(buf, lt, w5lo, w5hi);
 
@@ -441,27 +505,29 @@ static K2048Args k2048_args(const ShtTables& T) {
 
 bool fft_k2048_applies(const ShtTables& T) { return k2048_ok(T); }
 
-template <typename Rt>
+template <typename Rt, bool QUAD>
 static hipError_t phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride, Rt* GT,
                                    hipStream_t s) {
+  if (QUAD && (b.C & 3)) return hipErrorInvalidValue;
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = K * nunits;
   const K2048Args a = k2048_args(T);
+  const double* fd = (const double*)f;
   if (b.reality == S2LET_REAL)
-    k_phi_forward_2048<1, Rt><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<1, Rt, QUAD><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
   else
-    k_phi_forward_2048<0, Rt><<<nprob, TT, 0, s>>>(a, (const double*)f, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<0, Rt, QUAD><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
                                    double* GT, hipStream_t s) {
-  return phi_forward_2048(T, b, f, map_stride, GT, s);
+  return phi_forward_2048<double, false>(T, b, f, map_stride, GT, s);
 }
 
 hipError_t launch_phi_forward_2048_f32(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
                                        float* GT, hipStream_t s) {
-  return phi_forward_2048(T, b, f, map_stride, GT, s);
+  return phi_forward_2048<float, true>(T, b, f, map_stride, GT, s);
 }
 
 hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s,
@@ -477,50 +543,63 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
 }
 
 hipError_t launch_theta_2048_f32(const ShtTables& T, const Batch& b, const float* GT, float* HM, hipStream_t s) {
-  if (!T.sym) return hipErrorInvalidValue;
+  if (!T.sym || (b.C & 3)) return hipErrorInvalidValue;
   const int nprob = (K / 2) * (b.C / 2);
   k_theta_2048<true, float><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
   return hipGetLastError();
 }
 
 template <typename Rt>
-static hipError_t resample_2048(const ShtTables& T, const Batch& b, const Rt* FS, Rt* FT, hipStream_t s) {
-  if (!T.sym || !k2048_ok(T)) return hipErrorInvalidValue;
+static hipError_t resample_2048(const ShtTables& T, const Batch& b, const Rt* FS, Rt* FT, hipStream_t s, bool quad) {
+  if (!T.sym || !k2048_ok(T) || (quad && (b.C & 3))) return hipErrorInvalidValue;
   const int nprob = (K / 2) * (b.C / 2);   // even: K / 2 is
-  k_resample_2048<Rt><<<nprob / 2, 2 * TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
+  if (quad)
+    k_resample_2048<Rt, true><<<nprob / 2, 2 * TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
+  else
+    k_resample_2048<Rt, false><<<nprob / 2, 2 * TT, 0, s>>>(k2048_args(T), FS, FT, b.C, nprob);
   return hipGetLastError();
 }
 
-hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s) {
-  return resample_2048(T, b, FS, FT, s);
+hipError_t launch_resample_2048(const ShtTables& T, const Batch& b, const double* FS, double* FT, hipStream_t s,
+                                bool quad) {
+  return resample_2048(T, b, FS, FT, s, quad);
 }
 
 hipError_t launch_resample_2048_f32(const ShtTables& T, const Batch& b, const float* FS, float* FT,
                                     hipStream_t s) {
-  return resample_2048(T, b, FS, FT, s);
+  return resample_2048(T, b, FS, FT, s, true);
 }
 
 template <typename Rt>
 static hipError_t phi_inverse_2048(const ShtTables& T, const Batch& b, const Rt* FT, void* f, int64_t map_stride,
-                                   hipStream_t s) {
+                                   hipStream_t s, bool quad) {
+  if (quad && (b.C & 3)) return hipErrorInvalidValue;
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = K * nunits;
   const K2048Args a = k2048_args(T);
-  if (b.reality == S2LET_REAL)
-    k_phi_inverse_2048<1, Rt><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
-  else
-    k_phi_inverse_2048<0, Rt><<<nprob, TT, 0, s>>>(a, FT, (double*)f, map_stride, b.C, b.nb, nprob);
+  double* fd = (double*)f;
+  if (b.reality == S2LET_REAL) {
+    if (quad)
+      k_phi_inverse_2048<1, Rt, true><<<nprob, TT, 0, s>>>(a, FT, fd, map_stride, b.C, b.nb, nprob);
+    else
+      k_phi_inverse_2048<1, Rt, false><<<nprob, TT, 0, s>>>(a, FT, fd, map_stride, b.C, b.nb, nprob);
+  } else {
+    if (quad)
+      k_phi_inverse_2048<0, Rt, true><<<nprob, TT, 0, s>>>(a, FT, fd, map_stride, b.C, b.nb, nprob);
+    else
+      k_phi_inverse_2048<0, Rt, false><<<nprob, TT, 0, s>>>(a, FT, fd, map_stride, b.C, b.nb, nprob);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
-                                   int64_t map_stride, hipStream_t s) {
-  return phi_inverse_2048(T, b, FT, f, map_stride, s);
+                                   int64_t map_stride, hipStream_t s, bool quad) {
+  return phi_inverse_2048(T, b, FT, f, map_stride, s, quad);
 }
 
 hipError_t launch_phi_inverse_2048_f32(const ShtTables& T, const Batch& b, const float* FT, void* f,
                                        int64_t map_stride, hipStream_t s) {
-  return phi_inverse_2048(T, b, FT, f, map_stride, s);
+  return phi_inverse_2048(T, b, FT, f, map_stride, s, true);
 }
 
 }  // namespace s2let

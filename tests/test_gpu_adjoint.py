@@ -104,8 +104,14 @@ def test_wavelet_adjoint_parity(dev, L, B, J_min, multires, reality):
 
 
 @pytest.mark.parametrize("reality", [s2.REAL, s2.COMPLEX])
-def test_dot_product_identities_L256(dev, reality):
-    L, nm = 256, 4
+@pytest.mark.parametrize("L", [256, 2048])
+def test_dot_product_identities(dev, reality, L):
+    """<A x, y> = <x, A^H y> for the forward and inverse transforms.  At L = 256 with 4 maps the
+    transforms run on the MW nodes; at L = 2048 with 8 real (4 complex) maps, 16 columns, the
+    forward and inverse transforms take the symmetric grid with the column-quad stage layout and
+    their adjoints the row layout, so each identity ties the two."""
+    nm = 4 if L == 256 or reality == s2.COMPLEX else 8
+    _log("  dot products L=%d nmaps=%d reality=%d" % (L, nm, reality))
     real = reality == s2.REAL
     n = 2 * L - 1
     g = torch.Generator(device="cpu").manual_seed(7)

@@ -80,6 +80,34 @@ def test_small_uneven_batch_matches_single_calls(dev):
     plan.close()
 
 
+def test_batch_with_band_limit_2048(dev):
+    """A batch holding an L = 2048 map (its top scales run the band-limit 2048 stages, in the
+    column-quad layout of the symmetric path) beside small ones: the L = 2048 map's outputs equal
+    the single-call transforms of a stack of eight copies of it (16 columns, the same path), and
+    every map is reconstructed."""
+    params = [(2048, 2, 2.0), (64, 3, 2.0), (512, 2, 1.5)]
+    J_min = 3
+    plan = s2.BatchPlan([p[0] for p in params], [p[1] for p in params], J_min)
+    f, _ = _maps(params, 120, False, dev)
+    f_wav, f_scal, rec = plan.run(f)
+    torch.cuda.synchronize()
+    L, B, _ = params[0]
+    f0 = plan.map_view(f, 0).unsqueeze(0).contiguous()
+    w8, s8 = s2.analysis(f0.expand(8, -1, -1).contiguous(), L, B, J_min, True, s2.REAL)
+    torch.cuda.synchronize()
+    got_w = torch.cat([w.reshape(-1) for w in plan.map_view(f_wav, 0, "wav")])
+    e_w = _rel(got_w.cpu().numpy(), w8[0].reshape(-1).cpu().numpy())
+    sc = plan.map_view(f_scal, 0, "scal")
+    e_s = _rel(sc.cpu().numpy(), s8[0].reshape(sc.shape).cpu().numpy(), 1e-6)
+    _log("  L=2048 map against eight-map single calls: wavelets %.2e, scaling %.2e" % (e_w, e_s))
+    assert e_w < 1e-12 and e_s < 1e-12
+    for i, (Li, Bi, _) in enumerate(params):
+        e = _rel(plan.map_view(rec, i).cpu().numpy(), plan.map_view(f, i).cpu().numpy())
+        _log("  map %d (L=%d): reconstruction %.2e" % (i, Li, e))
+        assert e < 1e-12
+    plan.close()
+
+
 def test_autotune_and_graph_replay(dev):
     rng = np.random.default_rng(6)
     params = [(int(rng.choice([16, 32, 64])), int(rng.choice([2, 3])), 1.5) for _ in range(20)]

@@ -30,9 +30,10 @@ using Cx = typename std::conditional<sizeof(Rt) == 8, double2, float2>::type;
 
 // The column-quad layout of a stage buffer: element (t, m, c) at ((t (C/4) + c/4) K + m) 4 + c mod 4.
 // A phi problem (ring t and one unit: a map, or a pair of real maps) owns one column quad, so it
-// writes (reads) 32 contiguous bytes per order and 64 KiB in all; in the row layout ((t K + m) C + c)
-// the same bytes lie in 32-byte pieces 8 C bytes apart, one L2 request per 16-byte access, and those
-// requests, not HBM bandwidth, bound the phi stages (their time hardly changes without the DFT).
+// writes (reads) whole lines, 64 KiB contiguous; in the row layout ((t K + m) C + c) the same bytes
+// lie in 32-byte pieces 8 C bytes apart, each line shared with the problems of three other units,
+// and that, not HBM bandwidth, bounds the phi stages (their time hardly changes without the DFT,
+// nor when lane pairs make each store cover 32 contiguous bytes per row).
 // The theta and resampling problems (orders 2 mu and 2 mu + 1 of one column pair, every ring) pay
 // for it: in the column-quad layout the theta stage fetches about four times its bytes from HBM.
 // FT (resampling -> inverse phi) is column-quad on the symmetric path; GT (forward phi -> theta) only

@@ -41,10 +41,10 @@ PEAK_HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {
     # the Legendre kernels' sources; the counters are reported only while these files are unchanged
     "sources": ["paper_1211_1680_amd/csrc/kernels_legendre.hip", "paper_1211_1680_amd/csrc/legendre_rec.h"],
-    "sha256": "0fbbadce0bfd450630a7de260d6d7c805626734ae1e91ff9ee51098c84655b28",
+    "sha256": "2b4072ca3e2e4605e28aa78c2d9178af921a247bb7b8fb715c5e7bf85185960f",
     # k = 2048 launches of k_legendre_fwd_sym<32, double> / k_legendre_inv_sym<32, double>:
     # FETCH_SIZE + WRITE_SIZE, copy-calibrated (profiles/wavelet_L2048_16maps_fp64_hbm_traffic.txt)
-    "bytes_per_launch": {"legendre_analysis": 2.1101e+09, "legendre_synthesis": 1.8008e+09},
+    "bytes_per_launch": {"legendre_analysis": 2.1102e+09, "legendre_synthesis": 1.8116e+09},
 }
 
 
@@ -55,13 +55,14 @@ MEASURED_TRAFFIC = {
 MEASURED_PIPES = {
     "sources": ["paper_1211_1680_amd/csrc/kernels_legendre.hip", "paper_1211_1680_amd/csrc/kernels_legendre_bf16.hip",
                 "paper_1211_1680_amd/csrc/legendre_rec.h"],
-    "sha256": "675be48c735ac956de84d0f27e6e0078a96666955e07c2bd1ee44456a4746ea0",
-    "fp64": {"legendre_analysis": {"mfma": 0.554, "valu": 0.168, "lds": 0.340},
-             "legendre_synthesis": {"mfma": 0.543, "valu": 0.304, "lds": 0.193}},
-    "fp32": {"legendre_analysis": {"mfma": 0.393, "valu": 0.286, "lds": 0.291},
-             "legendre_synthesis": {"mfma": 0.221, "valu": 0.337, "lds": 0.097}},
-    "bf16x3": {"legendre_analysis": {"mfma": 0.084, "valu": 0.360, "lds": 0.412},
-               "legendre_synthesis": {"mfma": 0.101, "valu": 0.636, "lds": 0.407}},
+    "sha256": "53633bec582fdaea9f82fcddae2071683748984fb443a6bdf45296da250bbb9a",
+    "fp64": {"legendre_analysis": {"mfma": 0.559, "valu": 0.165, "lds": 0.336},
+             "legendre_synthesis": {"mfma": 0.539, "valu": 0.301, "lds": 0.178}},
+    # FP32 mode: its synthesis at 32 columns is the FP64 kernel
+    "fp32": {"legendre_analysis": {"mfma": 0.393, "valu": 0.278, "lds": 0.280},
+             "legendre_synthesis": {"mfma": 0.539, "valu": 0.301, "lds": 0.178}},
+    "bf16x3": {"legendre_analysis": {"mfma": 0.082, "valu": 0.339, "lds": 0.394},
+               "legendre_synthesis": {"mfma": 0.102, "valu": 0.602, "lds": 0.381}},
 }
 
 

@@ -201,10 +201,12 @@ bool sym_path(int k, const Batch& b, int precision, bool adjoint) {
 // (synthesis, then the quadrature's transpose) both evaluate it on the symmetric grid and
 // resample it to the MW nodes.
 bool sym_inverse_path(int k, const Batch& b) { return sym_path(k, b, S2LET_FP64, false); }
-// In the BF16x3 mode at band-limit 2048 the phi, theta and resampling stages of the symmetric-grid
-// transforms run in FP32 with FP32 buffers between them: their rounding (about 1e-6 relative) is
-// far inside that mode's bound, and half the LDS per problem lets four problems share a CU.  The
-// adjoint transforms (whose theta stage is the general one) stay FP64.
+// In the BF16x3 mode at band-limit 2048 the inverse transform's resampling and inverse phi stages
+// run in FP32 with FP32 buffers between them and the synthesis: their rounding (about 1e-7 of the
+// output maps) is far inside that mode's bound, and half the LDS per problem lets four problems
+// share a CU.  The forward stages stay FP64: their rounding is relative to the whole input map,
+// which a steep spectrum carries to its high degrees amplified (1.5e-4 of the finest wavelet scale
+// in FP32).  The adjoint transforms (whose theta stage is the general one) stay FP64.
 bool f32_stages(const ShtTables& T, bool sym_not_adjoint, int precision) {
   return sym_not_adjoint && precision == S2LET_MIXED_BF16X3 && fft_k2048_applies(T);
 }
@@ -296,21 +298,16 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
   hipError_t e;
   const double k = T.k, n = T.n;
   const bool sym = sym_path(T.k, b, precision, adjoint);
-  const bool f32 = f32_stages(T, sym && !adjoint, precision);
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
-  const double colb = (f32 ? 4.0 : 8.0) * b.used * k * k;
+  const double colb = 8.0 * b.used * k * k;
   ProfRec* r = prof_begin(ST_PHI_FWD, s, T.k);
   if (r) r->bytes = mapb + colb;
-  e = f32 ? launch_phi_forward_2048_f32(T, b, f, map_stride, (float*)w.GT, s)
-          : launch_phi_forward(T, b, f, map_stride, w.GT, s);
-  if (e != hipSuccess) return to_status(e);
+  if ((e = launch_phi_forward(T, b, f, map_stride, w.GT, s)) != hipSuccess) return to_status(e);
   prof_end(r, s);
   r = prof_begin(ST_THETA, s, T.k);
   if (r) r->bytes = 2.0 * colb;
   if (adjoint)
     e = launch_transpose_rows(b, T.k, w.GT, w.HM, n / (2.0 * M_PI), s);
-  else if (f32)
-    e = launch_theta_2048_f32(T, b, (const float*)w.GT, (float*)w.HM, s);
   else if (sym)
     e = T.k == 2048 ? launch_theta_2048(T, b, w.GT, w.HM, s, true) : launch_theta_sym_bs(T, b, w.GT, w.HM, s);
   else
@@ -325,10 +322,7 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     r->flops_full = r->triples * (r->rec_flops + r->col_flops);
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
-  if (f32)
-    e = launch_legendre_forward_bf16_sym_f32(T, G, b, (const float*)w.HM, w.R, pstride_of(T.k, b), lmin,
-                                             prof_counter(r), s);
-  else if (sym)
+  if (sym)
     e = launch_legendre_forward_sym(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, lmin, prof_counter(r), s);
   else
     e = launch_legendre_forward(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r), s);

@@ -99,8 +99,7 @@ __device__ __forceinline__ void load_orders(const TF* __restrict__ FT, int C, in
   }
 }
 
-// (QUAD: GT in the column-quad layout, see load_orders)
-template <int K, int T, typename TG = double, bool QUAD = false>
+template <int K, int T, typename TG = double>
 struct RingGather {
   typedef typename std::conditional<sizeof(TG) == 8, double2, float2>::type V2;
   static constexpr int PER = K / T;
@@ -109,11 +108,9 @@ struct RingGather {
   __device__ __forceinline__ void load(const TG* __restrict__ GT, int C, int mE, int s, int lt) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int r = lt + i * T;
-      const TG* row = QUAD ? GT + (((size_t)r * (C >> 2) + (s >> 1)) * K + mE) * 4 + 2 * (s & 1)
-                           : GT + ((size_t)r * K + mE) * C + 2 * s;
+      const TG* row = GT + ((size_t)(lt + i * T) * K + mE) * C + 2 * s;
       ge[i] = *reinterpret_cast<const V2*>(row);
-      go[i] = *reinterpret_cast<const V2*>(row + (QUAD ? 4 : C));
+      go[i] = *reinterpret_cast<const V2*>(row + C);
     }
   }
 };

@@ -4,14 +4,13 @@
 // MW sampling), the theta stage (extension, DFT, parity-split correlation with the even part of
 // the sin(theta) weight, DFT back, fold), and the inverse phi DFT.  One problem per 512-thread
 // block; 74-76 KiB of LDS and at most 128 VGPRs (4 waves per SIMD), so two blocks share a CU.
-// Each kernel is a template over its working precision Rt: double, or float for the BF16x3
-// contraction mode (whose stated bound, 1e-4, leaves room for FP32 transforms, about 1e-6), in
-// which the stage buffers between these kernels and the Legendre steps hold floats too.  The FP32
-// instantiations take 37-39 KiB of LDS and at most 64 VGPRs (the theta stage 80), so four
-// problems (three for the theta stage) share a CU.  Non-packed FP32 arithmetic issues at the FP64
-// rate, so the gain is in LDS traffic and occupancy: the theta and resampling stages, heavy in
-// radix-8 passes, gain about a third; the phi stages, bound by the odd-radix 4095-point arithmetic,
-// little.
+// The kernels are templates over their working precision Rt.  The inverse-direction ones (the
+// resampling and the inverse phi DFT) also run in FP32 in the BF16x3 contraction mode, with FP32
+// buffers between them and the Legendre synthesis: their rounding is relative to the output maps,
+// far inside that mode's bound.  (The forward stages stay FP64 in every mode: their rounding is
+// relative to the whole input map, and a steep spectrum carries it to the high degrees amplified,
+// measured at 1.5e-4 of the finest wavelet scale in FP32.)  The FP32 instantiations take 38 KiB of
+// LDS (a resampling block 76 KiB) and at most 64 VGPRs, so four problems share a CU.
 #include "common.h"
 #include "fft_ct.h"
 #include "../../include/s2let_mi355x.h"
@@ -36,8 +35,8 @@ using Cx = typename std::conditional<sizeof(Rt) == 8, double2, float2>::type;
 // nor when lane pairs make each store cover 32 contiguous bytes per row).
 // The theta and resampling problems (orders 2 mu and 2 mu + 1 of one column pair, every ring) pay
 // for it: in the column-quad layout the theta stage fetches about four times its bytes from HBM.
-// FT (resampling -> inverse phi) is column-quad on the symmetric path; GT (forward phi -> theta) only
-// in FP32, where the phi stage's gain is the larger (in FP64 the theta stage's loss is).
+// FT (resampling -> inverse phi) is column-quad on the symmetric path, a net gain; GT (forward phi
+// -> theta) keeps the row layout, where the theta stage's loss would outweigh the phi stage's gain.
 __device__ __forceinline__ size_t quad_at(int t, int m, int c, int C) {
   return (((size_t)t * (C >> 2) + (c >> 2)) * K + m) * 4 + (c & 3);
 }
@@ -121,9 +120,7 @@ __device__ __forceinline__ void stage_tables(const K2048Args& A, C2* w6lo, C2* w
 }  // namespace
 
 // phi stage, forward (see k_phi_forward): GT[(t*k + m)*C + c] for m < k.
-// QUAD: GT in the column-quad layout (unit u's columns are quad u; the unit-0 problems zero the
-// quads past the last unit, a unit without a second real map zeroes its upper half).
-template <int REAL, typename Rt, bool QUAD>
+template <int REAL, typename Rt>
 __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_2048(K2048Args A, const double* __restrict__ f,
                                                             long long map_stride, Rt* __restrict__ GT,
                                                             int C, int nb, int used, int nprob) {
@@ -149,26 +146,6 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_204
     for (int m = lt; m < K; m += TT) {
       const C2 zp = buf[m];
       const C2 zn = buf[m == 0 ? 0 : N - m];
-      if constexpr (QUAD) {
-        Rt* q = GT + quad_at(t, m, 4 * u, C);
-        if (REAL) {
-          q[0] = wphi * half * (zp.x + zn.x);
-          q[1] = wphi * half * (zp.y - zn.y);
-          q[2] = hasb ? wphi * half * (zp.y + zn.y) : Rt(0);
-          q[3] = hasb ? -wphi * half * (zp.x - zn.x) : Rt(0);
-        } else {
-          q[0] = wphi * zp.x;
-          q[1] = wphi * zp.y;
-          q[2] = (m == 0) ? Rt(0) : wphi * zn.x;
-          q[3] = (m == 0) ? Rt(0) : wphi * zn.y;
-        }
-        if (u == 0)
-          for (int cq = nunits; cq < (C >> 2); ++cq) {
-            Rt* z = GT + quad_at(t, m, 4 * cq, C);
-            z[0] = z[1] = z[2] = z[3] = Rt(0);
-          }
-        continue;
-      }
       Rt* row = GT + ((size_t)t * K + m) * C;
       if (REAL) {
         row[2 * ma] = wphi * half * (zp.x + zn.x);
@@ -196,15 +173,10 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_204
 // 2k-1-s, and writes the north/south sums and differences for the Legendre analysis on s < k/2,
 // column-pair major: row (m*(C/2) + cp)*k of double2, entry s = H(s) + H(k-1-s) and entry
 // k/2 + s = H(s) - H(k-1-s).
-// (FP32: 6 waves per SIMD, three problems per CU; at 8 the kernel spills and is slower)
-// GT: the row layout, except in FP32 (the BF16x3 mode's stages), whose GT is column-quad: there the
-// phi stage's gain outweighs the theta stage's loss, in FP64 it does not.
 template <bool SYM, typename Rt>
-__global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K2048Args A, const Rt* __restrict__ GT,
+__global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const Rt* __restrict__ GT,
                                                       Rt* __restrict__ HM, int C, int nprob) {
   typedef Cx<Rt> C2;
-  constexpr bool QUAD = SYM && sizeof(Rt) == 4;
-  static_assert(SYM || sizeof(Rt) == 8, "the MW-node output is FP64 only");
   __shared__ C2 buf[NBUF];
   __shared__ C2 w5lo[64], w5hi[64], w6lo[TWLO_SLOTS], w6hi[64];
   __shared__ double2 red_scratch[8];
@@ -215,13 +187,13 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K204
   const bool valid = p < nprob;
   const int ns = C / 2;
   int mu = 0, s = 0;
-  if (valid) theta_problem<QUAD>(p, ns, mu, s);
+  if (valid) theta_problem<false>(p, ns, mu, s);
   const int mE = 2 * mu, mO = 2 * mu + 1;   // mO < K always (K even)
 
   // packed extension without the odd pole value (applied by the pole correction, see k_theta)
   double2 racc = make_double2(0.0, 0.0);
   {
-    RingGather<K, TT, Rt, QUAD> x;
+    RingGather<K, TT, Rt> x;
     x.load(GT, C, mE, s, lt);
     // node r: even + odd order; node 2K-2-r (r < K-1): even - odd, the reflection's parity
 #pragma unroll
@@ -303,7 +275,7 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K204
     __syncthreads();
     fft4096_r8<false, TT>(buf, lt, w6lo, w6hi);
     if (valid) {
-      const Rt* rP = QUAD ? GT + quad_at(K - 1, mO, 2 * s, C) : GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
+      const Rt* rP = GT + ((size_t)(K - 1) * K + mO) * C + 2 * s;
       const C2 pO = CplxTraits<C2>::make(rP[0], rP[1]);
       for (int q = lt; q < K / 2; q += TT) {
         const int qs = K - 1 - q;   // the southern mirror of node q
@@ -506,29 +478,17 @@ static K2048Args k2048_args(const ShtTables& T) {
 
 bool fft_k2048_applies(const ShtTables& T) { return k2048_ok(T); }
 
-template <typename Rt, bool QUAD>
-static hipError_t phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride, Rt* GT,
-                                   hipStream_t s) {
-  if (QUAD && (b.C & 3)) return hipErrorInvalidValue;
+hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                   double* GT, hipStream_t s) {
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = K * nunits;
   const K2048Args a = k2048_args(T);
   const double* fd = (const double*)f;
   if (b.reality == S2LET_REAL)
-    k_phi_forward_2048<1, Rt, QUAD><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<1, double><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
   else
-    k_phi_forward_2048<0, Rt, QUAD><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<0, double><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
   return hipGetLastError();
-}
-
-hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
-                                   double* GT, hipStream_t s) {
-  return phi_forward_2048<double, false>(T, b, f, map_stride, GT, s);
-}
-
-hipError_t launch_phi_forward_2048_f32(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
-                                       float* GT, hipStream_t s) {
-  return phi_forward_2048<float, true>(T, b, f, map_stride, GT, s);
 }
 
 hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s,
@@ -540,13 +500,6 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
   } else {
     k_theta_2048<false, double><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_theta_2048_f32(const ShtTables& T, const Batch& b, const float* GT, float* HM, hipStream_t s) {
-  if (!T.sym || (b.C & 3)) return hipErrorInvalidValue;
-  const int nprob = (K / 2) * (b.C / 2);
-  k_theta_2048<true, float><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
   return hipGetLastError();
 }
 

@@ -97,6 +97,37 @@ def test_mixed_wavelets_per_scale(dev, mode):
     assert _errs(rec.cpu().numpy()[:2], f2)[0] < TOL[mode]
 
 
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_mixed_wavelets_per_scale_L2048(dev, mode):
+    """The full-size workload (16 real maps, L = 2048, B = 2, J_min = 3, multiresolution, spectrum
+    C_l = 1/(l(l+1)), seed 3): every scale of the mixed analysis against the FP64 run (itself
+    checked against the oracle in test_gpu_fullsize.py), relative to that scale's own max |FP64|,
+    and the reconstruction.  The spectrum puts the finest scales near 1e-3 of the map, so rounding
+    relative to the whole map in a forward stage would show there amplified (it did, at 1.5e-4 of
+    the finest scale, with FP32 forward phi and theta stages)."""
+    L, B, J_min, nm = 2048, 2, 3, 16
+    f = s2.mw_inverse(torch.from_numpy(si.random_flm(L, nm, reality=True, seed=3)).to(dev), L, s2.REAL)
+    w64, s64 = s2.analysis(f, L, B, J_min, True, s2.REAL)
+    w, sc = s2.analysis(f, L, B, J_min, True, s2.REAL, precision=PREC[mode])
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return ((a - b).abs().max() / b.abs().max()).item()
+
+    e = rel(sc, s64)
+    _log("  %s scaling: %.2e" % (mode, e))
+    assert e < TOL[mode]
+    for j, (g, r) in enumerate(zip(s2.split_wav(w, L, B, J_min, True), s2.split_wav(w64, L, B, J_min, True))):
+        e = rel(g, r)
+        _log("  %s scale j=%d: %.2e" % (mode, J_min + j, e))
+        assert e < TOL[mode]
+    del w64, s64
+    rec = s2.synthesis(w, sc, L, B, J_min, True, s2.REAL, precision=PREC[mode])
+    e = rel(rec, f)
+    _log("  %s reconstruction: %.2e" % (mode, e))
+    assert e < TOL[mode]
+
+
 def test_config_512_complex_side_by_side(dev):
     """One complex map, L=512, B=2, J_min=2, multiresolution, FP64, FP32 and BF16x3 side by side."""
     L, B, J_min = 512, 2, 2

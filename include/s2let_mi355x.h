@@ -55,8 +55,9 @@ enum { S2LET_REAL = 0, S2LET_COMPLEX = 1 };                       /* reality */
  * FP64; where that is not faster than FP64 (the symmetric-grid synthesis of 32-column batches,
  * whose FP64 running sums leave it one wave per SIMD), the FP64 contraction runs instead.
  * S2LET_MIXED_BF16X3: both operands split into two bfloat16 parts, three products; at L = 2048
- * the inverse transform's resampling and inverse phi stages also run in FP32 (rounding near 1e-7
- * of the output maps).  The stated bounds (relative to the largest output) are 2e-6 and 1e-4. */
+ * the inverse transforms' resampling and inverse phi stages, and the phi and theta stages of the
+ * wavelet synthesis's per-scale forward transforms, also run in FP32 (rounding near 1e-7 of the
+ * maps they transform).  The stated bounds (relative to the largest output) are 2e-6 and 1e-4. */
 enum { S2LET_FP64 = 0, S2LET_MIXED_FP32 = 1, S2LET_MIXED_BF16X3 = 2 };
 #define S2LET_MAX_L 2048
 

@@ -201,12 +201,14 @@ bool sym_path(int k, const Batch& b, int precision, bool adjoint) {
 // (synthesis, then the quadrature's transpose) both evaluate it on the symmetric grid and
 // resample it to the MW nodes.
 bool sym_inverse_path(int k, const Batch& b) { return sym_path(k, b, S2LET_FP64, false); }
-// In the BF16x3 mode at band-limit 2048 the inverse transform's resampling and inverse phi stages
-// run in FP32 with FP32 buffers between them and the synthesis: their rounding (about 1e-7 of the
-// output maps) is far inside that mode's bound, and half the LDS per problem lets four problems
-// share a CU.  The forward stages stay FP64: their rounding is relative to the whole input map,
-// which a steep spectrum carries to its high degrees amplified (1.5e-4 of the finest wavelet scale
-// in FP32).  The adjoint transforms (whose theta stage is the general one) stay FP64.
+// In the BF16x3 mode at band-limit 2048 the phi, theta and resampling stages may run in FP32 with FP32
+// buffers between them and the Legendre kernels (rounding near 1e-7, and half the LDS per problem,
+// so that four problems share a CU) where that rounding is relative to what is judged: the inverse
+// stages (relative to the output maps) and the forward stages of the wavelet synthesis's per-scale
+// transforms (relative to each scale's map, whose sum is the output).  The forward transform of an
+// input map keeps FP64 stages: there the rounding is relative to the whole map, and a steep spectrum
+// carries it to the high degrees amplified (1.5e-4 of the finest wavelet scale, above the mode's
+// bound, measured).  The adjoint transforms (whose theta stage is the general one) stay FP64.
 bool f32_stages(const ShtTables& T, bool sym_not_adjoint, int precision) {
   return sym_not_adjoint && precision == S2LET_MIXED_BF16X3 && fft_k2048_applies(T);
 }
@@ -292,22 +294,29 @@ double triples_of(int k) { return (double)k * (double)k * (double)(k + 1) / 2.0;
 // weight, no theta quadrature, the same Legendre analysis.
 // lmin > 0: the caller needs no degree below lmin; whole chunks of rows below it stay unwritten (the
 // tiling does not read rows where its kernel vanishes).
+// scale_maps: the maps are the wavelet or scaling maps of a synthesis, so that the stages' rounding
+// is judged against each map (see f32_stages).
 int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const void* f,
                   int64_t map_stride, const Workspace& w, int precision, hipStream_t s, bool adjoint = false,
-                  int lmin = 0) {
+                  int lmin = 0, bool scale_maps = false) {
   hipError_t e;
   const double k = T.k, n = T.n;
   const bool sym = sym_path(T.k, b, precision, adjoint);
+  const bool f32 = scale_maps && f32_stages(T, sym && !adjoint, precision);
   const double mapb = (b.reality == S2LET_REAL ? 8.0 : 16.0) * b.nb * k * n;
-  const double colb = 8.0 * b.used * k * k;
+  const double colb = (f32 ? 4.0 : 8.0) * b.used * k * k;
   ProfRec* r = prof_begin(ST_PHI_FWD, s, T.k);
   if (r) r->bytes = mapb + colb;
-  if ((e = launch_phi_forward(T, b, f, map_stride, w.GT, s)) != hipSuccess) return to_status(e);
+  e = f32 ? launch_phi_forward_2048_f32(T, b, f, map_stride, (float*)w.GT, s)
+          : launch_phi_forward(T, b, f, map_stride, w.GT, s);
+  if (e != hipSuccess) return to_status(e);
   prof_end(r, s);
   r = prof_begin(ST_THETA, s, T.k);
   if (r) r->bytes = 2.0 * colb;
   if (adjoint)
     e = launch_transpose_rows(b, T.k, w.GT, w.HM, n / (2.0 * M_PI), s);
+  else if (f32)
+    e = launch_theta_2048_f32(T, b, (const float*)w.GT, (float*)w.HM, s);
   else if (sym)
     e = T.k == 2048 ? launch_theta_2048(T, b, w.GT, w.HM, s, true) : launch_theta_sym_bs(T, b, w.GT, w.HM, s);
   else
@@ -322,7 +331,10 @@ int forward_batch(const ShtTables& T, const LegTables& G, const Batch& b, const 
     r->flops_full = r->triples * (r->rec_flops + r->col_flops);
     r->bytes = colb + 8.0 * b.used * (double)tri_rows(T.k);
   }
-  if (sym)
+  if (f32)
+    e = launch_legendre_forward_bf16_sym_f32(T, G, b, (const float*)w.HM, w.R, pstride_of(T.k, b), lmin,
+                                             prof_counter(r), s);
+  else if (sym)
     e = launch_legendre_forward_sym(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, lmin, prof_counter(r), s);
   else
     e = launch_legendre_forward(T, G, b, w.HM, w.R, pstride_of(T.k, b), precision, prof_counter(r), s);
@@ -707,7 +719,7 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
     const Workspace w = carve(ws, L, b.C, true);
     // scaling part
     const double* pin = (const double*)f_scal + (size_t)start * psz * cmul;
-    if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s, adjoint)) != S2LET_OK) return st;
+    if ((st = forward_batch(*TP, dc.leg, b, pin, psz, w, precision, s, adjoint, 0, true)) != S2LET_OK) return st;
     // S is built over the degrees the contributions cover so far (kcov): each tiling accumulates
     // below kcov and writes the new rows above it, so no row is zero-filled first -- unless the scales
     // stop short of L, which the band-limits of Eqs. (4), (8) rule out
@@ -723,7 +735,7 @@ int s2let_wav_scales_to_map(void* f, const void* f_wav, const void* f_scal, int 
       const int kj = bl_wav(j, L, B, multires, kernel);
       const double* win = (const double*)f_wav + ((size_t)start * wsz + off) * cmul;
       if ((st = forward_batch(*TJ[j - J_min], dc.leg, b, win, wsz, w, precision, s, adjoint,
-                              W->lmin[j - J_min])) != S2LET_OK)
+                              W->lmin[j - J_min], true)) != S2LET_OK)
         return st;
       e = tile_prof(dc.leg, b, w.R, kj, nparts_of(kj, b, precision, adjoint), w.S, L,
                     W->kappa + (size_t)(j - J_min) * L, kcov, false, s);

@@ -160,9 +160,15 @@ hipError_t launch_legendre_inverse_bf16_sym(const ShtTables& T, const LegTables&
                                             hipStream_t s);
 hipError_t launch_phi_inverse_2048(const ShtTables& T, const Batch& b, const double* FT, void* f,
                                    int64_t map_stride, hipStream_t s, bool quad);
-// FP32 variants of the band-limit 2048 inverse-direction stages and of the BF16x3 symmetric-grid
-// synthesis that feeds them (the BF16x3 mode's inverse transform on the symmetric grid): FS and FT
-// hold floats in the same layouts (FT column-quad); S and the maps stay FP64.
+// FP32 variants of the band-limit 2048 stages and of the BF16x3 symmetric-grid Legendre kernels'
+// ends that meet them: GT, HM, FS and FT hold floats in the same layouts (FT column-quad); the
+// maps, R and S stay FP64.
+hipError_t launch_phi_forward_2048_f32(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                       float* GT, hipStream_t s);
+hipError_t launch_theta_2048_f32(const ShtTables& T, const Batch& b, const float* GT, float* HM, hipStream_t s);
+hipError_t launch_legendre_forward_bf16_sym_f32(const ShtTables& T, const LegTables& G, const Batch& b,
+                                                const float* HM, double* R, long long part_stride, int lmin,
+                                                unsigned long long* counter, hipStream_t s);
 hipError_t launch_resample_2048_f32(const ShtTables& T, const Batch& b, const float* FS, float* FT,
                                     hipStream_t s);
 hipError_t launch_phi_inverse_2048_f32(const ShtTables& T, const Batch& b, const float* FT, void* f,

@@ -4,13 +4,14 @@
 // MW sampling), the theta stage (extension, DFT, parity-split correlation with the even part of
 // the sin(theta) weight, DFT back, fold), and the inverse phi DFT.  One problem per 512-thread
 // block; 74-76 KiB of LDS and at most 128 VGPRs (4 waves per SIMD), so two blocks share a CU.
-// The kernels are templates over their working precision Rt.  The inverse-direction ones (the
-// resampling and the inverse phi DFT) also run in FP32 in the BF16x3 contraction mode, with FP32
-// buffers between them and the Legendre synthesis: their rounding is relative to the output maps,
-// far inside that mode's bound.  (The forward stages stay FP64 in every mode: their rounding is
-// relative to the whole input map, and a steep spectrum carries it to the high degrees amplified,
-// measured at 1.5e-4 of the finest wavelet scale in FP32.)  The FP32 instantiations take 38 KiB of
-// LDS (a resampling block 76 KiB) and at most 64 VGPRs, so four problems share a CU.
+// The kernels are templates over their working precision Rt; FP32 instantiations serve the BF16x3
+// contraction mode, with FP32 buffers between them and the Legendre kernels.  They take 38 KiB of
+// LDS (a resampling block 76 KiB) and at most 64 VGPRs (the theta stage 80), so four (three)
+// problems share a CU.  The driver uses them where the rounding is relative to what is judged: the
+// inverse stages (relative to the output maps), and the forward stages of the wavelet synthesis's
+// per-scale transforms (relative to each scale's map).  The forward transform of an input map keeps
+// FP64: there the rounding is relative to the whole map, and a steep spectrum carries it to the high
+// degrees amplified (1.5e-4 of the finest wavelet scale, measured).
 #include "common.h"
 #include "fft_ct.h"
 #include "../../include/s2let_mi355x.h"
@@ -173,10 +174,12 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 8) void k_phi_forward_204
 // 2k-1-s, and writes the north/south sums and differences for the Legendre analysis on s < k/2,
 // column-pair major: row (m*(C/2) + cp)*k of double2, entry s = H(s) + H(k-1-s) and entry
 // k/2 + s = H(s) - H(k-1-s).
+// (FP32: 6 waves per SIMD, three problems per CU; at 8 the kernel spills and is slower)
 template <bool SYM, typename Rt>
-__global__ __launch_bounds__(TT, 4) void k_theta_2048(K2048Args A, const Rt* __restrict__ GT,
+__global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K2048Args A, const Rt* __restrict__ GT,
                                                       Rt* __restrict__ HM, int C, int nprob) {
   typedef Cx<Rt> C2;
+  static_assert(SYM || sizeof(Rt) == 8, "the MW-node output is FP64 only");
   __shared__ C2 buf[NBUF];
   __shared__ C2 w5lo[64], w5hi[64], w6lo[TWLO_SLOTS], w6hi[64];
   __shared__ double2 red_scratch[8];
@@ -478,17 +481,28 @@ static K2048Args k2048_args(const ShtTables& T) {
 
 bool fft_k2048_applies(const ShtTables& T) { return k2048_ok(T); }
 
-hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
-                                   double* GT, hipStream_t s) {
+template <typename Rt>
+static hipError_t phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride, Rt* GT,
+                                   hipStream_t s) {
   const int nunits = b.reality == S2LET_REAL ? (b.nb + 1) / 2 : b.nb;
   const int nprob = K * nunits;
   const K2048Args a = k2048_args(T);
   const double* fd = (const double*)f;
   if (b.reality == S2LET_REAL)
-    k_phi_forward_2048<1, double><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<1, Rt><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
   else
-    k_phi_forward_2048<0, double><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
+    k_phi_forward_2048<0, Rt><<<nprob, TT, 0, s>>>(a, fd, map_stride, GT, b.C, b.nb, b.used, nprob);
   return hipGetLastError();
+}
+
+hipError_t launch_phi_forward_2048(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                   double* GT, hipStream_t s) {
+  return phi_forward_2048(T, b, f, map_stride, GT, s);
+}
+
+hipError_t launch_phi_forward_2048_f32(const ShtTables& T, const Batch& b, const void* f, int64_t map_stride,
+                                       float* GT, hipStream_t s) {
+  return phi_forward_2048(T, b, f, map_stride, GT, s);
 }
 
 hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* GT, double* HM, hipStream_t s,
@@ -500,6 +514,13 @@ hipError_t launch_theta_2048(const ShtTables& T, const Batch& b, const double* G
   } else {
     k_theta_2048<false, double><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_theta_2048_f32(const ShtTables& T, const Batch& b, const float* GT, float* HM, hipStream_t s) {
+  if (!T.sym) return hipErrorInvalidValue;
+  const int nprob = (K / 2) * (b.C / 2);
+  k_theta_2048<true, float><<<nprob, TT, 0, s>>>(k2048_args(T), GT, HM, b.C, nprob);
   return hipGetLastError();
 }
 

@@ -343,6 +343,7 @@ __global__ __launch_bounds__(256) void k_legendre_inv_bf16(const double* __restr
 constexpr int FBS_ZR = 520;   // Z row (bf16): 512 nodes + 8; the 16 rows a quarter-wave reads sit
                               // 4 banks apart
 
+// HT: the element type of HM (double, or float when the theta stage runs in FP32)
 template <int C, typename HT>
 __global__ __launch_bounds__(512) void k_legendre_fwd_bf16_sym(const HT* __restrict__ HM,
                                                                double* __restrict__ R, long long part_stride,
@@ -718,6 +719,12 @@ static hipError_t fwd_bf16_sym(const ShtTables& T, const LegTables& G, const Bat
 hipError_t launch_legendre_forward_bf16_sym(const ShtTables& T, const LegTables& G, const Batch& b,
                                             const double* HM, double* R, long long part_stride, int lmin,
                                             unsigned long long* counter, hipStream_t s) {
+  return fwd_bf16_sym(T, G, b, HM, R, part_stride, lmin, counter, s);
+}
+
+hipError_t launch_legendre_forward_bf16_sym_f32(const ShtTables& T, const LegTables& G, const Batch& b,
+                                                const float* HM, double* R, long long part_stride, int lmin,
+                                                unsigned long long* counter, hipStream_t s) {
   return fwd_bf16_sym(T, G, b, HM, R, part_stride, lmin, counter, s);
 }
 

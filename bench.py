@@ -61,7 +61,9 @@ MEASURED_PIPES = {
     # FP32 mode: its synthesis at 32 columns is the FP64 kernel
     "fp32": {"legendre_analysis": {"mfma": 0.393, "valu": 0.278, "lds": 0.280},
              "legendre_synthesis": {"mfma": 0.539, "valu": 0.301, "lds": 0.178}},
-    "bf16x3": {"legendre_analysis": {"mfma": 0.082, "valu": 0.339, "lds": 0.394},
+    # BF16x3 analysis: the dispatch-weighted mean of its FP64-HM (input map) and FP32-HM (the synthesis's
+    # per-scale transforms) instantiations
+    "bf16x3": {"legendre_analysis": {"mfma": 0.082, "valu": 0.343, "lds": 0.397},
                "legendre_synthesis": {"mfma": 0.102, "valu": 0.602, "lds": 0.381}},
 }
 

@@ -307,6 +307,84 @@ def paper_sweep(s2, torch, si, dev, reps=5):
             "rows": rows}
 
 
+def _median_ms(torch, fn, reps, warmup=2):
+    """Median over `reps` runs of fn's GPU time (CUDA events on the current stream)."""
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[reps // 2]
+
+
+def other_configs(s2, torch, si, dev, reps=10):
+    """The remaining workloads of the measurement plan, timed in full (inputs untimed, median of
+    `reps` runs): one real map at L = 64 (full resolution, B = 2, J_0 = 0); one complex map at L = 512
+    (B = 2, J_0 = 2, multiresolution), FP64 and FP32 side by side, the SHT pair alone and the wavelet
+    analysis + synthesis, with FP32's error per scale against FP64; and the differentiation workload
+    (8 real maps, L = 1024, B = 2, J_0 = 2, multiresolution), one loss-and-gradient evaluation."""
+    import numpy as np
+    from paper_1211_1680_amd import autograd as ad
+    out = {}
+    # one real map, L = 64, full resolution
+    L, B, J0 = 64, 2, 0
+    f = s2.mw_inverse(torch.from_numpy(si.random_flm(L, 1, reality=True, seed=0)).to(dev), L, s2.REAL)
+
+    def c1():
+        w, sc = s2.analysis(f, L, B, J0, False, s2.REAL)
+        s2.synthesis(w, sc, L, B, J0, False, s2.REAL)
+    ms = _median_ms(torch, c1, reps)
+    out["L64_real_fullres"] = {"ms_ana_syn": round(ms, 4), "maps_per_s": round(1e3 / ms, 1)}
+    # one complex map, L = 512, multiresolution, FP64 and FP32
+    L, B, J0 = 512, 2, 2
+    f = s2.mw_inverse(torch.from_numpy(si.random_flm(L, 1, reality=False, seed=1)).to(dev), L, s2.COMPLEX)
+    row = {}
+    res = {}
+    for name, prec in (("fp64", s2.FP64), ("fp32", s2.MIXED_FP32)):
+        def sht():
+            s2.mw_inverse(s2.mw_forward(f, L, s2.COMPLEX, prec), L, s2.COMPLEX, prec)
+
+        def wav():
+            w, sc = s2.analysis(f, L, B, J0, True, s2.COMPLEX, prec)
+            s2.synthesis(w, sc, L, B, J0, True, s2.COMPLEX, prec)
+        row[name] = {"ms_sht_pair": round(_median_ms(torch, sht, reps), 4),
+                     "ms_ana_syn": round(_median_ms(torch, wav, reps), 4)}
+        res[name] = s2.analysis(f, L, B, J0, True, s2.COMPLEX, prec)
+    errs = {}
+    for j, (g, r) in enumerate(zip(s2.split_wav(res["fp32"][0], L, B, J0, True),
+                                   s2.split_wav(res["fp64"][0], L, B, J0, True))):
+        errs["j=%d" % (J0 + j)] = float(((g - r).abs().max() / r.abs().max()).item())
+    errs["scal"] = float(((res["fp32"][1] - res["fp64"][1]).abs().max() / res["fp64"][1].abs().max()).item())
+    row["fp32_rel_err_vs_fp64_per_scale"] = errs
+    out["L512_complex_multires"] = row
+    del res, f
+    # the differentiation workload: 8 real maps, L = 1024; loss |b f_lm - d|^2 + lam sum (W^j f)^2
+    L, B, J0, nm, lam, sigma = 1024, 2, 2, 8, 0.1, 0.005
+    ell = torch.arange(L, dtype=torch.float64, device=dev)
+    bl = torch.repeat_interleave(torch.exp(-ell * (ell + 1) * sigma * sigma / 2.0), 2 * torch.arange(L, device=dev) + 1)
+    s_lm = torch.from_numpy(si.random_flm(L, nm, reality=True, seed=4)).to(dev)
+    n_lm = torch.from_numpy(si.random_flm(L, nm, reality=True, seed=104, cl=np.full(L, 1e-4))).to(dev)
+    d = bl[None, :] * s_lm + n_lm
+    f0 = s2.mw_inverse(torch.from_numpy(si.random_flm(L, nm, reality=True, seed=204)).to(dev), L, s2.REAL)
+    row = {}
+    for name, prec in (("fp64", s2.FP64), ("fp32", s2.MIXED_FP32)):
+        def grad():
+            x = f0.detach().clone().requires_grad_(True)
+            r = bl[None, :] * ad.mw_forward_ad(x, L, s2.REAL, prec) - d
+            w, _ = ad.analysis_ad(x, L, B, J0, True, s2.REAL, prec)
+            loss = torch.sum(torch.abs(r) ** 2) + lam * torch.sum(w * w)
+            loss.backward()
+        ms = _median_ms(torch, grad, reps)
+        row[name] = {"ms_loss_and_gradient": round(ms, 3), "maps_per_s": round(nm * 1e3 / ms, 1)}
+    out["L1024_gradient_8maps"] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +399,9 @@ def main():
                     help="skip the uneven-batching measurement (256 maps of L in {64..512})")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the paper's accuracy/timing sweep (L = 4 ... 2048, one complex map)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (L = 64; one complex map at L = 512 in FP64 and FP32; "
+                         "the L = 1024 loss gradient)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB (read "
                          "and written once) so that a hardware-counter run can calibrate its byte "
@@ -475,6 +556,9 @@ def main():
     if not args.no_sweep:
         out["paper_sweep"] = paper_sweep(s2, torch, si, dev)
         progress("paper sweep done")
+    if not args.no_configs:
+        out["other_configs"] = other_configs(s2, torch, si, dev)
+        progress("other workloads done")
     if not args.no_cpu_baseline:
         progress("CPU oracle: analysis + synthesis of one map at L=%d" % L)
         out["cpu_baseline"] = cpu_baseline(L, B, J_min, multires)

@@ -97,18 +97,24 @@ def test_mixed_wavelets_per_scale(dev, mode):
     assert _errs(rec.cpu().numpy()[:2], f2)[0] < TOL[mode]
 
 
-@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
-def test_mixed_wavelets_per_scale_L2048(dev, mode):
+@pytest.mark.parametrize("mode,nm,reality", [("fp32", 16, s2.REAL), ("bf16x3", 16, s2.REAL),
+                                             ("bf16x3", 8, s2.COMPLEX), ("bf16x3", 8, s2.REAL)])
+def test_mixed_wavelets_per_scale_L2048(dev, mode, nm, reality):
     """The full-size workload (16 real maps, L = 2048, B = 2, J_min = 3, multiresolution, spectrum
-    C_l = 1/(l(l+1)), seed 3): every scale of the mixed analysis against the FP64 run (itself
-    checked against the oracle in test_gpu_fullsize.py), relative to that scale's own max |FP64|,
-    and the reconstruction.  The spectrum puts the finest scales near 1e-3 of the map, so rounding
-    relative to the whole map in a forward stage would show there amplified (it did, at 1.5e-4 of
-    the finest scale, with FP32 forward phi and theta stages)."""
-    L, B, J_min, nm = 2048, 2, 3, 16
-    f = s2.mw_inverse(torch.from_numpy(si.random_flm(L, nm, reality=True, seed=3)).to(dev), L, s2.REAL)
-    w64, s64 = s2.analysis(f, L, B, J_min, True, s2.REAL)
-    w, sc = s2.analysis(f, L, B, J_min, True, s2.REAL, precision=PREC[mode])
+    C_l = 1/(l(l+1)), seed 3), and in BF16x3 also 8 complex maps (32 columns) and 8 real maps
+    (16 columns), which take the other instantiations of the FP32 stage kernels: every scale of the
+    mixed analysis against the FP64 run (itself checked against the oracle in
+    test_gpu_fullsize.py), relative to that scale's own max |FP64|, and the reconstruction.  The
+    spectrum puts the finest scales near 1e-3 of the map, so rounding relative to the whole map in a
+    forward stage would show there amplified (it did, at 1.5e-4 of the finest scale, with FP32
+    forward phi and theta stages in the analysis)."""
+    L, B, J_min = 2048, 2, 3
+    real = reality == s2.REAL
+    flm = torch.from_numpy(si.random_flm(L, nm, reality=real, seed=3)).to(dev)
+    f = s2.mw_inverse(flm, L, reality)
+    del flm
+    w64, s64 = s2.analysis(f, L, B, J_min, True, reality)
+    w, sc = s2.analysis(f, L, B, J_min, True, reality, precision=PREC[mode])
     torch.cuda.synchronize()
 
     def rel(a, b):
@@ -122,7 +128,7 @@ def test_mixed_wavelets_per_scale_L2048(dev, mode):
         _log("  %s scale j=%d: %.2e" % (mode, J_min + j, e))
         assert e < TOL[mode]
     del w64, s64
-    rec = s2.synthesis(w, sc, L, B, J_min, True, s2.REAL, precision=PREC[mode])
+    rec = s2.synthesis(w, sc, L, B, J_min, True, reality, precision=PREC[mode])
     e = rel(rec, f)
     _log("  %s reconstruction: %.2e" % (mode, e))
     assert e < TOL[mode]

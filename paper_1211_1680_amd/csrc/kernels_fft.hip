@@ -465,9 +465,22 @@ static hipError_t prep(K kernel, size_t lds) {
   return hipSuccess;
 }
 
+// Problems per block for a launch of nprob problems.  fft_args packs as many problems into a block
+// as its LDS and 512 threads allow, which at the small band-limits puts every problem of a launch
+// in one or two blocks (one compute unit busy, tens of microseconds for microseconds of work).
+// Spread them over up to 256 blocks instead, keeping at least one full wavefront per block.
+static FftArgs spread_problems(FftArgs A, int nprob) {
+  const int pmin = A.T >= 64 ? 1 : 64 / A.T;
+  const int pspread = (nprob + 255) / 256;
+  const int p = pspread > pmin ? pspread : pmin;
+  if (p < A.P) A.P = p;
+  return A;
+}
+
 template <int REAL, int VPT>
-static hipError_t phi_fwd_v(const FftArgs& A, const void* f, int64_t map_stride, double* GT, const Batch& b,
+static hipError_t phi_fwd_v(const FftArgs& Ain, const void* f, int64_t map_stride, double* GT, const Batch& b,
                             int nprob, hipStream_t s) {
+  const FftArgs A = spread_problems(Ain, nprob);
   const int nblk = (nprob + A.P - 1) / A.P;
   const size_t lds = (size_t)A.P * A.buf * sizeof(double2);
   hipError_t e;
@@ -491,8 +504,9 @@ hipError_t launch_phi_forward(const ShtTables& T, const Batch& b, const void* f,
 }
 
 template <int VPT>
-static hipError_t theta_v(const FftArgs& A, const double* GT, double* HM, const Batch& b, int nprob,
+static hipError_t theta_v(const FftArgs& Ain, const double* GT, double* HM, const Batch& b, int nprob,
                           hipStream_t s) {
+  const FftArgs A = spread_problems(Ain, nprob);
   const int nblk = (nprob + A.P - 1) / A.P;
   const size_t lds = (size_t)A.P * A.buf * sizeof(double2);
   hipError_t e;
@@ -509,8 +523,9 @@ hipError_t launch_theta(const ShtTables& T, const Batch& b, const double* GT, do
 }
 
 template <int REAL, int VPT>
-static hipError_t phi_inv_v(const FftArgs& A, const double* FT, void* f, int64_t map_stride, const Batch& b,
+static hipError_t phi_inv_v(const FftArgs& Ain, const double* FT, void* f, int64_t map_stride, const Batch& b,
                             int nprob, hipStream_t s) {
+  const FftArgs A = spread_problems(Ain, nprob);
   const int nblk = (nprob + A.P - 1) / A.P;
   const size_t lds = (size_t)A.P * A.buf * sizeof(double2);
   hipError_t e;

@@ -17,6 +17,7 @@
 // s2let_batch_autotune times the stream counts and batch widths, then the persistent mode with
 // its tile shapes (one bucket at a time), on the caller's buffers, and keeps the fastest.
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -48,11 +49,28 @@ struct Seg {
   long long src, dst, len;
 };
 
+// One segment per blockIdx.y.  Where source and destination are alike modulo 16 bytes, the body
+// moves 16-byte pairs (after a one-element head that aligns them); otherwise single elements.
 __global__ void k_seg_copy(const double* __restrict__ src, double* __restrict__ dst, const Seg* __restrict__ segs) {
   const Seg sg = segs[blockIdx.y];
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < sg.len;
-       i += (long long)gridDim.x * blockDim.x)
-    dst[sg.dst + i] = src[sg.src + i];
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const double* ps = src + sg.src;
+  double* pd = dst + sg.dst;
+  // (doubles are 8-byte aligned: an address is 16-byte aligned or 8 past it)
+  const uintptr_t as = reinterpret_cast<uintptr_t>(ps), ad = reinterpret_cast<uintptr_t>(pd);
+  if (((as ^ ad) & 15) == 0) {
+    const long long head = (ad & 15) ? 1 : 0;   // one element before both are 16-byte aligned
+    if (tid == 0 && head && sg.len > 0) pd[0] = ps[0];
+    const long long body = sg.len > head ? (sg.len - head) / 2 : 0;
+    const double2* s2 = reinterpret_cast<const double2*>(ps + head);
+    double2* d2 = reinterpret_cast<double2*>(pd + head);
+    for (long long i = tid; i < body; i += stride) d2[i] = s2[i];
+    const long long tail = head + 2 * body;   // one element left when len - head is odd
+    if (tid == 0 && tail < sg.len) pd[tail] = ps[tail];
+  } else {
+    for (long long i = tid; i < sg.len; i += stride) pd[i] = ps[i];
+  }
 }
 
 constexpr int kMaxStreams = 8;

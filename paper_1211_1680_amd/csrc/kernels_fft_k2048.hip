@@ -346,8 +346,9 @@ __global__ __launch_bounds__(TT, sizeof(Rt) == 8 ? 4 : 6) void k_theta_2048(K204
 // FFT gives the Fourier coefficients |j| <= k-1, and the 4095-point inverse DFT evaluates them at
 // theta_t = pi (2t+1) / n; the parities separate by the reflection t -> n-1-t.
 // Output FT[(t*k + m)*C + c], t < k.  Two problems (adjacent column pairs) per 1024-thread
-// block, so that the output rows are written in 32-byte pieces by neighbouring lanes (16-byte
-// pieces from separate blocks reach HBM as partial writes, about 2.8 times the bytes).
+// block, so that neighbouring lanes write whole pieces of the output rows: 16-byte pieces from
+// separate blocks reach HBM as partial writes (about 2.8 times the bytes in the row layout; 1.4
+// times with the column-quad layout's 32-byte pieces, 1.1 times with its 64-byte pieces).
 // QUAD: FT in the column-quad layout (else the row layout, for the general theta stage of the adjoint)
 template <typename Rt, bool QUAD>
 __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_2048(K2048Args A, const Rt* __restrict__ FS,
@@ -391,30 +392,53 @@ __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_20
   ct_pass<4095, 9, 13, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
   ct_pass<4095, 7, 117, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
   ct_pass<4095, 5, 819, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
-  // thread T writes problem 2 p2 + (T & 1) at rings T / 2 + 512 i
-  const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
-  const int ph = 2 * p2 + h;
-  if (ph < nprob) {
-    int muh, sh;
-    theta_problem<QUAD>(ph, ns, muh, sh);
-    const C2* bh = bufs[h];
+  if constexpr (QUAD) {
+    // thread T writes order 2 mu + ((T >> 1) & 1) of problem 2 p2 + (T & 1) at rings T / 4 + 256 i:
+    // the block's two problems are the two column pairs of one quad, so the four lanes of a ring
+    // write its two orders' 64 contiguous bytes (32 in FP32) in one store instruction
+    const int h = threadIdx.x & 1, od = (threadIdx.x >> 1) & 1, rq = threadIdx.x >> 2;
+    const int ph = 2 * p2 + h;
+    if (ph < nprob) {
+      int muh, sh;
+      theta_problem<QUAD>(ph, ns, muh, sh);
+      const C2* bh = bufs[h];
+      constexpr int RPI = 2 * TT / 4;   // rings per iteration
 #pragma unroll
-    for (int i = 0; i < K / TT; ++i) {
-      const int t = rr + i * TT;
-      const C2 h1 = bh[t];
-      C2 he, ho;
-      if (t < K - 1) {
-        const C2 h2 = bh[N - 1 - t];
-        he = cadd(h1, h2);
-        ho = csub(h1, h2);
-      } else {
-        he = cadd(h1, h1);
-        ho = czero<C2>();
+      for (int i = 0; i < K / RPI; ++i) {
+        const int t = rq + i * RPI;
+        const C2 h1 = bh[t];
+        C2 v;
+        if (t < K - 1) {
+          const C2 h2 = bh[N - 1 - t];
+          v = od ? csub(h1, h2) : cadd(h1, h2);
+        } else {
+          v = od ? czero<C2>() : cadd(h1, h1);
+        }
+        *reinterpret_cast<C2*>(FT + quad_at(t, 2 * muh + od, 2 * sh, C)) = v;
       }
-      if (QUAD) {
-        *reinterpret_cast<C2*>(FT + quad_at(t, 2 * muh, 2 * sh, C)) = he;
-        *reinterpret_cast<C2*>(FT + quad_at(t, 2 * muh + 1, 2 * sh, C)) = ho;
-      } else {
+    }
+  } else {
+    // row layout: thread T writes problem 2 p2 + (T & 1) at rings T / 2 + 512 i, the two problems'
+    // adjacent column pairs as 32-byte pieces
+    const int h = threadIdx.x & 1, rr = threadIdx.x >> 1;
+    const int ph = 2 * p2 + h;
+    if (ph < nprob) {
+      int muh, sh;
+      theta_problem<QUAD>(ph, ns, muh, sh);
+      const C2* bh = bufs[h];
+#pragma unroll
+      for (int i = 0; i < K / TT; ++i) {
+        const int t = rr + i * TT;
+        const C2 h1 = bh[t];
+        C2 he, ho;
+        if (t < K - 1) {
+          const C2 h2 = bh[N - 1 - t];
+          he = cadd(h1, h2);
+          ho = csub(h1, h2);
+        } else {
+          he = cadd(h1, h1);
+          ho = czero<C2>();
+        }
         *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh) * C + 2 * sh) = he;
         *reinterpret_cast<C2*>(FT + ((size_t)t * K + 2 * muh + 1) * C + 2 * sh) = ho;
       }

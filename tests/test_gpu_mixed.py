@@ -98,11 +98,13 @@ def test_mixed_wavelets_per_scale(dev, mode):
 
 
 @pytest.mark.parametrize("mode,nm,reality", [("fp32", 16, s2.REAL), ("bf16x3", 16, s2.REAL),
-                                             ("bf16x3", 8, s2.COMPLEX), ("bf16x3", 8, s2.REAL)])
+                                             ("bf16x3", 8, s2.COMPLEX), ("bf16x3", 8, s2.REAL),
+                                             ("bf16x3", 7, s2.REAL)])
 def test_mixed_wavelets_per_scale_L2048(dev, mode, nm, reality):
     """The full-size workload (16 real maps, L = 2048, B = 2, J_min = 3, multiresolution, spectrum
     C_l = 1/(l(l+1)), seed 3), and in BF16x3 also 8 complex maps (32 columns) and 8 real maps
-    (16 columns), which take the other instantiations of the FP32 stage kernels: every scale of the
+    (16 columns), which take the other instantiations of the FP32 stage kernels, and 7 real maps
+    (14 of 16 columns used: the last phi unit holds one map): every scale of the
     mixed analysis against the FP64 run (itself checked against the oracle in
     test_gpu_fullsize.py), relative to that scale's own max |FP64|, and the reconstruction.  The
     spectrum puts the finest scales near 1e-3 of the map, so rounding relative to the whole map in a

@@ -407,7 +407,36 @@ __global__ __launch_bounds__(2 * TT, sizeof(Rt) == 8 ? 4 : 8) void k_resample_20
   ct_pass<4095, 9, 13, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
   ct_pass<4095, 7, 117, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
   ct_pass<4095, 5, 819, true, TT, 1, A8, A8, false>(buf, lt, w5lo, w5hi);
-  if constexpr (QUAD) {
+  if constexpr (QUAD && sizeof(Rt) == 4) {
+    // FP32: thread T writes order 2 mu + (T & 1) of both problems at rings T / 2 + 512 i, the quad's
+    // four columns as one 16-byte store (problem 2 p2 takes the quad's first column pair)
+    const int od = threadIdx.x & 1, rr = threadIdx.x >> 1;
+    if (2 * p2 + 1 < nprob) {
+      int mu0, s0;
+      theta_problem<QUAD>(2 * p2, ns, mu0, s0);
+#pragma unroll
+      for (int i = 0; i < K / TT; ++i) {
+        const int t = rr + i * TT;
+        C2 v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const C2 h1 = bufs[h][t];
+          if (t < K - 1) {
+            const C2 h2 = bufs[h][N - 1 - t];
+            v[h] = od ? csub(h1, h2) : cadd(h1, h2);
+          } else {
+            v[h] = od ? czero<C2>() : cadd(h1, h1);
+          }
+        }
+        float4 q;
+        q.x = v[0].x;
+        q.y = v[0].y;
+        q.z = v[1].x;
+        q.w = v[1].y;
+        *reinterpret_cast<float4*>(FT + quad_at(t, 2 * mu0 + od, 2 * s0, C)) = q;
+      }
+    }
+  } else if constexpr (QUAD) {
     // thread T writes order 2 mu + ((T >> 1) & 1) of problem 2 p2 + (T & 1) at rings T / 4 + 256 i:
     // the block's two problems are the two column pairs of one quad, so the four lanes of a ring
     // write its two orders' 64 contiguous bytes (32 in FP32) in one store instruction
